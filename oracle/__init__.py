@@ -1,0 +1,31 @@
+"""FP64 CPU oracle for the space-time isogeometric Galerkin heat-equation solver.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library (``paper_1909_07309_amd``); the only module both sides import is
+``workloads`` (seeded random draws and sizes, none of the method's arithmetic).
+
+Everything here is plain numpy/scipy in float64, written from the paper
+(Loli, Montardini, Sangalli, Tani, "An efficient solver for space-time
+isogeometric Galerkin methods for parabolic problems", arXiv:1909.07309):
+
+* ``bsplines``  - knot vectors, Cox-de Boor recursion (Section 2.1), 1D
+                  Galerkin matrices W_t, M_t, K_l, M_l (eq. time_mat,
+                  space_univ_par_mat), Gauss-Legendre quadrature.
+* ``dense``     - dense Kronecker assembly of A and A-hat (eq. syst_mat,
+                  prec_definition), an independent brute-force space-time
+                  quadrature of the bilinear form (Section 3.1), direct solves.
+* ``fd``        - the fast-diagonalization apply of A-hat^{-1} with banded
+                  shifted time solves, and a Kronecker matvec (Section 4.4,
+                  Section 4.5), for full-size checks and the CPU baseline.
+* ``arrowhead`` - the paper's stable arrowhead factorization of the time
+                  pencil and Algorithm 1 with the block-LU middle solve
+                  (Sections 4.2-4.4), as an independent cross-check of ``fd``.
+* ``annulus``   - quarter-annulus geometry, variable separable coefficients,
+                  the geometry-aware preconditioner A-hat^G (Section 4.3).
+* ``adjoint``   - dense adjoint gradients of a quadratic loss.
+* ``problems``  - load vectors of the synthetic workloads.
+
+Functions without an independent pin say "parity unpinned" in their docstring.
+"""

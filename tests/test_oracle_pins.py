@@ -1,0 +1,260 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: numbers the
+paper prints (tests/golden/cond_numbers.json), closed forms, exact identities,
+a library routine (scipy's B-spline design matrix), an independent brute-force
+quadrature of the bilinear form, dense direct solves, and observed convergence
+rates of a manufactured solution.  The last tests plant plausible mistakes in
+the oracle and check that a pin catches each of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.interpolate as si
+import scipy.linalg as sla
+
+import workloads as wl
+from oracle import arrowhead as ah
+from oracle import bsplines as bs
+from oracle import dense
+from oracle import fd
+from oracle.convergence import manufactured_errors
+from oracle.problems import CubeProblem
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cond_numbers.json")))
+
+
+def round2(x):
+    """Round to two significant digits, as the paper's tables print."""
+    e = np.floor(np.log10(abs(x)))
+    return round(x / 10 ** e, 1) * 10 ** e
+
+
+# ------------------------------------------------------------- B-spline basis
+
+@pytest.mark.parametrize("p,n_el", [(1, 5), (2, 8), (3, 7), (4, 6)])
+def test_cox_de_boor_matches_scipy_design_matrix(p, n_el):
+    xi = bs.open_uniform_knots(n_el, p)
+    x = np.linspace(0.0, 1.0, 97)[:-1] + 0.003
+    ours = bs.basis(xi, p, x)
+    ref = si.BSpline.design_matrix(x, xi, p).toarray()
+    assert np.abs(ours - ref).max() < 1e-14
+    # derivative: scipy's BSpline with unit coefficient vectors
+    m = len(xi) - p - 1
+    dref = np.stack([si.BSpline(xi, np.eye(m)[i], p).derivative()(x) for i in range(m)], axis=1)
+    assert np.abs(bs.basis_derivative(xi, p, x) - dref).max() < 1e-12
+
+
+def test_partition_of_unity_and_open_ends():
+    xi = bs.open_uniform_knots(9, 3)
+    x = np.linspace(0, 1, 201)
+    B = bs.basis(xi, 3, x)
+    assert np.abs(B.sum(1) - 1).max() < 1e-14
+    # open knot vector: interpolatory at both ends
+    assert B[0, 0] == 1.0 and B[-1, -1] == 1.0
+
+
+def test_linear_splines_closed_forms():
+    """p = 1 (hat functions): M = h/6 tridiag(1, 4, 1), K = 1/h tridiag(-1, 2, -1) inside."""
+    n = 10
+    h = 1.0 / n
+    K, M = bs.space_matrices(n, 1)
+    Mref = h / 6 * (4 * np.eye(n - 1) + np.eye(n - 1, k=1) + np.eye(n - 1, k=-1))
+    Kref = 1 / h * (2 * np.eye(n - 1) - np.eye(n - 1, k=1) - np.eye(n - 1, k=-1))
+    assert np.abs(M - Mref).max() < 1e-15 and np.abs(K - Kref).max() < 1e-12
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_quadrature_is_exact(p):
+    """p+1 Gauss points per element integrate all 1D products exactly: more points change nothing."""
+    xi = bs.open_uniform_knots(7, p)
+    for f in (bs.mass, bs.stiffness, bs.advection):
+        assert np.abs(f(xi, p) - f(xi, p, nq=p + 6)).max() < 1e-13
+
+
+# ------------------------------------------------ printed condition numbers
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8])
+def test_table1_kappa_spatial_eigvecs(p):
+    t = GOLDEN["table1_space"]
+    want = t["value"][t["p"].index(p)]
+    for n_el in t["n_el"]:
+        K, M = bs.space_matrices(n_el, p)
+        lam, U = fd.space_eig(K, M)
+        assert round2(np.linalg.cond(U)) == pytest.approx(want)
+
+
+def test_table3_kappa_stable_time_factor():
+    for row in GOLDEN["table3_time_stable"]["rows"]:
+        for p, want in zip(row["p"], row["value"]):
+            if p > 5 and row["n_el"] > 64:
+                continue  # keeps the CPU suite short; same values as n_el = 64
+            Wt, Mt = bs.time_matrices(row["n_el"], p)
+            Ut = ah.time_arrowhead(Wt, Mt)[0]
+            assert round2(np.linalg.cond(Ut)) == pytest.approx(want), (row["n_el"], p)
+
+
+def test_table2_kappa_unstable_time_eig():
+    """kappa2 of the M_t-normalised eigenvectors of (W_t, M_t): pins W_t."""
+    for e in GOLDEN["table2_time_unstable"]["entries"]:
+        Wt, Mt = bs.time_matrices(e["n_el"], e["p"])
+        _, U = sla.eig(Wt, Mt)
+        U = U / np.sqrt(np.real(np.einsum("ij,ik,kj->j", U.conj(), Mt, U)))
+        assert round2(np.linalg.cond(U)) == pytest.approx(e["value"]), e
+
+
+# ---------------------------------------------------------- exact identities
+
+@pytest.mark.parametrize("p,n_el", [(2, 8), (3, 16), (4, 5)])
+def test_time_matrix_identities(p, n_el):
+    """eq. integral_W: W + W^T = b(T) b(T)^T = e_n e_n^T, so W-ring is skew and omega = 1/2."""
+    Wt, Mt = bs.time_matrices(n_el, p)
+    n = Wt.shape[0]
+    E = np.zeros((n, n))
+    E[-1, -1] = 1.0
+    assert np.abs(Wt + Wt.T - E).max() < 1e-14
+    assert Wt[-1, -1] == pytest.approx(0.5, abs=1e-14)
+    Wf, Mf = bs.time_matrices_full(n_el, p, T=2.5)
+    assert np.abs(Wf.sum(axis=1)).max() < 1e-14          # derivative of the constant 1
+    assert Mf.sum() == pytest.approx(2.5, rel=1e-14)      # int_0^T 1 dt
+    assert np.abs(bs.stiffness(bs.open_uniform_knots(n_el, p), p).sum(1)).max() < 1e-11
+    # M_t = T * M-hat, W_t independent of T (Section 4)
+    W2, M2 = bs.time_matrices(n_el, p, T=3.0)
+    assert np.abs(W2 - Wt).max() < 1e-13 and np.abs(M2 - 3.0 * Mt).max() < 1e-13
+
+
+def test_spatial_eigendecomposition_and_laplacian_limit():
+    K, M = bs.space_matrices(64, 3)
+    lam, U = fd.space_eig(K, M)
+    assert np.abs(U.T @ M @ U - np.eye(len(lam))).max() < 1e-13
+    assert np.abs(U.T @ K @ U - np.diag(lam)).max() < 1e-9 * lam.max()
+    # smallest Dirichlet-Laplacian eigenvalue on (0,1) is pi^2
+    assert lam[0] == pytest.approx(np.pi ** 2, rel=1e-10)
+    assert np.all(np.diff(lam) > 0)
+
+
+# ------------------------------------------------ Kronecker form of the system
+
+@pytest.mark.parametrize("d,n_el,p,T,gamma,nu", [(1, 5, 3, 2.0, 0.7, 1.3), (2, 3, 2, 1.0, 1.0, 1.0),
+                                                 (2, 3, 3, 0.5, 2.0, 0.3), (3, 2, 2, 1.0, 1.0, 1.0)])
+def test_kronecker_system_matches_brute_force_quadrature(d, n_el, p, T, gamma, nu):
+    A = dense.unit_cube_system(d, n_el, p, T, gamma, nu)
+    Ab = dense.brute_force_system(d, n_el, p, T, gamma, nu)
+    assert np.abs(A - Ab).max() < 1e-13 * max(1.0, np.abs(A).max())
+
+
+def test_kron_matvec_and_mass_apply_match_dense():
+    w = wl.scaled(wl.WORKLOADS["cube_p3_n64"], 3)
+    pr = CubeProblem(w)
+    A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d, 1.3, 0.6)
+    x = wl.random_tensor(w.shape, 5)
+    y = fd.kron_matvec(x, pr.Wt, pr.Mt, pr.K1d, pr.M1d, 1.3, 0.6)
+    assert np.abs(y.ravel() - A @ x.ravel()).max() < 1e-14 * np.abs(A).max() * 50
+    yt = fd.kron_matvec(x, pr.Wt, pr.Mt, pr.K1d, pr.M1d, 1.3, 0.6, transpose=True)
+    assert np.abs(yt.ravel() - A.T @ x.ravel()).max() < 1e-14 * np.abs(A).max() * 50
+    Ms = dense.kron_all([pr.Mt] + pr.M1d[::-1])
+    assert np.abs(fd.mass_apply(x, pr.Mt, pr.M1d).ravel() - Ms @ x.ravel()).max() < 1e-16 * 50
+
+
+# -------------------------------------------------- A-hat^{-1} by FD and arrowhead
+
+@pytest.mark.parametrize("name,n_el", [("square_p2_n8", 8), ("cube_p3_n64", 3), ("cube_p3_n64", 4)])
+def test_fd_apply_matches_dense_solve(name, n_el):
+    w = wl.scaled(wl.WORKLOADS[name], n_el)
+    pr = CubeProblem(w)
+    for gamma, nu in [(1.0, 1.0), (0.3, 2.5)]:
+        A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d, gamma, nu)
+        r = wl.random_tensor(w.shape, 11)
+        P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, gamma, nu)
+        s = P.apply(r)
+        ref = dense.solve(A, r.ravel())
+        assert np.abs(s.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+        st = P.apply(r, transpose=True)
+        reft = dense.solve(A.T, r.ravel())
+        assert np.abs(st.ravel() - reft).max() <= 1e-12 * np.abs(reft).max()
+
+
+def test_arrowhead_factorization_properties():
+    Wt, Mt = bs.time_matrices(16, 3)
+    U, Delta, lam_ring, g, sigma = ah.time_arrowhead(Wt, Mt)
+    n = Wt.shape[0]
+    assert np.abs(U.conj().T @ Mt @ U - np.eye(n)).max() < 1e-12        # eq. Mt-orthogonality
+    off = Delta.copy()
+    off[np.arange(n - 1), np.arange(n - 1)] = 0
+    off[-1, :] = 0
+    off[:, -1] = 0
+    assert np.abs(off).max() < 1e-12                                     # arrowhead
+    assert np.abs(np.diag(Delta)[:-1] - lam_ring).max() < 1e-11
+    assert np.abs(lam_ring.real).max() < 1e-12                            # purely imaginary
+    assert np.abs(Delta[:-1, -1] - g).max() < 1e-12                       # g of eq. time_eig_2
+    assert np.abs(Delta[-1, :-1] + g.conj()).max() < 1e-12                # lower arm is -g^*
+    rho = U[-1, -1].real
+    assert sigma == pytest.approx(rho ** 2 / 2, rel=1e-12)                # from eq. integral_W
+
+
+@pytest.mark.parametrize("name,n_el", [("square_p2_n8", 8), ("cube_p3_n64", 3)])
+def test_arrowhead_apply_matches_banded_fd_and_dense(name, n_el):
+    w = wl.scaled(wl.WORKLOADS[name], n_el)
+    pr = CubeProblem(w)
+    r = wl.random_tensor(w.shape, 3)
+    s_fd = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, 0.8, 1.7).apply(r)
+    s_ah = ah.ArrowheadPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, 0.8, 1.7).apply(r)
+    A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d, 0.8, 1.7)
+    ref = dense.solve(A, r.ravel())
+    assert np.abs(s_ah.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(s_fd - s_ah).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_banded_solve_rejects_zero_pivot():
+    Wt, Mt = bs.time_matrices(4, 2)
+    with pytest.raises(ZeroDivisionError):
+        fd.banded_shifted_solve(Wt, Mt, np.ones(3), np.ones((Wt.shape[0], 3)), 0.0, 0.0)
+
+
+# ------------------------------------------------------ discretisation error
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_manufactured_solution_rates(p):
+    """Section 5.1 and eq. a-riori-error-bound: L2 order p+1, X-type norm order p."""
+    e8 = manufactured_errors(2, 8, p)
+    e16 = manufactured_errors(2, 16, p)
+    r_l2 = np.log2(e8[0] / e16[0])
+    r_x = np.log2(e8[1] / e16[1])
+    assert abs(r_l2 - (p + 1)) < 0.15, r_l2
+    assert abs(r_x - p) < 0.15, r_x
+
+
+# ----------------------------------------------------------- planted mistakes
+
+def test_pins_catch_transposed_time_derivative(monkeypatch):
+    """If W were assembled with the derivative on the test index, the brute-force pin fails."""
+    orig = bs.advection
+    monkeypatch.setattr(bs, "advection", lambda xi, p, nq=None: orig(xi, p, nq).T)
+    A = dense.unit_cube_system(2, 3, 2)
+    monkeypatch.setattr(bs, "advection", orig)
+    Ab = dense.brute_force_system(2, 3, 2)
+    assert np.abs(A - Ab).max() > 1e-3
+
+
+def test_pins_catch_untransposed_forward_transform(monkeypatch):
+    """Step 2 with U_l instead of U_l^T breaks agreement with the dense solve."""
+    w = wl.scaled(wl.WORKLOADS["cube_p3_n64"], 3)
+    pr = CubeProblem(w)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt)
+    P.U = [U.T for U in P.U]       # apply() transposes them back the wrong way round
+    r = wl.random_tensor(w.shape, 1)
+    A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    ref = dense.solve(A, r.ravel())
+    assert np.abs(P.apply(r).ravel() - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_pins_catch_dropped_spatial_stiffness_term():
+    """Dropping one direction's stiffness term from K_s breaks the brute-force pin."""
+    K, M = bs.space_matrices(3, 2)
+    Wt, Mt = bs.time_matrices(3, 2)
+    Ms = np.kron(M, M)
+    Ks_wrong = np.kron(M, K)          # missing K (x) M
+    A_wrong = np.kron(Wt, Ms) + np.kron(Mt, Ks_wrong)
+    assert np.abs(A_wrong - dense.brute_force_system(2, 3, 2)).max() > 1e-3
