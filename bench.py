@@ -1,0 +1,177 @@
+"""Benchmark: fast-diagonalization preconditioner applies per second (in unknowns
+per second) and GMRES solve time to 1e-8, FP64 vs mixed precision, on the 3D
+unit-cube workload (p = 3, 64 elements per direction, 65^3 x 66 = 18,125,250
+unknowns), one GPU.
+
+A timed step is one application s = A-hat^{-1} r of the FP64 preconditioner to
+one resident FP64 tensor (forward spatial transforms, shifted time solves, back
+transforms).  The JSON line also reports the FP32 / BF16 applies, the GMRES /
+flexible GMRES solves with their iteration counts, true residuals and errors
+against the CPU oracle's solution, the event-timed roofline of the dominant
+kernel, and the CPU oracle's throughput on the host (baseline only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, f_host, target_s=12.0):
+    """The oracle's FD apply (numpy/scipy FP64) on the full tensor, repeated ~target_s."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import fd
+    from oracle.problems import CubeProblem
+    pr = CubeProblem(w)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, w.gamma, w.nu)
+    reps, t0 = 0, time.perf_counter()
+    u = None
+    while True:
+        u = P.apply(f_host)
+        reps += 1
+        if time.perf_counter() - t0 >= target_s or reps >= 8:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return u, {"value": w.N / dt, "unit": "DoF/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{reps} full FP64 applies of A-hat^-1 on the {w.N}-unknown tensor "
+                         f"(numpy/scipy, BLAS threads={threads}, nproc={os.cpu_count()})",
+               "s_per_apply": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import workloads as wl
+    from paper_1909_07309_amd.problem import CubeFactors, source
+
+    w = wl.WORKLOADS["cube_p3_n64"]
+    log(f"[bench] workload {w.name}: N = {w.N}")
+    fac = CubeFactors(w)
+    plan = fac.make_plan()
+    f = source(w, plan)
+    torch.cuda.synchronize()
+    s = torch.empty_like(f)
+
+    def timed_applies(prec, steps, warmup, profile=False):
+        for _ in range(warmup):
+            plan.apply_Pinv(f, s, prec=prec)
+        torch.cuda.synchronize()
+        if profile:
+            plan.profile_reset()
+            plan.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.apply_Pinv(f, s, prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = plan.profile()
+            plan.profile_enable(False)
+        return dt, prof
+
+    # ---- FP64 apply: the headline (event timing of each kernel over the same region)
+    dt, prof = timed_applies("fp64", args.steps, args.warmup, profile=True)
+    ms_per_step = dt / args.steps * 1e3
+    value = w.N * args.steps / dt
+    log(f"[bench] fp64 apply {ms_per_step:.3f} ms  {value:.3e} DoF/s")
+    kernels = {k: {"ms_per_launch": v[0] / v[2], "launches_per_step": v[2] / args.steps,
+                   "share": v[0] / sum(x[0] for x in prof.values()),
+                   "GBps": v[1] / (v[0] * 1e-3) / 1e9}
+               for k, v in prof.items() if v[2]}
+    dom = max(kernels, key=lambda k: kernels[k]["share"])
+    ms_l, by_l = prof[dom][0] / prof[dom][2], prof[dom][1] / prof[dom][2]
+    achieved = by_l / (ms_l * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": by_l, "ms_per_launch": ms_l}
+    # whole-apply view: FP64 flops 4*d*n_s per unknown for the transforms (+ time solves)
+    flops = (4 * w.d * w.n_s + 8 * w.p + 2) * w.N
+    apply_tflops = flops / (ms_per_step * 1e-3) / 1e12
+
+    # ---- mixed-precision applies
+    mixed = {}
+    for prec in ("fp32", "bf16"):
+        dtp, _ = timed_applies(prec, args.steps, args.warmup)
+        mixed[prec] = {"ms_per_apply": dtp / args.steps * 1e3, "DoF_per_s": w.N * args.steps / dtp}
+        log(f"[bench] {prec} apply {mixed[prec]['ms_per_apply']:.3f} ms")
+
+    # ---- CPU oracle baseline (also the reference solution: A-hat = A on the cube)
+    cpu = None
+    u_ref = None
+    if not args.no_cpu_baseline:
+        f_host = f.cpu().numpy()
+        u_ref, cpu = cpu_baseline(w, f_host)
+        log(f"[bench] cpu oracle {cpu['s_per_apply']:.2f} s/apply ({cpu['cores']} threads)")
+
+    # ---- solves to 1e-8
+    solves = {}
+    if not args.no_solve:
+        for prec in ("fp64", "fp32", "bf16"):
+            flexible = prec != "fp64"
+            u0 = torch.zeros_like(f)
+            plan.gmres_solve(f, u0, restart=w.restart, rtol=w.rtol, maxit=w.maxit,
+                             flexible=flexible, prec=prec)  # warm (allocations)
+            u = torch.zeros_like(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, info = plan.gmres_solve(f, u, restart=w.restart, rtol=w.rtol, maxit=w.maxit,
+                                       flexible=flexible, prec=prec)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3
+            rec = {"ms": t, "iters": info["iters"], "relres_true": info["relres_true"],
+                   "method": "FGMRES(30)" if flexible else "GMRES(30)"}
+            if u_ref is not None:
+                uh = u.cpu().numpy()
+                rec["rel_err_vs_oracle"] = float(np.linalg.norm(uh - u_ref) / np.linalg.norm(u_ref))
+            solves[prec] = rec
+            log(f"[bench] solve {prec}: {rec}")
+
+    line = {
+        "metric": "P^-1 applies/s (DoF/s) + solve time to 1e-8 resid, FP64 vs mixed",
+        "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "unit cube x [0,1], p=3, 64 elements/direction, "
+                               "65^3 x 66 = 18,125,250 unknowns, one FP64 A-hat^-1 apply per step",
+                   "N": w.N, "d": w.d, "p": w.p, "n_el": w.n_el, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "apply_fp64_tflops": apply_tflops,
+        "kernels_fp64_apply": kernels,
+        "mixed_apply": mixed,
+        "solve_to_1e-8": solves,
+        "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items()
+                                                  if k != "s_per_apply"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

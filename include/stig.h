@@ -1,0 +1,231 @@
+/*
+ * stig.h -- C ABI of libstig, an MI355X (gfx950) implementation of the hot path
+ * of the space-time isogeometric Galerkin heat-equation solver of Loli,
+ * Montardini, Sangalli and Tani (arXiv:1909.07309): applying the Kronecker-sum
+ * preconditioner A-hat = gamma W_t (x) M_s + nu M_t (x) K_s by fast
+ * diagonalization inside (flexible) GMRES.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Unknown tensors are contiguous FP64 arrays in device memory with layout
+ *    [rhs][t][x_d]...[x_1] (x_1 fastest): the colexicographic vec of Section 2.3.
+ *    One tensor has N = n_t * n_1 * ... * n_d entries; a batch holds nrhs of them.
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *    memory on the plan's device.  The caller owns every buffer it passes; the
+ *    library never frees caller memory.  The plan owns its own internal device
+ *    workspace (eigenvector matrices, band coefficients, intermediate tensors,
+ *    Krylov basis), allocated with hipMalloc by the calls that need it and freed
+ *    by stig_plan_destroy.
+ *  - Every device operation is ordered on the plan's stream.  stig_apply_Pinv,
+ *    stig_matvec_A and stig_apply_mass return as soon as their kernels are
+ *    queued; stig_gmres_solve synchronises the stream (the Givens rotations run
+ *    on the host) and returns when the solution is written.
+ *  - Errors are returned as codes, never thrown across the ABI; a description of
+ *    the last error on the calling thread is available from stig_last_error().
+ *    Negative codes mean nothing usable was written; positive codes are warnings
+ *    with a result written.
+ *  - A plan is not thread-safe: calls on one plan must not overlap.
+ */
+#ifndef STIG_H
+#define STIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stig_plan stig_plan;
+
+typedef enum {
+  STIG_OK = 0,
+  STIG_NOT_CONVERGED = 1,   /* gmres: maxit reached; best iterate written */
+  STIG_EINVAL = -1,         /* bad size, null pointer, out-of-band matrix entry */
+  STIG_ENOMEM = -2,         /* device allocation failed */
+  STIG_EHIP = -3,           /* a HIP runtime call failed */
+  STIG_EBREAKDOWN = -4,     /* non-positive pivot in a shifted time system, or
+                               non-positive-definite spatial mass matrix */
+  STIG_ENONFINITE = -5,     /* NaN/Inf met in a residual norm */
+  STIG_ESTATE = -6          /* call made before the setup it needs */
+} stig_status;
+
+/* Arithmetic of the fast-diagonalization apply (the mode-k GEMMs and the time
+ * solves).  Boundary I/O is FP64 in every case.
+ *   STIG_FP64: FP64 MFMA GEMMs, FP64 time solves, FP64 intermediates.
+ *   STIG_FP32: FP32 MFMA GEMMs (FP32 accumulation), FP32 time solves and
+ *              intermediates.
+ *   STIG_BF16: BF16 MFMA operands with FP32 accumulation, FP32 time solves,
+ *              BF16 intermediates. */
+typedef enum { STIG_FP64 = 0, STIG_FP32 = 1, STIG_BF16 = 2 } stig_prec;
+
+typedef struct {
+  int iters;            /* total inner (Arnoldi) iterations over all restarts */
+  int restarts;         /* number of restart cycles started after the first */
+  double relres_true;   /* ||f - A u||_2 / ||f||_2 recomputed in FP64 at exit */
+  double relres_est;    /* GMRES residual estimate at exit (relative) */
+  double t_solve_ms;    /* wall time of the call (host clock, stream synchronised) */
+} stig_info;
+
+/* ------------------------------------------------------------- plan lifetime */
+
+/* Create a plan for d spatial dimensions (1 <= d <= 3) with n_s[l] unknowns in
+ * direction l+1 (host array of d ints), n_t unknowns in time, spline degrees
+ * p_s (space) and p_t (time) that bound the bandwidths of the 1D factors
+ * (Section 4.5: bandwidth 2p+1), on HIP stream `stream` (hipStream_t; NULL is
+ * the null stream) of the current device.  No device memory is touched.
+ * Sizes: 1 <= n_s[l] <= 200, 2 <= n_t <= 1024, 1 <= p_s, p_t <= 5. */
+stig_status stig_plan_create(stig_plan **out, int d, const int *n_s, int n_t,
+                             int p_s, int p_t, void *stream);
+
+void stig_plan_destroy(stig_plan *plan);
+
+/* Change the stream later calls are ordered on. */
+stig_status stig_set_stream(stig_plan *plan, void *stream);
+
+/* ------------------------------------------------------------------ setup */
+
+/* Step 1 of Algorithm 1 (Section 4.4) for the banded-time form of A-hat^{-1}.
+ *   K1d[l], M1d[l] (host, l = 0..d-1): dense row-major n_s[l] x n_s[l] spatial
+ *       stiffness and mass factors of direction l+1 (eq. space_univ_par_mat, or the
+ *       geometry-weighted K-tilde_l, M-tilde_l of Section 4.3).  Symmetric, M SPD.
+ *   Wt, Mt (host): dense row-major n_t x n_t time factors (eq. time_mat).
+ *   gamma, nu: coefficients of eq. prec_definition.
+ * The library solves K_l U_l = M_l U_l Lambda_l with U_l^T M_l U_l = I
+ * (eq. space_eig) by Cholesky + cyclic Jacobi on the host, uploads U_l, U_l^T,
+ * Lambda_l (and FP32/BF16 copies), and the band coefficients of W_t, W_t^T, M_t.
+ * The same factors define the matrix-free matvec of stig_matvec_A unless
+ * stig_set_A_csr is called.  Entries outside the bandwidth p_s / p_t must be 0
+ * (else STIG_EINVAL).  May be called again to replace the factors. */
+stig_status stig_setup_1d_pencils(stig_plan *plan, const double *const *K1d,
+                                  const double *const *M1d, const double *Wt,
+                                  const double *Mt, double gamma, double nu);
+
+/* Optional: geometry-aware scaling of eq. prec_geo.  D (device, N doubles,
+ * layout [t][x_d]..[x_1]) holds D_ii = A_ii / A-tilde_ii > 0.  After this call,
+ * stig_apply_Pinv applies (D^{1/2} A-tilde D^{1/2})^{-1} = D^{-1/2} A-tilde^{-1} D^{-1/2},
+ * with the D^{-1/2} scalings fused into the first and last spatial passes.
+ * The library keeps its own copy of D^{-1/2}.  D = NULL removes the scaling. */
+stig_status stig_set_diag_scaling(stig_plan *plan, const double *D);
+
+/* Optional: use an explicit CSR matrix for stig_matvec_A instead of the
+ * matrix-free Kronecker form (the quarter-annulus workload of Section 4.3.1,
+ * whose spatial factors are not Kronecker products).  Device arrays, owned by
+ * the caller and kept alive while the plan uses them: rowptr (N+1 int64),
+ * col (nnz int32, sorted within a row), val (nnz FP64).  Pass rowptr = NULL to
+ * go back to the matrix-free form.  Transposed products are not supported on
+ * the CSR form (STIG_EINVAL). */
+stig_status stig_set_A_csr(stig_plan *plan, const int64_t *rowptr,
+                           const int32_t *col, const double *val, int64_t nnz);
+
+/* ---------------------------------------------------------------- hot path */
+
+/* s = A-hat^{-1} r (transpose = 0) or s = A-hat^{-T} r (transpose = 1) for nrhs
+ * right-hand sides: eq. prec_appl solved by Algorithm 1 with the time pencil
+ * kept banded: forward spatial transform with U_l^T (mode-l products,
+ * eq. kron_vec_multi), one shifted system (gamma W_t + nu lambda_k M_t) per
+ * spatial eigen-index k (transposed W_t for the adjoint), back transform with
+ * U_l.  r, s: device, nrhs * N doubles; r and s may not overlap.  prec selects
+ * the arithmetic (stig_prec). */
+stig_status stig_apply_Pinv(stig_plan *plan, const double *r, double *s,
+                            int nrhs, int transpose, stig_prec prec);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), FP64, eq. syst_mat:
+ * A = gamma W_t (x) M_s + nu M_t (x) K_s, computed matrix-free by banded mode
+ * products (Section 4.5), or with the CSR matrix of stig_set_A_csr.
+ * x, y: device, nrhs * N doubles, not overlapping. */
+stig_status stig_matvec_A(stig_plan *plan, const double *x, double *y, int nrhs,
+                          int transpose);
+
+/* y = (M_t (x) M_d (x) ... (x) M_1) z, FP64: the load vector of the spline
+ * function with coefficients z (used to build smooth synthetic sources).
+ * Uses the factors given to stig_setup_1d_pencils. */
+stig_status stig_apply_mass(stig_plan *plan, const double *z, double *y, int nrhs);
+
+/* Spatial part of the initial-datum lifting (Section 3.1, non-homogeneous
+ * initial condition): with a (host, n_t) = column of the unrestricted W for the
+ * removed first time function restricted to the kept rows, and b (host, n_t) the
+ * same column of the unrestricted M_t,
+ *     g = -( gamma M_s (sum_t a_t lam_t) + nu K_s (sum_t b_t lam_t) ),
+ * i.e. g = -A_{I,0}^T lam for lam (device, nrhs * N) and g (device, nrhs * N_s).
+ * It is the gradient of a loss with respect to the initial-datum coefficients
+ * when lam is the adjoint state. */
+stig_status stig_lift_adjoint(stig_plan *plan, const double *a_col,
+                              const double *b_col, const double *lam, double *g,
+                              int nrhs);
+
+/* Solve A u = f for nrhs right-hand sides by restarted GMRES(restart) with right
+ * preconditioning by A-hat^{-1} (or A-hat^{-T} with transpose = 1, which solves
+ * A^T u = f).  flexible = 1 selects flexible GMRES (stores the preconditioned
+ * vectors; required when prec != STIG_FP64 because the low-precision apply is not
+ * a fixed linear operator).  Arnoldi with classical Gram-Schmidt and one
+ * re-orthogonalisation, all in FP64 on the device; Givens rotations on the host.
+ * u: device, in = initial guess, out = solution.  Stops when the FP64 true
+ * relative residual ||f - A u|| / ||f|| <= rtol, or after maxit inner iterations
+ * per right-hand side (then STIG_NOT_CONVERGED).  Right-hand sides are solved one
+ * after another.  info (host, may be NULL) receives the worst case over the batch. */
+stig_status stig_gmres_solve(stig_plan *plan, const double *f, double *u, int nrhs,
+                             int restart, double rtol, int maxit, int flexible,
+                             int transpose, stig_prec prec, stig_info *info);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Kernel classes timed by the optional event profiler. */
+enum {
+  STIG_K_MODE_GEMM = 0,   /* mode-k MFMA products of the FD apply */
+  STIG_K_TIME_SOLVE = 1,  /* banded shifted time solves */
+  STIG_K_BAND_PASS = 2,   /* banded mode products of the matvec / mass apply */
+  STIG_K_KRYLOV = 3,      /* Arnoldi dot products and updates */
+  STIG_K_CSR = 4,         /* CSR matvec */
+  STIG_NUM_KERNEL_KINDS = 5
+};
+
+/* on != 0: every kernel launch of the plan is bracketed by two HIP events on
+ * the plan's stream; stig_profile_get synchronises the stream and returns, per
+ * kernel class, the summed event time (ms), the summed algorithmic bytes of
+ * those launches (compulsory reads + writes of each launch's inputs and outputs,
+ * e.g. 16 bytes per unknown for an FP64 mode product) and the launch count.
+ * Host pointers may be NULL.  Events cost a few microseconds per launch. */
+stig_status stig_profile_enable(stig_plan *plan, int on);
+stig_status stig_profile_reset(stig_plan *plan);
+stig_status stig_profile_get(stig_plan *plan, int kind, double *total_ms, double *bytes,
+                             long long *launches);
+
+/* Device bytes the plan currently holds (for reporting). */
+size_t stig_plan_device_bytes(const stig_plan *plan);
+
+/* ------------------------------------------------------- 1D spline assembly */
+
+/* Gauss-Legendre points and weights on [0, length] split into n_el equal
+ * elements, nq points per element (host arrays of n_el * nq). */
+stig_status stig_quadrature(int n_el, int nq, double length, double *x, double *w);
+
+/* Dense row-major m x m matrix (m = n_el + p) of the open uniform
+ * maximal-continuity B-spline basis of degree p on [0, length] (Section 2.1):
+ *   kind 0: mass       [M]_ij = int c b_i b_j
+ *   kind 1: stiffness  [K]_ij = int c b_i' b_j'
+ *   kind 2: advection  [W]_ij = int c b_j' b_i      (eq. time_mat)
+ * c = 1 if weight is NULL, else the values of the coefficient at the nq points
+ * per element of stig_quadrature (host, n_el * nq).  nq <= 0 selects p + 1. */
+stig_status stig_assemble_1d(int n_el, int p, double length, int kind,
+                             const double *weight, int nq, double *out);
+
+/* Load vector [g]_i = int f b_i (host, m entries) from the values of f at the
+ * stig_quadrature points (host, n_el * nq). */
+stig_status stig_load_1d(int n_el, int p, double length, const double *fvals,
+                         int nq, double *out);
+
+/* Symmetric-definite generalized eigenproblem K U = M U Lambda, U^T M U = I,
+ * eigenvalues ascending (host, n x n row-major in/out; lam: n).  The routine the
+ * setup uses; exposed for testing. */
+stig_status stig_sym_eig(int n, const double *K, const double *M, double *U,
+                         double *lam);
+
+const char *stig_status_string(stig_status status);
+const char *stig_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STIG_H */

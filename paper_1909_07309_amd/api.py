@@ -1,0 +1,217 @@
+"""Thin Python binding of libstig (argument marshalling only).
+
+Device buffers are PyTorch CUDA (HIP) tensors in float64; every operation
+runs in libstig's kernels on torch's current stream.  Names follow the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import PREC, StigInfo, check, dptr, lib
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, n: int, name: str) -> C.c_void_p:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A libstig plan for d spatial dims with sizes n_s (direction order 1..d), n_t time unknowns."""
+
+    def __init__(self, n_s, n_t, p_s, p_t):
+        n_s = [int(v) for v in n_s]
+        self.d = len(n_s)
+        self.n_s, self.n_t, self.p_s, self.p_t = n_s, int(n_t), int(p_s), int(p_t)
+        self.N_s = int(np.prod(n_s))
+        self.N = self.N_s * self.n_t
+        # tensor shape [t][x_d]..[x_1]
+        self.shape = (self.n_t,) + tuple(reversed(n_s))
+        h = C.c_void_p()
+        arr = (C.c_int * self.d)(*n_s)
+        check(lib().stig_plan_create(C.byref(h), self.d, arr, self.n_t, self.p_s, self.p_t,
+                                     _stream()))
+        self._h = h
+        self._keep = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().stig_plan_destroy(h)
+            self._h = None
+
+    def _sync_stream(self):
+        check(lib().stig_set_stream(self._h, _stream()))
+
+    def _nrhs(self, t):
+        n = t.numel()
+        if n % self.N:
+            raise ValueError(f"tensor size {n} is not a multiple of N = {self.N}")
+        return n // self.N
+
+    def setup_1d_pencils(self, K1d, M1d, Wt, Mt, gamma=1.0, nu=1.0):
+        mats = [np.ascontiguousarray(m, dtype=np.float64) for m in list(K1d) + list(M1d)]
+        self._host = mats
+        Ks = (C.POINTER(C.c_double) * self.d)(*[dptr(m) for m in mats[:self.d]])
+        Ms = (C.POINTER(C.c_double) * self.d)(*[dptr(m) for m in mats[self.d:]])
+        Wt = np.ascontiguousarray(Wt, dtype=np.float64)
+        Mt = np.ascontiguousarray(Mt, dtype=np.float64)
+        for l in range(self.d):
+            if mats[l].shape != (self.n_s[l], self.n_s[l]):
+                raise ValueError("spatial factor has the wrong shape")
+        if Wt.shape != (self.n_t, self.n_t) or Mt.shape != (self.n_t, self.n_t):
+            raise ValueError("time factor has the wrong shape")
+        self._sync_stream()
+        check(lib().stig_setup_1d_pencils(self._h, Ks, Ms, dptr(Wt), dptr(Mt), float(gamma),
+                                          float(nu)))
+
+    def set_diag_scaling(self, D):
+        self._sync_stream()
+        if D is None:
+            check(lib().stig_set_diag_scaling(self._h, None))
+        else:
+            check(lib().stig_set_diag_scaling(self._h, _dev(D, self.N, "D")))
+
+    def set_A_csr(self, rowptr, col, val):
+        self._sync_stream()
+        if rowptr is None:
+            self._keep.pop("csr", None)
+            check(lib().stig_set_A_csr(self._h, None, None, None, 0))
+            return
+        assert rowptr.dtype == torch.int64 and col.dtype == torch.int32 and val.dtype == torch.float64
+        assert rowptr.is_cuda and col.is_cuda and val.is_cuda
+        assert rowptr.numel() == self.N + 1 and col.numel() == val.numel()
+        self._keep["csr"] = (rowptr, col, val)
+        check(lib().stig_set_A_csr(self._h, C.c_void_p(rowptr.data_ptr()),
+                                   C.c_void_p(col.data_ptr()), C.c_void_p(val.data_ptr()),
+                                   int(val.numel())))
+
+    def apply_Pinv(self, r, s=None, transpose=False, prec="fp64"):
+        nrhs = self._nrhs(r)
+        if s is None:
+            s = torch.empty_like(r)
+        self._sync_stream()
+        check(lib().stig_apply_Pinv(self._h, _dev(r, nrhs * self.N, "r"),
+                                    _dev(s, nrhs * self.N, "s"), nrhs, int(bool(transpose)),
+                                    PREC[prec]))
+        return s
+
+    def matvec_A(self, x, y=None, transpose=False):
+        nrhs = self._nrhs(x)
+        if y is None:
+            y = torch.empty_like(x)
+        self._sync_stream()
+        check(lib().stig_matvec_A(self._h, _dev(x, nrhs * self.N, "x"),
+                                  _dev(y, nrhs * self.N, "y"), nrhs, int(bool(transpose))))
+        return y
+
+    def apply_mass(self, z, y=None):
+        nrhs = self._nrhs(z)
+        if y is None:
+            y = torch.empty_like(z)
+        self._sync_stream()
+        check(lib().stig_apply_mass(self._h, _dev(z, nrhs * self.N, "z"),
+                                    _dev(y, nrhs * self.N, "y"), nrhs))
+        return y
+
+    def lift_adjoint(self, a_col, b_col, lam, g=None):
+        nrhs = self._nrhs(lam)
+        a_col = np.ascontiguousarray(a_col, dtype=np.float64)
+        b_col = np.ascontiguousarray(b_col, dtype=np.float64)
+        assert a_col.shape == (self.n_t,) and b_col.shape == (self.n_t,)
+        if g is None:
+            g = torch.empty((nrhs,) + self.shape[1:], dtype=torch.float64, device=lam.device)
+        self._sync_stream()
+        check(lib().stig_lift_adjoint(self._h, dptr(a_col), dptr(b_col),
+                                      _dev(lam, nrhs * self.N, "lam"),
+                                      _dev(g, nrhs * self.N_s, "g"), nrhs))
+        return g
+
+    def gmres_solve(self, f, u=None, restart=30, rtol=1e-8, maxit=300, flexible=False,
+                    transpose=False, prec="fp64", allow_not_converged=False):
+        nrhs = self._nrhs(f)
+        if u is None:
+            u = torch.zeros_like(f)
+        info = StigInfo()
+        self._sync_stream()
+        code = lib().stig_gmres_solve(self._h, _dev(f, nrhs * self.N, "f"),
+                                      _dev(u, nrhs * self.N, "u"), nrhs, int(restart),
+                                      float(rtol), int(maxit), int(bool(flexible)),
+                                      int(bool(transpose)), PREC[prec], C.byref(info))
+        check(code, allow_warning=allow_not_converged)
+        return u, {"iters": info.iters, "restarts": info.restarts,
+                   "relres_true": info.relres_true, "relres_est": info.relres_est,
+                   "t_solve_ms": info.t_solve_ms, "converged": code == 0}
+
+    KERNEL_KINDS = ("mode_gemm", "time_solve", "band_pass", "krylov", "csr")
+
+    def profile_enable(self, on=True):
+        self._sync_stream()
+        check(lib().stig_profile_enable(self._h, int(bool(on))))
+
+    def profile_reset(self):
+        check(lib().stig_profile_reset(self._h))
+
+    def profile(self):
+        """{kind: (total_ms, algorithmic_bytes, launches)} for the kernels timed so far."""
+        out = {}
+        for k, name in enumerate(self.KERNEL_KINDS):
+            ms, by, n = C.c_double(), C.c_double(), C.c_longlong()
+            check(lib().stig_profile_get(self._h, k, C.byref(ms), C.byref(by), C.byref(n)))
+            out[name] = (ms.value, by.value, n.value)
+        return out
+
+    def device_bytes(self):
+        return int(lib().stig_plan_device_bytes(self._h))
+
+
+# ----------------------------------------------------------- 1D assembly (host)
+
+def quadrature(n_el, nq, length=1.0):
+    x = np.empty(n_el * nq)
+    w = np.empty(n_el * nq)
+    check(lib().stig_quadrature(n_el, nq, float(length), dptr(x), dptr(w)))
+    return x, w
+
+
+def assemble_1d(n_el, p, kind, length=1.0, weight=None, nq=0):
+    """Full (unrestricted) m x m 1D matrix; kind in {'mass', 'stiffness', 'advection'}."""
+    k = {"mass": 0, "stiffness": 1, "advection": 2}[kind]
+    m = n_el + p
+    out = np.empty((m, m))
+    wp = None
+    if weight is not None:
+        weight = np.ascontiguousarray(weight, dtype=np.float64)
+        wp = dptr(weight)
+    check(lib().stig_assemble_1d(n_el, p, float(length), k, wp, int(nq), dptr(out)))
+    return out
+
+
+def load_1d(n_el, p, fvals, nq, length=1.0):
+    fvals = np.ascontiguousarray(fvals, dtype=np.float64)
+    out = np.empty(n_el + p)
+    check(lib().stig_load_1d(n_el, p, float(length), dptr(fvals), int(nq), dptr(out)))
+    return out
+
+
+def sym_eig(K, M):
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = K.shape[0]
+    U = np.empty((n, n))
+    lam = np.empty(n)
+    check(lib().stig_sym_eig(n, dptr(K), dptr(M), dptr(U), dptr(lam)))
+    return lam, U

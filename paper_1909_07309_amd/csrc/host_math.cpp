@@ -1,0 +1,261 @@
+// Host-side numerics of libstig: Gauss-Legendre rules, B-spline evaluation,
+// 1D Galerkin matrices and the symmetric-definite eigensolver of the setup step.
+//
+// B-splines (Section 2.1): open uniform knot vector with p+1 repeated end knots
+// and n_el-1 simple interior knots, so m = n_el + p functions of maximal
+// continuity.  On a knot span only p+1 functions are nonzero; they are computed
+// with the triangular de Boor table (the Cox-de Boor recursion restricted to
+// the nonzero functions), and derivatives from the degree p-1 values.
+//
+// Eigensolver (step 1 of Algorithm 1, eq. space_eig): K U = M U Lambda with
+// U^T M U = I.  With M = L L^T (Cholesky), C = L^{-1} K L^{-T} is symmetric;
+// cyclic Jacobi rotations diagonalise C = Q Lambda Q^T; U = L^{-T} Q.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+#include <vector>
+
+#include "stig_internal.h"
+
+namespace stig {
+
+void gauss_legendre(int nq, std::vector<double> &x, std::vector<double> &w) {
+  // Nodes on [-1, 1]: Newton iteration on P_nq from the Chebyshev-like guess,
+  // P_n evaluated with the three-term recurrence (n+1)P_{n+1} = (2n+1)xP_n - nP_{n-1}.
+  x.assign(nq, 0.0);
+  w.assign(nq, 0.0);
+  for (int i = 0; i < nq; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (nq + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= nq; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (nq == 1) { p1 = z; p0 = 1.0; }
+      dp = nq * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= nq; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (nq == 1) { p1 = z; p0 = 1.0; }
+      dp = nq * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[nq - 1 - i] = z;  // ascending order
+    w[nq - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void element_quadrature(int n_el, int nq, double length, std::vector<double> &x,
+                        std::vector<double> &w) {
+  std::vector<double> g, gw;
+  gauss_legendre(nq, g, gw);
+  x.resize((size_t)n_el * nq);
+  w.resize((size_t)n_el * nq);
+  double h = length / n_el;
+  for (int e = 0; e < n_el; ++e)
+    for (int q = 0; q < nq; ++q) {
+      x[(size_t)e * nq + q] = e * h + 0.5 * h * (g[q] + 1.0);
+      w[(size_t)e * nq + q] = 0.5 * h * gw[q];
+    }
+}
+
+// Knot value xi_j (0-based, j = 0 .. m+p) of the open uniform knot vector.
+static inline double knot(int j, int n_el, int p, double length) {
+  int k = j - p;  // interior index
+  if (k <= 0) return 0.0;
+  if (k >= n_el) return length;
+  return length * (double)k / n_el;
+}
+
+// Values N[0..p] and derivatives D[0..p] of the p+1 B-splines that are nonzero on
+// element e (functions e .. e+p, 0-based) at the point x inside that element.
+void span_basis(int e, int n_el, int p, double length, double x, double *N, double *D) {
+  // de Boor triangle: degree-k values of functions e+p-k .. e+p on span [xi_{e+p}, xi_{e+p+1})
+  std::vector<double> left(p + 1), right(p + 1), val(p + 1, 0.0), prev(p + 1, 0.0);
+  int s = e + p;  // index of the span's left knot
+  val[0] = 1.0;
+  for (int k = 1; k <= p; ++k) {
+    left[k] = x - knot(s + 1 - k, n_el, p, length);
+    right[k] = knot(s + k, n_el, p, length) - x;
+    if (k == p) std::copy(val.begin(), val.begin() + p, prev.begin());  // degree p-1 values
+    double saved = 0.0;
+    for (int r = 0; r < k; ++r) {
+      double den = right[r + 1] + left[k - r];
+      double t = den != 0.0 ? val[r] / den : 0.0;
+      val[r] = saved + right[r + 1] * t;
+      saved = left[k - r] * t;
+    }
+    val[k] = saved;
+  }
+  for (int r = 0; r <= p; ++r) N[r] = val[r];
+  if (D) {
+    if (p == 0) { D[0] = 0.0; return; }
+    // prev[0..p-1]: degree p-1 functions e+1 .. e+p (global indices), nonzero on the span.
+    // b'_{i,p} = p/(xi_{i+p}-xi_i) b_{i,p-1} - p/(xi_{i+p+1}-xi_{i+1}) b_{i+1,p-1}
+    for (int r = 0; r <= p; ++r) {
+      int i = e + r;  // global function index
+      double a = 0.0, b = 0.0;
+      // b_{i,p-1} nonzero on this span iff e+1 <= i <= e+p  -> prev[i-e-1]
+      if (i >= e + 1) {
+        double den = knot(i + p, n_el, p, length) - knot(i, n_el, p, length);
+        if (den != 0.0) a = p / den * prev[i - e - 1];
+      }
+      if (i + 1 <= e + p) {
+        double den = knot(i + p + 1, n_el, p, length) - knot(i + 1, n_el, p, length);
+        if (den != 0.0) b = p / den * prev[i + 1 - e - 1];
+      }
+      D[r] = a - b;
+    }
+  }
+}
+
+void assemble_1d(int n_el, int p, double length, int kind, const double *weight, int nq,
+                 double *out) {
+  if (nq <= 0) nq = p + 1;
+  int m = n_el + p;
+  std::fill(out, out + (size_t)m * m, 0.0);
+  std::vector<double> x, w;
+  element_quadrature(n_el, nq, length, x, w);
+  std::vector<double> N(p + 1), D(p + 1);
+  for (int e = 0; e < n_el; ++e)
+    for (int q = 0; q < nq; ++q) {
+      size_t iq = (size_t)e * nq + q;
+      span_basis(e, n_el, p, length, x[iq], N.data(), D.data());
+      double c = w[iq] * (weight ? weight[iq] : 1.0);
+      for (int a = 0; a <= p; ++a)
+        for (int b = 0; b <= p; ++b) {
+          double v;
+          if (kind == 0) v = N[a] * N[b];
+          else if (kind == 1) v = D[a] * D[b];
+          else v = D[b] * N[a];  // row i = test function (value), column j = trial (derivative)
+          out[(size_t)(e + a) * m + (e + b)] += c * v;
+        }
+    }
+}
+
+void load_1d(int n_el, int p, double length, const double *fvals, int nq, double *out) {
+  int m = n_el + p;
+  std::fill(out, out + m, 0.0);
+  std::vector<double> x, w;
+  element_quadrature(n_el, nq, length, x, w);
+  std::vector<double> N(p + 1);
+  for (int e = 0; e < n_el; ++e)
+    for (int q = 0; q < nq; ++q) {
+      size_t iq = (size_t)e * nq + q;
+      span_basis(e, n_el, p, length, x[iq], N.data(), nullptr);
+      for (int a = 0; a <= p; ++a) out[e + a] += w[iq] * fvals[iq] * N[a];
+    }
+}
+
+// Returns false if M is not positive definite.
+bool sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  // Cholesky M = L L^T (lower)
+  for (int j = 0; j < n; ++j) {
+    double s = M[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(s > 0.0)) return false;
+    double d = std::sqrt(s);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = M[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = t / d;
+    }
+  }
+  // C = L^{-1} K L^{-T}: first Y = L^{-1} K (forward substitution per column),
+  // then C = L^{-1} Y^T (Y^T = K L^{-T} since K is symmetric).
+  std::vector<double> Y((size_t)n * n), C((size_t)n * n);
+  auto lower_solve = [&](const double *B, double *X) {  // X = L^{-1} B, B n x n row-major
+    for (int c = 0; c < n; ++c)
+      for (int i = 0; i < n; ++i) {
+        double s = B[(size_t)i * n + c];
+        for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * X[(size_t)k * n + c];
+        X[(size_t)i * n + c] = s / L[(size_t)i * n + i];
+      }
+  };
+  lower_solve(K, Y.data());
+  std::vector<double> Yt((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Yt[(size_t)i * n + j] = Y[(size_t)j * n + i];
+  lower_solve(Yt.data(), C.data());
+  for (int i = 0; i < n; ++i)  // symmetrise rounding
+    for (int j = i + 1; j < n; ++j) {
+      double a = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+      C[(size_t)i * n + j] = C[(size_t)j * n + i] = a;
+    }
+  // cyclic Jacobi on C, accumulating rotations in Q
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      diag += C[(size_t)i * n + i] * C[(size_t)i * n + i];
+      for (int j = i + 1; j < n; ++j) off += C[(size_t)i * n + j] * C[(size_t)i * n + j];
+    }
+    if (off <= 1e-34 * diag) break;
+    for (int pi = 0; pi < n - 1; ++pi)
+      for (int qi = pi + 1; qi < n; ++qi) {
+        double apq = C[(size_t)pi * n + qi];
+        if (apq == 0.0) continue;
+        double app = C[(size_t)pi * n + pi], aqq = C[(size_t)qi * n + qi];
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns pi, qi
+          double ckp = C[(size_t)k * n + pi], ckq = C[(size_t)k * n + qi];
+          C[(size_t)k * n + pi] = c * ckp - s * ckq;
+          C[(size_t)k * n + qi] = s * ckp + c * ckq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows pi, qi
+          double cpk = C[(size_t)pi * n + k], cqk = C[(size_t)qi * n + k];
+          C[(size_t)pi * n + k] = c * cpk - s * cqk;
+          C[(size_t)qi * n + k] = s * cpk + c * cqk;
+        }
+        C[(size_t)pi * n + qi] = C[(size_t)qi * n + pi] = 0.0;
+        for (int k = 0; k < n; ++k) {
+          double qkp = Q[(size_t)k * n + pi], qkq = Q[(size_t)k * n + qi];
+          Q[(size_t)k * n + pi] = c * qkp - s * qkq;
+          Q[(size_t)k * n + qi] = s * qkp + c * qkq;
+        }
+      }
+  }
+  // sort ascending
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(),
+            [&](int a, int b) { return C[(size_t)a * n + a] < C[(size_t)b * n + b]; });
+  // U = L^{-T} Q (back substitution with L^T per column), columns reordered
+  for (int cc = 0; cc < n; ++cc) {
+    int c = ord[cc];
+    lam[cc] = C[(size_t)c * n + c];
+    for (int i = n - 1; i >= 0; --i) {
+      double s = Q[(size_t)i * n + c];
+      for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * U[(size_t)k * n + cc];
+      U[(size_t)i * n + cc] = s / L[(size_t)i * n + i];
+    }
+  }
+  // deterministic sign: largest-magnitude entry of each eigenvector positive
+  for (int c = 0; c < n; ++c) {
+    int imax = 0;
+    for (int i = 1; i < n; ++i)
+      if (std::fabs(U[(size_t)i * n + c]) > std::fabs(U[(size_t)imax * n + c])) imax = i;
+    if (U[(size_t)imax * n + c] < 0)
+      for (int i = 0; i < n; ++i) U[(size_t)i * n + c] = -U[(size_t)i * n + c];
+  }
+  return true;
+}
+
+}  // namespace stig

@@ -1,0 +1,335 @@
+// Device kernels of the fast-diagonalization apply (steps 2-4 of Algorithm 1,
+// Section 4.4, with the time pencil kept banded).
+//
+//  * mode_gemm: one mode-k product Y = X x_k Op (Section 2.3) of the unknown
+//    tensor with a small dense square matrix (U_l or U_l^T), on MFMA.
+//  * time_band_solve: one banded shifted system (gamma W_t + nu lambda_k M_t)
+//    per spatial eigen-index k, Gaussian elimination without pivoting.
+//
+// The tensor is viewed as [outer][n][inner] around the contracted axis: a
+// "column" c in [0, outer*inner) is the pencil (o, i) = (c / inner, c % inner)
+// whose n entries sit at o*n*inner + k*inner + i.  A mode product is then the
+// GEMM Y[:, c] = Op * X[:, c] over all columns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stig {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// bf16 stored as its 16 raw bits.
+struct bf16 {
+  uint16_t bits;
+};
+
+__device__ __host__ inline uint16_t float_to_bf16_bits(float f) {
+  union { float f; uint32_t u; } v;
+  v.f = f;
+  uint32_t u = v.u;
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __host__ inline float bf16_bits_to_float(uint16_t b) {
+  union { float f; uint32_t u; } v;
+  v.u = ((uint32_t)b) << 16;
+  return v.f;
+}
+
+// Conversions between storage types and compute types.
+template <typename T> struct Conv;
+template <> struct Conv<double> {
+  __device__ static inline double to_f64(double x) { return x; }
+  __device__ static inline float to_f32(double x) { return (float)x; }
+  __device__ static inline double from_f64(double x) { return x; }
+  __device__ static inline double from_f32(float x) { return (double)x; }
+};
+template <> struct Conv<float> {
+  __device__ static inline double to_f64(float x) { return (double)x; }
+  __device__ static inline float to_f32(float x) { return x; }
+  __device__ static inline float from_f64(double x) { return (float)x; }
+  __device__ static inline float from_f32(float x) { return x; }
+};
+template <> struct Conv<bf16> {
+  __device__ static inline double to_f64(bf16 x) { return (double)bf16_bits_to_float(x.bits); }
+  __device__ static inline float to_f32(bf16 x) { return bf16_bits_to_float(x.bits); }
+  __device__ static inline bf16 from_f64(double x) { return bf16{float_to_bf16_bits((float)x)}; }
+  __device__ static inline bf16 from_f32(float x) { return bf16{float_to_bf16_bits(x)}; }
+};
+
+// ------------------------------------------------------------- MFMA traits
+// Each trait describes one 16x16 output tile instruction D = A(16xK) B(Kx16) + D.
+// Lane l of a wave holds A rows (l % 16), B columns (l % 16), and the k-slice
+// (l / 16) * KPL .. + KPL-1 of the current K step; the 4 accumulator values of
+// lane l are D rows 4*(l/16) + v, column l % 16.
+template <typename TC> struct Mfma;
+
+template <> struct Mfma<double> {
+  static constexpr int KSTEP = 4, KPL = 1;
+  typedef double elem;   // LDS element
+  typedef double frag;   // per-lane operand
+  typedef v4d acc;
+  typedef double acc_elem;
+  __device__ static inline frag load(const elem *p) { return *p; }
+  __device__ static inline acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline elem from_f64(double x) { return x; }
+  __device__ static inline elem zero() { return 0.0; }
+};
+
+template <> struct Mfma<float> {
+  static constexpr int KSTEP = 4, KPL = 1;
+  typedef float elem;
+  typedef float frag;
+  typedef v4f acc;
+  typedef float acc_elem;
+  __device__ static inline frag load(const elem *p) { return *p; }
+  __device__ static inline acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline elem from_f64(double x) { return (float)x; }
+  __device__ static inline elem zero() { return 0.0f; }
+};
+
+template <> struct Mfma<bf16> {
+  static constexpr int KSTEP = 16, KPL = 4;
+  typedef uint16_t elem;
+  typedef v4s frag;
+  typedef v4f acc;
+  typedef float acc_elem;
+  __device__ static inline frag load(const elem *p) {
+    return *reinterpret_cast<const v4s *>(p);  // 8-byte aligned by construction
+  }
+  __device__ static inline acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline elem from_f64(double x) { return float_to_bf16_bits((float)x); }
+  __device__ static inline elem zero() { return 0; }
+};
+
+__host__ __device__ constexpr inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Leading dimension (in elements) of an LDS tile holding k = 0 .. kpad-1 per
+// column, padded so consecutive columns start in different LDS banks.
+template <typename TC> __host__ __device__ inline int lds_ld(int n) {
+  int kpad = round_up(n, Mfma<TC>::KSTEP);
+  if (sizeof(typename Mfma<TC>::elem) >= 4) return kpad | 1;  // odd stride in 4/8-byte words
+  return kpad + 4;                                              // bf16: keep 8-byte alignment
+}
+
+constexpr int GEMM_TILE_COLS = 64;
+
+// Y[:, c] = Op * X[:, c] for all columns c (see header comment).
+// Op: n x n row-major in compute precision (device).
+// Block = JB waves (JB = blockDim.x / 64); blockIdx.y selects the group of JB
+// 16-row output tiles, wave w owns output rows 16*(JB*blockIdx.y + w) .. +15.
+// Dynamic LDS: (GEMM_TILE_COLS + 16*JB) * ld elements.
+// in_scale / out_scale: optional per-entry factors (length nscale, index taken
+// modulo nscale) multiplied in on load / on store.
+template <typename Tin, typename Tout, typename TC>
+__global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
+                          const typename Mfma<TC>::elem *__restrict__ Op, int n, int64_t inner,
+                          int64_t total_cols, const double *__restrict__ in_scale,
+                          const double *__restrict__ out_scale, int64_t nscale) {
+  typedef Mfma<TC> MF;
+  typedef typename MF::elem E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld = lds_ld<TC>(n);
+  const int kpad = round_up(n, MF::KSTEP);
+  const int JB = blockDim.x >> 6;
+  const int row0 = blockIdx.y * JB * 16;                 // first output row of this block
+  E *opl = reinterpret_cast<E *>(smem);                  // [16*JB][ld]
+  E *tile = opl + (size_t)16 * JB * ld;                  // [GEMM_TILE_COLS][ld]
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
+
+  // rows row0 .. row0+16*JB-1 of Op -> LDS once per block, zero padded.
+  for (int e = tid; e < 16 * JB * kpad; e += nthr) {
+    int jl = e / kpad, k = e - jl * kpad, j = row0 + jl;
+    opl[(size_t)jl * ld + k] = (j < n && k < n) ? Op[(size_t)j * n + k] : MF::zero();
+  }
+
+  const int64_t ntiles = (total_cols + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
+  const int64_t slab = (int64_t)n * inner;
+  const uint32_t uinner = (uint32_t)inner;  // host guarantees total_cols < 2^31
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t c0 = t * GEMM_TILE_COLS;
+    __syncthreads();  // previous tile fully consumed; Op visible
+    // ---- load the X tile (converted) into tile[col][k]
+    if (inner == 1) {
+      // the tile's columns are contiguous rows of length n in memory
+      for (int e = tid; e < GEMM_TILE_COLS * kpad; e += nthr) {
+        int col = e / kpad, k = e - col * kpad;
+        int64_t c = c0 + col;
+        E v = MF::zero();
+        if (c < total_cols && k < n) {
+          int64_t a = c * n + k;
+          double x = Conv<Tin>::to_f64(in[a]);
+          if (in_scale) x *= in_scale[a % nscale];
+          v = MF::from_f64(x);
+        }
+        tile[(size_t)col * ld + k] = v;
+      }
+    } else {
+      // nthr is a multiple of 64, so each thread always touches the same column
+      const int col = tid & (GEMM_TILE_COLS - 1);
+      const int64_t c = c0 + col;
+      const bool valid = c < total_cols;
+      int64_t base = 0;
+      if (valid) {
+        uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
+        base = (int64_t)o * slab + i;
+      }
+      for (int k = tid / GEMM_TILE_COLS; k < kpad; k += nthr / GEMM_TILE_COLS) {
+        E v = MF::zero();
+        if (valid && k < n) {
+          int64_t a = base + (int64_t)k * inner;
+          double x = Conv<Tin>::to_f64(in[a]);
+          if (in_scale) x *= in_scale[a % nscale];
+          v = MF::from_f64(x);
+        }
+        tile[(size_t)col * ld + k] = v;
+      }
+    }
+    __syncthreads();
+    // ---- MFMA: wave owns output rows row0+16*wave .. +15, all tile columns
+    typename MF::acc acc[GEMM_TILE_COLS / 16];
+#pragma unroll
+    for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct)
+      for (int v = 0; v < 4; ++v) acc[ct][v] = 0;
+    const E *arow = opl + (size_t)(wave * 16 + (lane & 15)) * ld + (lane >> 4) * MF::KPL;
+    const E *bcol = tile + (size_t)(lane & 15) * ld + (lane >> 4) * MF::KPL;
+    for (int k0 = 0; k0 < kpad; k0 += MF::KSTEP) {
+      typename MF::frag a = MF::load(arow + k0);
+#pragma unroll
+      for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
+        typename MF::frag b = MF::load(bcol + (size_t)ct * 16 * ld + k0);
+        acc[ct] = MF::mma(a, b, acc[ct]);
+      }
+    }
+    // ---- accumulators -> global, rows j < n; lane holds column (lane & 15) of
+    // each 16-column tile ct and rows 16*wave + 4*(lane>>4) + v.
+#pragma unroll
+    for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
+      int64_t c = c0 + ct * 16 + (lane & 15);
+      if (c >= total_cols) continue;
+      int64_t base, step;
+      if (inner == 1) {
+        base = c * n;
+        step = 1;
+      } else {
+        uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
+        base = (int64_t)o * slab + i;
+        step = inner;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int j = row0 + wave * 16 + (lane >> 4) * 4 + v;
+        if (j < n) {
+          int64_t a = base + (int64_t)j * step;
+          double y = (double)acc[ct][v];
+          if (out_scale) y *= out_scale[a % nscale];
+          out[a] = Conv<Tout>::from_f64(y);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- time solves
+// For each spatial eigen-index k (and right-hand side), solve
+//   (gamma W + nu lam_k M) q = r   along t (stride ns between consecutive t),
+// with banded W, M given as rows of 2P+1 coefficients: wb[i*(2P+1) + P + m] =
+// W[i][i+m] (zero outside the matrix).  Elimination without pivoting: the
+// symmetric part of the matrix is (gamma/2) e_n e_n^T + nu lam_k M, positive
+// definite, so every pivot is positive; a non-positive pivot sets *flag.
+// Scratch (compute type, [rhs][t][P+1][ns]): the U row entries u[i][i+1..i+P-1],
+// the reciprocal pivot and the forward-substituted y_i.  u[i][i+P] equals the
+// untouched matrix entry and is recomputed.
+template <typename Tio, typename TC, int P>
+__global__ void time_band_solve(const Tio *__restrict__ in, Tio *__restrict__ out,
+                                const double *__restrict__ lam, const TC *__restrict__ wb,
+                                const TC *__restrict__ mb, TC gamma, TC nu, int nt, int64_t ns,
+                                int nrhs, TC *__restrict__ scratch, int *__restrict__ flag) {
+  constexpr int B = 2 * P + 1;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ns * nrhs) return;
+  int64_t rhs = g / ns, k = g - rhs * ns;
+  const Tio *r = in + rhs * ns * nt + k;
+  Tio *q = out + rhs * ns * nt + k;
+  TC *sc = scratch + rhs * ns * nt * (P + 1) + k;
+  const TC lk = (TC)lam[k];
+  // rolling state of the previous P rows: U entries (c = 1..P), reciprocal pivot, y
+  TC pu[P][P + 1];   // pu[dist-1][c] = u[i-dist][i-dist+c], c = 1..P (index 0 unused)
+  TC prp[P], py[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    prp[a] = 0;
+    py[a] = 0;
+#pragma unroll
+    for (int c = 0; c <= P; ++c) pu[a][c] = 0;
+  }
+  bool bad = false;
+  for (int i = 0; i < nt; ++i) {
+    TC row[B];
+#pragma unroll
+    for (int m = 0; m < B; ++m) row[m] = gamma * wb[i * B + m] + nu * lk * mb[i * B + m];
+    TC y = Conv<Tio>::to_f64(r[(int64_t)i * ns]);
+    // eliminate with rows j = i-P .. i-1 (increasing j): dist = P .. 1
+#pragma unroll
+    for (int dist = P; dist >= 1; --dist) {
+      if (i - dist >= 0) {
+        TC l = row[P - dist] * prp[dist - 1];
+#pragma unroll
+        for (int c = 1; c <= P; ++c) row[P - dist + c] -= l * pu[dist - 1][c];
+        y -= l * py[dist - 1];
+      }
+    }
+    TC piv = row[P];
+    if (!(piv > (TC)0)) bad = true;
+    TC rp = (TC)1 / piv;
+    // shift state
+#pragma unroll
+    for (int a = P - 1; a >= 1; --a) {
+      prp[a] = prp[a - 1];
+      py[a] = py[a - 1];
+#pragma unroll
+      for (int c = 1; c <= P; ++c) pu[a][c] = pu[a - 1][c];
+    }
+    prp[0] = rp;
+    py[0] = y;
+#pragma unroll
+    for (int c = 1; c <= P; ++c) pu[0][c] = row[P + c];
+    TC *s = sc + (int64_t)i * (P + 1) * ns;
+#pragma unroll
+    for (int c = 1; c < P; ++c) s[(int64_t)(c - 1) * ns] = row[P + c];
+    s[(int64_t)(P - 1) * ns] = rp;
+    s[(int64_t)P * ns] = y;
+  }
+  if (bad) *flag = 1;
+  // back substitution, rolling last P solution values
+  TC qn[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) qn[a] = 0;  // qn[c-1] = q[i+c]
+  for (int i = nt - 1; i >= 0; --i) {
+    const TC *s = sc + (int64_t)i * (P + 1) * ns;
+    TC acc = s[(int64_t)P * ns];
+#pragma unroll
+    for (int c = 1; c < P; ++c) acc -= s[(int64_t)(c - 1) * ns] * qn[c - 1];
+    // outermost superdiagonal: untouched entry
+    TC uP = gamma * wb[i * B + 2 * P] + nu * lk * mb[i * B + 2 * P];
+    acc -= uP * qn[P - 1];
+    TC qi = acc * s[(int64_t)(P - 1) * ns];
+#pragma unroll
+    for (int a = P - 1; a >= 1; --a) qn[a] = qn[a - 1];
+    qn[0] = qi;
+    q[(int64_t)i * ns] = Conv<Tio>::from_f64((double)qi);
+  }
+}
+
+}  // namespace stig

@@ -1,0 +1,950 @@
+// libstig: C ABI over the HIP kernels of the fast-diagonalization apply, the
+// Kronecker / CSR matvec and (flexible) GMRES.  See include/stig.h for the
+// contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stig.h"
+#include "kernels_fd.h"
+#include "kernels_krylov.h"
+#include "kernels_matvec.h"
+#include "stig_internal.h"
+
+using namespace stig;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+stig_status fail(stig_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(STIG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));        \
+  } while (0)
+
+#define STIG_TRY(expr)                \
+  do {                                \
+    stig_status _s = (expr);          \
+    if (_s < 0) return _s;            \
+  } while (0)
+
+constexpr int MAX_P = 5;
+constexpr size_t GEMM_LDS_LIMIT = 160 * 1024;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  stig_status ensure(size_t need) {
+    if (need <= bytes) return STIG_OK;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    if (hipMalloc(&p, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STIG_ENOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    }
+    bytes = need;
+    return STIG_OK;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+template <typename T> stig_status upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
+  STIG_TRY(b.ensure(v.size() * sizeof(T)));
+  HIP_TRY(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return STIG_OK;
+}
+
+}  // namespace
+
+struct stig_plan {
+  int d = 0;
+  int n[3] = {1, 1, 1};
+  int nt = 0, ps = 0, pt = 0;
+  int64_t Ns = 0, N = 0;
+  hipStream_t stream = nullptr;
+  bool ready = false;
+  double gamma = 1.0, nu = 1.0;
+  // eigenvectors: [l] -> U_l and U_l^T in FP64, FP32, BF16 (row-major n x n)
+  DevBuf U64[3], UT64[3], U32[3], UT32[3], U16[3], UT16[3];
+  DevBuf lam;            // Ns doubles: lambda_k = sum_l lambda_{l,i_l}
+  DevBuf tW64, tWT64, tM64, tW32, tWT32, tM32;  // time bands (unscaled)
+  DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
+  DevBuf sK[3], sM[3];    // spatial bands (matvec, mass apply)
+  DevBuf dmh;             // D^{-1/2}, N doubles (optional)
+  bool has_dmh = false;
+  const int64_t *csr_rowptr = nullptr;
+  const int32_t *csr_col = nullptr;
+  const double *csr_val = nullptr;
+  int64_t csr_nnz = 0;
+  // scratch
+  DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, w, tmp, partial, small, flag, lift0, lift1;
+  std::vector<double> host_small;
+  // optional per-kernel timing with HIP events on the plan's stream
+  bool prof = false;
+  struct Pending {
+    int kind;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[STIG_NUM_KERNEL_KINDS] = {0};
+  double prof_bytes[STIG_NUM_KERNEL_KINDS] = {0};
+  long long prof_count[STIG_NUM_KERNEL_KINDS] = {0};
+  ~stig_plan() {
+    for (auto &q : pending) {
+      (void)hipEventDestroy(q.a);
+      (void)hipEventDestroy(q.b);
+    }
+    for (auto e : free_events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+
+stig_status check_plan(const stig_plan *p, bool need_ready) {
+  if (!p) return fail(STIG_EINVAL, "null plan");
+  if (need_ready && !p->ready) return fail(STIG_ESTATE, "stig_setup_1d_pencils has not been called");
+  return STIG_OK;
+}
+
+hipEvent_t take_event(stig_plan *p) {
+  if (!p->free_events.empty()) {
+    hipEvent_t e = p->free_events.back();
+    p->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one kernel launch with events when profiling is on.
+struct ProfScope {
+  stig_plan *p;
+  int kind;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(stig_plan *p_, int kind_, double bytes_) : p(p_), kind(kind_), bytes(bytes_) {
+    if (p->prof) {
+      a = take_event(p);
+      if (a) (void)hipEventRecord(a, p->stream);
+    }
+  }
+  ~ProfScope() {
+    if (p->prof && a) {
+      hipEvent_t b = take_event(p);
+      if (b) {
+        (void)hipEventRecord(b, p->stream);
+        p->pending.push_back({kind, bytes, a, b});
+      } else {
+        p->free_events.push_back(a);
+      }
+    }
+  }
+};
+
+stig_status prof_collect(stig_plan *p) {
+  if (p->pending.empty()) return STIG_OK;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (auto &q : p->pending) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, q.a, q.b));
+    p->prof_ms[q.kind] += ms;
+    p->prof_bytes[q.kind] += q.bytes;
+    p->prof_count[q.kind] += 1;
+    p->free_events.push_back(q.a);
+    p->free_events.push_back(q.b);
+  }
+  p->pending.clear();
+  return STIG_OK;
+}
+
+// band[j*(2P+1) + P + m] = A[j][j+m]; error if A has entries outside the band.
+stig_status extract_band(const double *A, int n, int P, std::vector<double> &band,
+                         const char *name) {
+  band.assign((size_t)n * (2 * P + 1), 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = A[(size_t)i * n + j];
+      if (std::abs(i - j) > P) {
+        if (v != 0.0)
+          return fail(STIG_EINVAL, std::string(name) + " has an entry outside its bandwidth");
+        continue;
+      }
+      band[(size_t)i * (2 * P + 1) + P + (j - i)] = v;
+    }
+  return STIG_OK;
+}
+
+template <typename T> std::vector<T> convert(const std::vector<double> &v);
+template <> std::vector<double> convert(const std::vector<double> &v) { return v; }
+template <> std::vector<float> convert(const std::vector<double> &v) {
+  return std::vector<float>(v.begin(), v.end());
+}
+template <> std::vector<uint16_t> convert(const std::vector<double> &v) {
+  std::vector<uint16_t> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = float_to_bf16_bits((float)v[i]);
+  return o;
+}
+
+inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ------------------------------------------------------------ mode GEMM launch
+
+template <typename Tin, typename Tout, typename TC>
+stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
+                             const typename Mfma<TC>::elem *op, int n, int64_t inner,
+                             int64_t total_cols, const double *in_scale,
+                             const double *out_scale) {
+  typedef typename Mfma<TC>::elem E;
+  if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
+  const int jt = (n + 15) / 16;
+  const int ld = lds_ld<TC>(n);
+  // as many 16-row output tiles per block as fit in LDS (all of them when possible,
+  // so each input tile is read from HBM once)
+  int JB = jt;
+  auto lds_of = [&](int jb) { return (size_t)(16 * jb + GEMM_TILE_COLS) * ld * sizeof(E); };
+  while (JB > 1 && lds_of(JB) > GEMM_LDS_LIMIT) JB = (JB + 1) / 2;
+  size_t lds = lds_of(JB);
+  if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
+  const int groups = (jt + JB - 1) / JB;
+  auto kern = mode_gemm<Tin, Tout, TC>;
+  static size_t configured = 0;  // per instantiation
+  if (lds > 65536 && lds > configured) {
+    HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    configured = lds;
+  }
+  int64_t ntiles = (total_cols + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
+  unsigned grid = (unsigned)std::min<int64_t>(ntiles, 4096);
+  ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
+  hipLaunchKernelGGL(kern, dim3(grid, groups), dim3(64 * JB), lds, p->stream, in, out, op, n, inner,
+                     total_cols, in_scale, out_scale, p->N);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tio, typename TC, int P>
+stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  const TC *wb, *mb;
+  if (std::is_same<TC, double>::value) {
+    wb = (const TC *)(transpose ? p->tWT64.p : p->tW64.p);
+    mb = (const TC *)p->tM64.p;
+  } else {
+    wb = (const TC *)(transpose ? p->tWT32.p : p->tW32.p);
+    mb = (const TC *)p->tM32.p;
+  }
+  int64_t work = p->Ns * nrhs;
+  ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
+  hipLaunchKernelGGL((time_band_solve<Tio, TC, P>), dim3(grid_for(work, 256)), dim3(256), 0,
+                     p->stream, in, out, p->lam.as<double>(), wb, mb, (TC)p->gamma, (TC)p->nu,
+                     p->nt, p->Ns, nrhs, p->tscr.as<TC>(), p->flag.as<int>());
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tio, typename TC>
+stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  STIG_TRY(p->tscr.ensure((size_t)(p->pt + 1) * p->N * nrhs * sizeof(TC)));
+  switch (p->pt) {
+    case 1: return launch_time_p<Tio, TC, 1>(p, in, out, nrhs, transpose);
+    case 2: return launch_time_p<Tio, TC, 2>(p, in, out, nrhs, transpose);
+    case 3: return launch_time_p<Tio, TC, 3>(p, in, out, nrhs, transpose);
+    case 4: return launch_time_p<Tio, TC, 4>(p, in, out, nrhs, transpose);
+    case 5: return launch_time_p<Tio, TC, 5>(p, in, out, nrhs, transpose);
+  }
+  return fail(STIG_EINVAL, "unsupported time degree");
+}
+
+// Typed access to the eigenvector copies of one precision.
+template <typename TC> struct OpSet;
+template <> struct OpSet<double> {
+  static const double *U(stig_plan *p, int l) { return p->U64[l].as<double>(); }
+  static const double *UT(stig_plan *p, int l) { return p->UT64[l].as<double>(); }
+};
+template <> struct OpSet<float> {
+  static const float *U(stig_plan *p, int l) { return p->U32[l].as<float>(); }
+  static const float *UT(stig_plan *p, int l) { return p->UT32[l].as<float>(); }
+};
+template <> struct OpSet<bf16> {
+  static const uint16_t *U(stig_plan *p, int l) { return p->U16[l].as<uint16_t>(); }
+  static const uint16_t *UT(stig_plan *p, int l) { return p->UT16[l].as<uint16_t>(); }
+};
+
+template <typename TC> struct TimeCompute { typedef float type; };
+template <> struct TimeCompute<double> { typedef double type; };
+
+// Steps 2-4 of Algorithm 1 with storage type S for the intermediates and compute
+// type TC for the GEMMs.
+template <typename S, typename TC>
+stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int transpose) {
+  const int64_t tot = p->N * nrhs;
+  STIG_TRY(p->s0.ensure(tot * sizeof(S)));
+  STIG_TRY(p->s1.ensure(tot * sizeof(S)));
+  S *buf[2] = {p->s0.as<S>(), p->s1.as<S>()};
+  int cur = 0;
+  const double *scale = p->has_dmh ? p->dmh.as<double>() : nullptr;
+  // step 2: forward spatial transform, X x_l U_l^T for l = 1..d
+  int64_t inner = 1;
+  for (int l = 0; l < p->d; ++l) {
+    int n = p->n[l];
+    int64_t cols = tot / n;
+    if (l == 0)
+      STIG_TRY((launch_mode_gemm<double, S, TC>(p, r, buf[cur], OpSet<TC>::UT(p, l), n, inner,
+                                                 cols, scale, nullptr)));
+    else {
+      STIG_TRY((launch_mode_gemm<S, S, TC>(p, buf[cur ^ 1], buf[cur], OpSet<TC>::UT(p, l), n,
+                                            inner, cols, nullptr, nullptr)));
+    }
+    cur ^= 1;
+    inner *= n;
+  }
+  // step 3: shifted time systems
+  STIG_TRY((launch_time<S, typename TimeCompute<TC>::type>(p, buf[cur ^ 1], buf[cur], nrhs,
+                                                            transpose)));
+  cur ^= 1;
+  // step 4: back transform, x_l U_l for l = d..1
+  for (int l = p->d - 1; l >= 0; --l) {
+    int n = p->n[l];
+    inner /= n;
+    int64_t cols = tot / n;
+    if (l == 0)
+      STIG_TRY((launch_mode_gemm<S, double, TC>(p, buf[cur ^ 1], s, OpSet<TC>::U(p, l), n, inner,
+                                                 cols, nullptr, scale)));
+    else {
+      STIG_TRY((launch_mode_gemm<S, S, TC>(p, buf[cur ^ 1], buf[cur], OpSet<TC>::U(p, l), n,
+                                            inner, cols, nullptr, nullptr)));
+      cur ^= 1;
+    }
+  }
+  return STIG_OK;
+}
+
+// --------------------------------------------------------------- band passes
+
+template <int P>
+stig_status band_pass_p(stig_plan *p, const double *in1, const double *in2, double *out1,
+                        double *out2, const double *Ba, const double *Bb, const double *Bc, int n,
+                        int64_t inner, int64_t total) {
+  ProfScope ps(p, STIG_K_BAND_PASS,
+               (double)total * 8 * ((in1 ? 1 : 0) + (in2 ? 1 : 0) + (out1 ? 1 : 0) + (out2 ? 1 : 0)));
+  if (inner == 1) {
+    hipLaunchKernelGGL(band_pass_contig<P>, dim3(grid_for(total, 256)), dim3(256), 0, p->stream,
+                       in1, in2, out1, out2, Ba, Bb, Bc, n, total);
+  } else {
+    int64_t cols = total / n;
+    hipLaunchKernelGGL(band_pass_strided<P>, dim3(grid_for(cols, 256)), dim3(256), 0, p->stream,
+                       in1, in2, out1, out2, Ba, Bb, Bc, n, inner, cols);
+  }
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+stig_status band_pass(stig_plan *p, int P, const double *in1, const double *in2, double *out1,
+                      double *out2, const double *Ba, const double *Bb, const double *Bc, int n,
+                      int64_t inner, int64_t total) {
+  switch (P) {
+    case 1: return band_pass_p<1>(p, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, total);
+    case 2: return band_pass_p<2>(p, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, total);
+    case 3: return band_pass_p<3>(p, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, total);
+    case 4: return band_pass_p<4>(p, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, total);
+    case 5: return band_pass_p<5>(p, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, total);
+  }
+  return fail(STIG_EINVAL, "unsupported degree");
+}
+
+// Spatial passes over a tensor of `tot` entries whose spatial part is the
+// fastest d axes.  mass_only: out_a = x (x) M_1 .. M_d.  Otherwise a = mass
+// chain, b = stiffness sum; returns pointers to the final (a, b).
+stig_status spatial_chain(stig_plan *p, const double *x, int64_t tot, bool with_stiff,
+                          const double **a_out, const double **b_out, DevBuf *bufs[4]) {
+  const double *a = x, *b = nullptr;
+  int slot = 0;
+  int64_t inner = 1;
+  for (int l = 0; l < p->d; ++l) {
+    double *oa = bufs[slot]->as<double>();
+    double *ob = with_stiff ? bufs[slot + 1]->as<double>() : nullptr;
+    STIG_TRY(band_pass(p, p->ps, a, b, oa, ob, p->sM[l].as<double>(), p->sM[l].as<double>(),
+                       p->sK[l].as<double>(), p->n[l], inner, tot));
+    a = oa;
+    b = ob;
+    slot ^= 2;
+    inner *= p->n[l];
+  }
+  *a_out = a;
+  *b_out = b;
+  return STIG_OK;
+}
+
+stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int transpose) {
+  const int64_t tot = p->N * nrhs;
+  if (p->csr_rowptr) {
+    if (transpose) return fail(STIG_EINVAL, "transposed product not supported on the CSR form");
+    for (int r = 0; r < nrhs; ++r) {
+      ProfScope ps(p, STIG_K_CSR, (double)p->csr_nnz * 12 + (double)p->N * 24);
+      hipLaunchKernelGGL(csr_spmv, dim3(grid_for(p->N * 64, 256)), dim3(256), 0, p->stream,
+                         p->csr_rowptr, p->csr_col, p->csr_val, x + r * p->N, y + r * p->N, p->N);
+      HIP_TRY(hipGetLastError());
+    }
+    return STIG_OK;
+  }
+  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+  for (auto *b : bufs) STIG_TRY(b->ensure(tot * sizeof(double)));
+  const double *a, *b;
+  STIG_TRY(spatial_chain(p, x, tot, true, &a, &b, bufs));
+  // time pass: y = nu (b x_t M_t) + gamma (a x_t W_t)
+  const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
+  STIG_TRY(band_pass(p, p->pt, a, b, nullptr, y, nullptr, p->tnM.as<double>(), gW, p->nt, p->Ns,
+                     tot));
+  return STIG_OK;
+}
+
+// ------------------------------------------------------------------- GMRES
+
+struct Krylov {
+  stig_plan *p;
+  double *partial() { return p->partial.as<double>(); }
+  double *small() { return p->small.as<double>(); }
+  // out[0..KRY_MAXV) of the small buffer region `slot`
+  double *slot(int k) { return small() + k * KRY_MAXV; }
+
+  stig_status dots(const double *V, int nv, const double *w, int with_norm, int out_slot) {
+    ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 1) * p->N * 8);
+    hipLaunchKernelGGL(krylov_dots, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N, nv, w,
+                       p->N, with_norm, partial());
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(reduce_partials, dim3(KRY_MAXV), dim3(KRY_BLOCK), 0, p->stream, partial(),
+                       KRY_GRID, slot(out_slot));
+    HIP_TRY(hipGetLastError());
+    return STIG_OK;
+  }
+  stig_status update(const double *V, int nv, const double *coef, double sign, double *w,
+                     int with_dots, int out_slot) {
+    ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 2) * p->N * 8);
+    hipLaunchKernelGGL(krylov_update, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N, nv,
+                       coef, sign, w, p->N, with_dots, partial());
+    HIP_TRY(hipGetLastError());
+    if (with_dots) {
+      hipLaunchKernelGGL(reduce_partials, dim3(KRY_MAXV), dim3(KRY_BLOCK), 0, p->stream,
+                         partial(), KRY_GRID, slot(out_slot));
+      HIP_TRY(hipGetLastError());
+    }
+    return STIG_OK;
+  }
+  stig_status axpby(const double *x, const double *y, double *out, double a, double b) {
+    hipLaunchKernelGGL(stig::axpby, dim3(grid_for(p->N, 256, 8192)), dim3(256), 0, p->stream, x,
+                       y, out, a, b, p->N);
+    HIP_TRY(hipGetLastError());
+    return STIG_OK;
+  }
+  // host value of ||x||_2 (synchronises)
+  stig_status norm(const double *x, double *out) {
+    STIG_TRY(dots(x, 0, x, 1, 3));
+    double v;
+    HIP_TRY(hipMemcpyAsync(&v, slot(3) + KRY_MAXV - 1, sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    *out = std::sqrt(v);
+    return STIG_OK;
+  }
+};
+
+stig_status apply_dispatch(stig_plan *p, const double *r, double *s, int nrhs, int transpose,
+                           stig_prec prec) {
+  switch (prec) {
+    case STIG_FP64: return run_apply<double, double>(p, r, s, nrhs, transpose);
+    case STIG_FP32: return run_apply<float, float>(p, r, s, nrhs, transpose);
+    case STIG_BF16: return run_apply<bf16, bf16>(p, r, s, nrhs, transpose);
+  }
+  return fail(STIG_EINVAL, "unknown precision");
+}
+
+stig_status check_flag(stig_plan *p) {
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, p->flag.p, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (f) {
+    int z = 0;
+    HIP_TRY(hipMemcpy(p->flag.p, &z, sizeof(int), hipMemcpyHostToDevice));
+    return fail(STIG_EBREAKDOWN, "non-positive pivot in a shifted time system");
+  }
+  return STIG_OK;
+}
+
+// One right-hand side: restarted (F)GMRES with right preconditioning.
+stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rtol, int maxit,
+                      int flexible, int transpose, stig_prec prec, stig_info *info) {
+  const int64_t N = p->N;
+  Krylov K{p};
+  STIG_TRY(p->V.ensure((size_t)(m + 1) * N * sizeof(double)));
+  if (flexible) STIG_TRY(p->Z.ensure((size_t)m * N * sizeof(double)));
+  STIG_TRY(p->w.ensure(N * sizeof(double)));
+  STIG_TRY(p->tmp.ensure(N * sizeof(double)));
+  double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *w = p->w.as<double>(),
+         *tmp = p->tmp.as<double>();
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> &hs = p->host_small;
+  hs.assign(4 * KRY_MAXV, 0.0);
+
+  double fnorm;
+  STIG_TRY(K.norm(f, &fnorm));
+  if (!std::isfinite(fnorm)) return fail(STIG_ENONFINITE, "non-finite right-hand side norm");
+  info->iters = 0;
+  info->restarts = 0;
+  info->relres_true = 0.0;
+  info->relres_est = 0.0;
+  if (fnorm == 0.0) {
+    HIP_TRY(hipMemsetAsync(u, 0, N * sizeof(double), p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return STIG_OK;
+  }
+  // r0 = f - A u
+  STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
+  STIG_TRY(K.axpby(f, tmp, V, 1.0, -1.0));
+  double beta;
+  STIG_TRY(K.norm(V, &beta));
+  if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite initial residual");
+  info->relres_true = beta / fnorm;
+  info->relres_est = info->relres_true;
+  int cycle = 0;
+  while (beta / fnorm > rtol && info->iters < maxit) {
+    if (cycle++ > 0) info->restarts++;
+    STIG_TRY(K.axpby(V, nullptr, V, 1.0 / beta, 0.0));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double *vj = V + (int64_t)j * N;
+      double *zj = flexible ? Z + (int64_t)j * N : tmp;
+      STIG_TRY(apply_dispatch(p, vj, zj, 1, transpose, prec));
+      STIG_TRY(run_matvec(p, zj, w, 1, transpose));
+      // classical Gram-Schmidt with one re-orthogonalisation
+      STIG_TRY(K.dots(V, j + 1, w, 0, 0));                  // h1 = V^T w
+      STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, w, 1, 1));  // w -= V h1; h2 = V^T w
+      STIG_TRY(K.update(V, j + 1, K.slot(1), -1.0, w, 1, 2));  // w -= V h2; ||w||^2
+      HIP_TRY(hipMemcpyAsync(hs.data(), K.slot(0), 3 * KRY_MAXV * sizeof(double),
+                             hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      STIG_TRY(check_flag(p));
+      info->iters++;
+      double hnext = std::sqrt(hs[2 * KRY_MAXV + KRY_MAXV - 1]);
+      double colnorm = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        double h = hs[i] + hs[KRY_MAXV + i];
+        H[(size_t)i * m + j] = h;
+        colnorm += h * h;
+      }
+      H[(size_t)(j + 1) * m + j] = hnext;
+      if (!std::isfinite(hnext) || !std::isfinite(colnorm))
+        return fail(STIG_ENONFINITE, "non-finite value in the Arnoldi process");
+      // apply previous rotations, then a new one that zeroes H[j+1][j]
+      for (int i = 0; i < j; ++i) {
+        double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[(size_t)j * m + j], b = hnext;
+      double rr = std::hypot(a, b);
+      cs[j] = rr == 0.0 ? 1.0 : a / rr;
+      sn[j] = rr == 0.0 ? 0.0 : b / rr;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      info->relres_est = std::fabs(g[j + 1]) / fnorm;
+      bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
+      if (info->relres_est <= rtol || breakdown || info->iters >= maxit) break;
+      if (j + 1 < m) STIG_TRY(K.axpby(w, nullptr, V + (int64_t)(j + 1) * N, 1.0 / hnext, 0.0));
+    }
+    // y = R^{-1} g
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
+      y[i] = s / H[(size_t)i * m + i];
+    }
+    std::copy(y.begin(), y.begin() + k, hs.begin() + 3 * KRY_MAXV);
+    HIP_TRY(hipMemcpyAsync(K.slot(3), hs.data() + 3 * KRY_MAXV, k * sizeof(double),
+                           hipMemcpyHostToDevice, p->stream));
+    if (flexible) {
+      STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));   // u += Z y
+    } else {
+      HIP_TRY(hipMemsetAsync(tmp, 0, N * sizeof(double), p->stream));
+      STIG_TRY(K.update(V, k, K.slot(3), 1.0, tmp, 0, 0)); // tmp = V y
+      STIG_TRY(apply_dispatch(p, tmp, w, 1, transpose, prec));
+      STIG_TRY(K.axpby(u, w, u, 1.0, 1.0));                 // u += P^{-1} V y
+    }
+    // true residual
+    STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
+    STIG_TRY(K.axpby(f, tmp, V, 1.0, -1.0));
+    STIG_TRY(K.norm(V, &beta));
+    if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite residual");
+    info->relres_true = beta / fnorm;
+  }
+  STIG_TRY(check_flag(p));
+  return info->relres_true <= rtol ? STIG_OK : STIG_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char *stig_status_string(stig_status s) {
+  switch (s) {
+    case STIG_OK: return "ok";
+    case STIG_NOT_CONVERGED: return "not converged";
+    case STIG_EINVAL: return "invalid argument";
+    case STIG_ENOMEM: return "out of device memory";
+    case STIG_EHIP: return "HIP runtime error";
+    case STIG_EBREAKDOWN: return "breakdown (non-positive pivot)";
+    case STIG_ENONFINITE: return "non-finite value";
+    case STIG_ESTATE: return "plan not set up";
+  }
+  return "unknown status";
+}
+
+const char *stig_last_error(void) { return g_last_error.c_str(); }
+
+stig_status stig_plan_create(stig_plan **out, int d, const int *n_s, int n_t, int p_s, int p_t,
+                             void *stream) {
+  if (!out) return fail(STIG_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (d < 1 || d > 3 || !n_s) return fail(STIG_EINVAL, "d must be 1..3 with n_s given");
+  if (n_t < 2 || n_t > 1024) return fail(STIG_EINVAL, "n_t out of range");
+  if (p_s < 1 || p_s > MAX_P || p_t < 1 || p_t > MAX_P)
+    return fail(STIG_EINVAL, "spline degree must be 1..5");
+  stig_plan *p = new stig_plan;
+  p->d = d;
+  p->Ns = 1;
+  for (int l = 0; l < d; ++l) {
+    if (n_s[l] < 1 || n_s[l] > 200) {
+      delete p;
+      return fail(STIG_EINVAL, "n_s out of range");
+    }
+    p->n[l] = n_s[l];
+    p->Ns *= n_s[l];
+  }
+  p->nt = n_t;
+  p->ps = p_s;
+  p->pt = p_t;
+  p->N = p->Ns * n_t;
+  p->stream = (hipStream_t)stream;
+  *out = p;
+  return STIG_OK;
+}
+
+void stig_plan_destroy(stig_plan *plan) { delete plan; }
+
+stig_status stig_set_stream(stig_plan *plan, void *stream) {
+  STIG_TRY(check_plan(plan, false));
+  plan->stream = (hipStream_t)stream;
+  return STIG_OK;
+}
+
+stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const double *const *M1d,
+                                  const double *Wt, const double *Mt, double gamma, double nu) {
+  STIG_TRY(check_plan(p, false));
+  if (!K1d || !M1d || !Wt || !Mt) return fail(STIG_EINVAL, "null matrix pointer");
+  if (!(gamma >= 0.0) || !(nu >= 0.0) || !std::isfinite(gamma) || !std::isfinite(nu))
+    return fail(STIG_EINVAL, "gamma and nu must be finite and non-negative");
+  p->ready = false;
+  p->gamma = gamma;
+  p->nu = nu;
+  hipStream_t s = p->stream;
+  std::vector<std::vector<double>> lams(p->d);
+  for (int l = 0; l < p->d; ++l) {
+    int n = p->n[l];
+    if (!K1d[l] || !M1d[l]) return fail(STIG_EINVAL, "null spatial factor");
+    std::vector<double> U((size_t)n * n), UT((size_t)n * n);
+    lams[l].resize(n);
+    if (!sym_eig(n, K1d[l], M1d[l], U.data(), lams[l].data()))
+      return fail(STIG_EBREAKDOWN, "spatial mass matrix is not positive definite");
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) UT[(size_t)i * n + j] = U[(size_t)j * n + i];
+    STIG_TRY(upload(p->U64[l], U, s));
+    STIG_TRY(upload(p->UT64[l], UT, s));
+    STIG_TRY(upload(p->U32[l], convert<float>(U), s));
+    STIG_TRY(upload(p->UT32[l], convert<float>(UT), s));
+    STIG_TRY(upload(p->U16[l], convert<uint16_t>(U), s));
+    STIG_TRY(upload(p->UT16[l], convert<uint16_t>(UT), s));
+    std::vector<double> kb, mb;
+    STIG_TRY(extract_band(K1d[l], n, p->ps, kb, "spatial stiffness"));
+    STIG_TRY(extract_band(M1d[l], n, p->ps, mb, "spatial mass"));
+    STIG_TRY(upload(p->sK[l], kb, s));
+    STIG_TRY(upload(p->sM[l], mb, s));
+    HIP_TRY(hipStreamSynchronize(s));  // host vectors go out of scope
+  }
+  // lambda_k = sum_l lambda_{l, i_l}, k = i_1 + n_1 (i_2 + n_2 i_3)
+  std::vector<double> lk(p->Ns);
+  for (int64_t k = 0; k < p->Ns; ++k) {
+    int64_t r = k;
+    double v = 0.0;
+    for (int l = 0; l < p->d; ++l) {
+      v += lams[l][r % p->n[l]];
+      r /= p->n[l];
+    }
+    lk[k] = v;
+  }
+  STIG_TRY(upload(p->lam, lk, s));
+  int nt = p->nt, P = p->pt;
+  std::vector<double> WT((size_t)nt * nt);
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j < nt; ++j) WT[(size_t)i * nt + j] = Wt[(size_t)j * nt + i];
+  std::vector<double> wb, wtb, mb;
+  STIG_TRY(extract_band(Wt, nt, P, wb, "W_t"));
+  STIG_TRY(extract_band(WT.data(), nt, P, wtb, "W_t"));
+  STIG_TRY(extract_band(Mt, nt, P, mb, "M_t"));
+  STIG_TRY(upload(p->tW64, wb, s));
+  STIG_TRY(upload(p->tWT64, wtb, s));
+  STIG_TRY(upload(p->tM64, mb, s));
+  STIG_TRY(upload(p->tW32, convert<float>(wb), s));
+  STIG_TRY(upload(p->tWT32, convert<float>(wtb), s));
+  STIG_TRY(upload(p->tM32, convert<float>(mb), s));
+  std::vector<double> gw(wb), gwt(wtb), nm(mb);
+  for (auto &v : gw) v *= gamma;
+  for (auto &v : gwt) v *= gamma;
+  for (auto &v : nm) v *= nu;
+  STIG_TRY(upload(p->tgW, gw, s));
+  STIG_TRY(upload(p->tgWT, gwt, s));
+  STIG_TRY(upload(p->tnM, nm, s));
+  STIG_TRY(p->flag.ensure(sizeof(int)));
+  HIP_TRY(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
+  STIG_TRY(p->partial.ensure((size_t)KRY_MAXV * KRY_GRID * sizeof(double)));
+  STIG_TRY(p->small.ensure((size_t)4 * KRY_MAXV * sizeof(double)));
+  HIP_TRY(hipStreamSynchronize(s));
+  // pivot check: one FP64 time pass on a zero input factors every shifted system
+  {
+    DevBuf zin, zout;
+    STIG_TRY(zin.ensure(p->N * sizeof(double)));
+    STIG_TRY(zout.ensure(p->N * sizeof(double)));
+    HIP_TRY(hipMemsetAsync(zin.p, 0, p->N * sizeof(double), s));
+    STIG_TRY((launch_time<double, double>(p, zin.as<double>(), zout.as<double>(), 1, 0)));
+    HIP_TRY(hipStreamSynchronize(s));
+    STIG_TRY(check_flag(p));
+  }
+  p->ready = true;
+  return STIG_OK;
+}
+
+stig_status stig_set_diag_scaling(stig_plan *p, const double *D) {
+  STIG_TRY(check_plan(p, false));
+  if (!D) {
+    p->has_dmh = false;
+    return STIG_OK;
+  }
+  STIG_TRY(p->dmh.ensure(p->N * sizeof(double)));
+  hipLaunchKernelGGL(rsqrt_copy, dim3(grid_for(p->N, 256, 8192)), dim3(256), 0, p->stream, D,
+                     p->dmh.as<double>(), p->N);
+  HIP_TRY(hipGetLastError());
+  p->has_dmh = true;
+  return STIG_OK;
+}
+
+stig_status stig_set_A_csr(stig_plan *p, const int64_t *rowptr, const int32_t *col,
+                           const double *val, int64_t nnz) {
+  STIG_TRY(check_plan(p, false));
+  if (!rowptr) {
+    p->csr_rowptr = nullptr;
+    return STIG_OK;
+  }
+  if (!col || !val || nnz < 0) return fail(STIG_EINVAL, "bad CSR arrays");
+  p->csr_rowptr = rowptr;
+  p->csr_col = col;
+  p->csr_val = val;
+  p->csr_nnz = nnz;
+  return STIG_OK;
+}
+
+stig_status stig_apply_Pinv(stig_plan *p, const double *r, double *s, int nrhs, int transpose,
+                            stig_prec prec) {
+  STIG_TRY(check_plan(p, true));
+  if (!r || !s || nrhs < 1) return fail(STIG_EINVAL, "bad apply arguments");
+  if (r == s) return fail(STIG_EINVAL, "r and s must not overlap");
+  return apply_dispatch(p, r, s, nrhs, transpose ? 1 : 0, prec);
+}
+
+stig_status stig_matvec_A(stig_plan *p, const double *x, double *y, int nrhs, int transpose) {
+  STIG_TRY(check_plan(p, true));
+  if (!x || !y || nrhs < 1 || x == y) return fail(STIG_EINVAL, "bad matvec arguments");
+  return run_matvec(p, x, y, nrhs, transpose ? 1 : 0);
+}
+
+stig_status stig_apply_mass(stig_plan *p, const double *z, double *y, int nrhs) {
+  STIG_TRY(check_plan(p, true));
+  if (!z || !y || nrhs < 1 || z == y) return fail(STIG_EINVAL, "bad mass-apply arguments");
+  const int64_t tot = p->N * nrhs;
+  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+  for (auto *b : bufs) STIG_TRY(b->ensure(tot * sizeof(double)));
+  const double *a, *b;
+  STIG_TRY(spatial_chain(p, z, tot, false, &a, &b, bufs));
+  return band_pass(p, p->pt, a, nullptr, y, nullptr, p->tM64.as<double>(), nullptr, nullptr, p->nt,
+                   p->Ns, tot);
+}
+
+stig_status stig_lift_adjoint(stig_plan *p, const double *a_col, const double *b_col,
+                              const double *lam, double *g, int nrhs) {
+  STIG_TRY(check_plan(p, true));
+  if (!a_col || !b_col || !lam || !g || nrhs < 1) return fail(STIG_EINVAL, "bad lift arguments");
+  const int64_t ts = p->Ns * nrhs;
+  std::vector<double> ab(a_col, a_col + p->nt), bb(b_col, b_col + p->nt);
+  DevBuf wa, wbv;
+  STIG_TRY(upload(wa, ab, p->stream));
+  STIG_TRY(upload(wbv, bb, p->stream));
+  STIG_TRY(p->lift0.ensure(ts * sizeof(double)));
+  STIG_TRY(p->lift1.ensure(ts * sizeof(double)));
+  hipLaunchKernelGGL(time_weighted_sum, dim3(grid_for(ts, 256)), dim3(256), 0, p->stream, lam,
+                     p->lift0.as<double>(), wa.as<double>(), p->nt, p->Ns, nrhs);
+  hipLaunchKernelGGL(time_weighted_sum, dim3(grid_for(ts, 256)), dim3(256), 0, p->stream, lam,
+                     p->lift1.as<double>(), wbv.as<double>(), p->nt, p->Ns, nrhs);
+  HIP_TRY(hipGetLastError());
+  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+  for (auto *b : bufs) STIG_TRY(b->ensure(ts * sizeof(double)));
+  const double *ma, *dummy, *sa, *sb;
+  STIG_TRY(spatial_chain(p, p->lift0.as<double>(), ts, false, &ma, &dummy, bufs));
+  // keep the mass result: copy it to g scaled, before the buffers are reused
+  hipLaunchKernelGGL(stig::axpby, dim3(grid_for(ts, 256, 8192)), dim3(256), 0, p->stream, ma,
+                     nullptr, g, -p->gamma, 0.0, ts);
+  HIP_TRY(hipGetLastError());
+  STIG_TRY(spatial_chain(p, p->lift1.as<double>(), ts, true, &sa, &sb, bufs));
+  hipLaunchKernelGGL(stig::axpby, dim3(grid_for(ts, 256, 8192)), dim3(256), 0, p->stream, g, sb,
+                     g, 1.0, -p->nu, ts);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(p->stream));  // wa, wbv freed on return
+  return STIG_OK;
+}
+
+stig_status stig_gmres_solve(stig_plan *p, const double *f, double *u, int nrhs, int restart,
+                             double rtol, int maxit, int flexible, int transpose, stig_prec prec,
+                             stig_info *info) {
+  STIG_TRY(check_plan(p, true));
+  if (!f || !u || nrhs < 1 || f == u) return fail(STIG_EINVAL, "bad solve arguments");
+  if (restart < 1 || restart > KRY_MAXV - 1) return fail(STIG_EINVAL, "restart must be 1..32");
+  if (!(rtol > 0.0) || maxit < 1) return fail(STIG_EINVAL, "rtol must be > 0 and maxit >= 1");
+  if (prec != STIG_FP64 && !flexible)
+    return fail(STIG_EINVAL, "a low-precision preconditioner needs flexible GMRES");
+  auto t0 = std::chrono::steady_clock::now();
+  stig_info worst{0, 0, 0.0, 0.0, 0.0};
+  stig_status result = STIG_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    stig_info one{0, 0, 0.0, 0.0, 0.0};
+    stig_status st = gmres_one(p, f + r * p->N, u + r * p->N, restart, rtol, maxit, flexible,
+                               transpose ? 1 : 0, prec, &one);
+    if (st < 0) return st;
+    if (st == STIG_NOT_CONVERGED) result = st;
+    worst.iters = std::max(worst.iters, one.iters);
+    worst.restarts = std::max(worst.restarts, one.restarts);
+    worst.relres_true = std::max(worst.relres_true, one.relres_true);
+    worst.relres_est = std::max(worst.relres_est, one.relres_est);
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  worst.t_solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = worst;
+  return result;
+}
+
+stig_status stig_profile_enable(stig_plan *p, int on) {
+  STIG_TRY(check_plan(p, false));
+  if (!on) STIG_TRY(prof_collect(p));
+  p->prof = on != 0;
+  return STIG_OK;
+}
+
+stig_status stig_profile_reset(stig_plan *p) {
+  STIG_TRY(check_plan(p, false));
+  STIG_TRY(prof_collect(p));
+  for (int k = 0; k < STIG_NUM_KERNEL_KINDS; ++k) {
+    p->prof_ms[k] = 0.0;
+    p->prof_bytes[k] = 0.0;
+    p->prof_count[k] = 0;
+  }
+  return STIG_OK;
+}
+
+stig_status stig_profile_get(stig_plan *p, int kind, double *total_ms, double *bytes,
+                             long long *launches) {
+  STIG_TRY(check_plan(p, false));
+  if (kind < 0 || kind >= STIG_NUM_KERNEL_KINDS) return fail(STIG_EINVAL, "bad kernel kind");
+  STIG_TRY(prof_collect(p));
+  if (total_ms) *total_ms = p->prof_ms[kind];
+  if (bytes) *bytes = p->prof_bytes[kind];
+  if (launches) *launches = p->prof_count[kind];
+  return STIG_OK;
+}
+
+size_t stig_plan_device_bytes(const stig_plan *p) {
+  if (!p) return 0;
+  size_t t = 0;
+  const DevBuf *bs[] = {&p->lam, &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
+                        &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->s0, &p->s1, &p->tscr, &p->m0,
+                        &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->w, &p->tmp, &p->partial,
+                        &p->small, &p->flag, &p->lift0, &p->lift1};
+  for (auto *b : bs) t += b->bytes;
+  for (int l = 0; l < 3; ++l)
+    t += p->U64[l].bytes + p->UT64[l].bytes + p->U32[l].bytes + p->UT32[l].bytes +
+         p->U16[l].bytes + p->UT16[l].bytes + p->sK[l].bytes + p->sM[l].bytes;
+  return t;
+}
+
+stig_status stig_quadrature(int n_el, int nq, double length, double *x, double *w) {
+  if (n_el < 1 || nq < 1 || !x || !w || !(length > 0)) return fail(STIG_EINVAL, "bad quadrature");
+  std::vector<double> xs, ws;
+  element_quadrature(n_el, nq, length, xs, ws);
+  std::copy(xs.begin(), xs.end(), x);
+  std::copy(ws.begin(), ws.end(), w);
+  return STIG_OK;
+}
+
+stig_status stig_assemble_1d(int n_el, int p, double length, int kind, const double *weight,
+                             int nq, double *out) {
+  if (n_el < 1 || p < 1 || p > 16 || kind < 0 || kind > 2 || !out || !(length > 0))
+    return fail(STIG_EINVAL, "bad 1D assembly arguments");
+  assemble_1d(n_el, p, length, kind, weight, nq, out);
+  return STIG_OK;
+}
+
+stig_status stig_load_1d(int n_el, int p, double length, const double *fvals, int nq,
+                         double *out) {
+  if (n_el < 1 || p < 1 || nq < 1 || !fvals || !out || !(length > 0))
+    return fail(STIG_EINVAL, "bad 1D load arguments");
+  load_1d(n_el, p, length, fvals, nq, out);
+  return STIG_OK;
+}
+
+stig_status stig_sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
+  if (n < 1 || !K || !M || !U || !lam) return fail(STIG_EINVAL, "bad eigenproblem arguments");
+  if (!sym_eig(n, K, M, U, lam)) return fail(STIG_EBREAKDOWN, "M is not positive definite");
+  return STIG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,29 @@
+// Internal declarations shared by the host translation units of libstig.
+#pragma once
+
+#include <vector>
+
+namespace stig {
+
+// Gauss-Legendre rule with nq points on [-1, 1], nodes ascending.
+void gauss_legendre(int nq, std::vector<double> &x, std::vector<double> &w);
+
+// nq Gauss points per element of [0, length] split into n_el equal elements.
+void element_quadrature(int n_el, int nq, double length, std::vector<double> &x,
+                        std::vector<double> &w);
+
+// Values (and derivatives if D != nullptr) of the p+1 B-splines nonzero on
+// element e at the point x of that element; function indices e .. e+p.
+void span_basis(int e, int n_el, int p, double length, double x, double *N, double *D);
+
+// Dense m x m 1D Galerkin matrix (kind 0 mass, 1 stiffness, 2 advection).
+void assemble_1d(int n_el, int p, double length, int kind, const double *weight, int nq,
+                 double *out);
+
+// Load vector from values of f at the element quadrature points.
+void load_1d(int n_el, int p, double length, const double *fvals, int nq, double *out);
+
+// K U = M U Lambda, U^T M U = I, ascending; false if M is not SPD.
+bool sym_eig(int n, const double *K, const double *M, double *U, double *lam);
+
+}  // namespace stig

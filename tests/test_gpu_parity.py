@@ -1,0 +1,144 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Floating-point bars: FP64 A-hat^{-1} within 1e-12 relative (max-norm, relative
+to the largest reference entry); FP64 matvec and mass apply within 1e-13;
+GMRES solutions with oracle-recomputed relative residual <= rtol.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import dense
+from oracle import fd
+from oracle.problems import CubeProblem
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _relmax(a, ref):
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
+
+
+def _setup(name, n_el, **kw):
+    from paper_1909_07309_amd.problem import CubeFactors
+    w = wl.scaled(wl.WORKLOADS[name], n_el, **kw) if n_el else wl.WORKLOADS[name]
+    fac = CubeFactors(w)
+    return w, fac, fac.make_plan(), CubeProblem(w)
+
+
+# sizes span one and several 16-row MFMA tiles, 64-column tiles and ragged tails
+SHAPES = [("square_p2_n8", None), ("square_p2_n8", 17), ("cube_p3_n64", 5),
+          ("cube_p3_n64", 14), ("cube_p3_n64", 31), ("annulus_p4_n128", 20)]
+
+
+@pytest.mark.parametrize("name,n_el", SHAPES)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_pinv_fp64_matches_oracle(name, n_el, transpose):
+    w, fac, plan, pr = _setup(name, n_el)
+    r = wl.random_tensor((2,) + w.shape, 7)
+    s = plan.apply_Pinv(_dev(r), transpose=transpose).cpu().numpy()
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, w.gamma, w.nu)
+    for b in range(2):
+        ref = P.apply(r[b], transpose=transpose)
+        assert _relmax(s[b], ref) <= 1e-12
+
+
+def test_apply_pinv_matches_dense_solve_tiny():
+    w, fac, plan, pr = _setup("cube_p3_n64", 3)
+    A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    r = wl.random_tensor(w.shape, 3)
+    s = plan.apply_Pinv(_dev(r)).cpu().numpy()
+    assert _relmax(s.ravel(), dense.solve(A, r.ravel())) <= 1e-12
+
+
+@pytest.mark.parametrize("name,n_el", SHAPES)
+def test_matvec_and_mass_match_oracle(name, n_el):
+    w, fac, plan, pr = _setup(name, n_el)
+    x = wl.random_tensor((2,) + w.shape, 9)
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
+    m = plan.apply_mass(_dev(x)).cpu().numpy()
+    for b in range(2):
+        ref = fd.kron_matvec(x[b], pr.Wt, pr.Mt, pr.K1d, pr.M1d, w.gamma, w.nu)
+        reft = fd.kron_matvec(x[b], pr.Wt, pr.Mt, pr.K1d, pr.M1d, w.gamma, w.nu, transpose=True)
+        refm = fd.mass_apply(x[b], pr.Mt, pr.M1d)
+        assert _relmax(y[b], ref) <= 1e-13
+        assert _relmax(yt[b], reft) <= 1e-13
+        assert _relmax(m[b], refm) <= 1e-13
+
+
+def test_square_solve_matches_dense_direct():
+    """The 2D unit-square workload (p=2, 8 elements, 10 random sines), GMRES(30) to 1e-10."""
+    from paper_1909_07309_amd.problem import source
+    w, fac, plan, pr = _setup("square_p2_n8", None)
+    f = source(w, plan)
+    f_ref = pr.source()
+    assert _relmax(f.cpu().numpy(), f_ref) <= 1e-13
+    u, info = plan.gmres_solve(f, restart=w.restart, rtol=w.rtol, maxit=w.maxit)
+    A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    u = u.cpu().numpy().ravel()
+    res = np.linalg.norm(f_ref.ravel() - A @ u) / np.linalg.norm(f_ref)
+    assert res <= w.rtol
+    u_ref = dense.solve(A, f_ref.ravel())
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    assert info["iters"] == 1        # A-hat = A on the unit square
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_fgmres_reaches_fp64_accuracy(prec):
+    from paper_1909_07309_amd.problem import source
+    w, fac, plan, pr = _setup("cube_p3_n64", 12)
+    f = source(w, plan)
+    u, info = plan.gmres_solve(f, restart=30, rtol=1e-8, maxit=100, flexible=True, prec=prec)
+    f_ref = pr.source()
+    u = u.cpu().numpy()
+    r = f_ref - fd.kron_matvec(u, pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    assert np.linalg.norm(r) / np.linalg.norm(f_ref) <= 1e-8
+    assert info["iters"] > 1     # the low-precision apply is inexact
+    # per-apply accuracy: ||A P~^{-1} r - r|| / ||r||
+    rr = wl.random_tensor(w.shape, 4)
+    s = plan.apply_Pinv(_dev(rr), prec=prec).cpu().numpy()
+    e = np.linalg.norm(fd.kron_matvec(s, pr.Wt, pr.Mt, pr.K1d, pr.M1d) - rr) / np.linalg.norm(rr)
+    assert e < (1e-5 if prec == "fp32" else 0.5)
+
+
+def test_full_size_cube_apply_and_solve():
+    """The 3D cube at p=3, 64 elements (18,125,250 unknowns), in the bench's launch shape."""
+    from paper_1909_07309_amd.problem import source
+    w, fac, plan, pr = _setup("cube_p3_n64", None)
+    f = source(w, plan)
+    f_ref = pr.source()
+    assert _relmax(f.cpu().numpy(), f_ref) <= 1e-13
+    s = plan.apply_Pinv(f).cpu().numpy()
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt)
+    ref = P.apply(f_ref)
+    assert _relmax(s, ref) <= 1e-12
+    u, info = plan.gmres_solve(f, restart=30, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    r = f_ref - fd.kron_matvec(u, pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    assert np.linalg.norm(r) / np.linalg.norm(f_ref) <= 1e-8
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_errors_are_reported():
+    from paper_1909_07309_amd import StigError
+    w, fac, plan, pr = _setup("square_p2_n8", None)
+    x = torch.zeros(w.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(StigError):
+        plan.apply_Pinv(x, s=x)                       # overlapping buffers
+    f = x.clone()
+    f.view(-1)[3] = float("nan")
+    with pytest.raises(StigError) as e:
+        plan.gmres_solve(f)
+    assert e.value.code == -5                         # non-finite
+    with pytest.raises(StigError) as e:
+        plan.gmres_solve(x + 1.0, prec="bf16")        # low precision needs flexible GMRES
+    assert e.value.code == -1
+    u, info = plan.gmres_solve(torch.ones_like(x), rtol=1e-30, maxit=1,
+                               allow_not_converged=True)
+    assert not info["converged"] and info["iters"] == 1

@@ -1,0 +1,92 @@
+"""CPU tests of libstig's host side: the library loads and exports every entry
+point of include/stig.h, its host numerics (quadrature, B-spline assembly,
+eigensolver) agree with the oracle, and argument validation returns the
+documented codes.  No GPU call is made."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bsplines as bs
+from oracle import fd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1909_07309_amd import _lib as L
+    return L
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "stig.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stig_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = L.lib()
+    syms = header_symbols()
+    assert "stig_apply_Pinv" in syms and "stig_gmres_solve" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in L.SIGNATURES, f"{s} has no ctypes signature"
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n_el", [1, 3, 8, 13])
+def test_assembly_matches_oracle(p, n_el):
+    from paper_1909_07309_amd import api
+    for T in (1.0, 2.5):
+        xi = bs.open_uniform_knots(n_el, p, T)
+        for kind, ref in (("mass", bs.mass(xi, p)), ("stiffness", bs.stiffness(xi, p)),
+                          ("advection", bs.advection(xi, p))):
+            A = api.assemble_1d(n_el, p, kind, length=T)
+            assert np.abs(A - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (kind, T)
+
+
+def test_weighted_assembly_and_load_match_oracle():
+    from paper_1909_07309_amd import api
+    n_el, p, nq = 6, 3, 6
+    x, w = api.quadrature(n_el, nq)
+    xo, wo = bs.gauss_points(bs.open_uniform_knots(n_el, p), nq)
+    assert np.abs(x - xo).max() < 1e-15 and np.abs(w - wo).max() < 1e-15
+    c = 1.0 / (1.0 + 0.3 * np.cos(np.pi * x))
+    A = api.assemble_1d(n_el, p, "mass", weight=c, nq=nq)
+    ref = bs.mass(bs.open_uniform_knots(n_el, p), p,
+                  weight=lambda t: 1.0 / (1.0 + 0.3 * np.cos(np.pi * t)), nq=nq)
+    assert np.abs(A - ref).max() < 1e-15
+    g = api.load_1d(n_el, p, np.sin(2 * np.pi * x), nq)
+    go = bs.load(bs.open_uniform_knots(n_el, p), p, lambda t: np.sin(2 * np.pi * t), nq=nq)
+    assert np.abs(g - go).max() < 1e-15
+
+
+@pytest.mark.parametrize("n_el,p", [(8, 2), (64, 3), (128, 4)])
+def test_host_eigensolver_matches_oracle(n_el, p):
+    from paper_1909_07309_amd import api
+    K, M = bs.space_matrices(n_el, p)
+    lam, U = api.sym_eig(K, M)
+    lo, _ = fd.space_eig(K, M)
+    assert np.abs(lam - lo).max() <= 1e-12 * lo.max()
+    n = len(lam)
+    assert np.abs(U.T @ M @ U - np.eye(n)).max() < 1e-12
+    assert np.abs(U.T @ K @ U - np.diag(lam)).max() < 1e-12 * lam.max()
+
+
+def test_argument_validation_without_gpu():
+    L = _lib()
+    lib = L.lib()
+    h = C.c_void_p()
+    n = (C.c_int * 3)(65, 65, 65)
+    assert lib.stig_plan_create(C.byref(h), 4, n, 66, 3, 3, None) == -1       # d > 3
+    assert lib.stig_plan_create(C.byref(h), 3, n, 66, 9, 3, None) == -1       # degree too high
+    assert lib.stig_plan_create(C.byref(h), 3, n, 66, 3, 3, None) == 0
+    # apply before setup -> ESTATE; no device memory is touched
+    assert lib.stig_apply_Pinv(h, C.c_void_p(8), C.c_void_p(16), 1, 0, 0) == -6
+    assert b"setup" in lib.stig_last_error()
+    assert lib.stig_gmres_solve(h, None, None, 1, 30, 1e-8, 10, 0, 0, 0, None) == -6
+    lib.stig_plan_destroy(h)
+    assert lib.stig_status_string(-4) == b"breakdown (non-positive pivot)"
