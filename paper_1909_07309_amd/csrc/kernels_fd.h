@@ -64,8 +64,10 @@ template <> struct Conv<bf16> {
 // ------------------------------------------------------------- MFMA traits
 // Each trait describes one 16x16 output tile instruction D = A(16xK) B(Kx16) + D.
 // Lane l of a wave holds A rows (l % 16), B columns (l % 16), and the k-slice
-// (l / 16) * KPL .. + KPL-1 of the current K step; the 4 accumulator values of
-// lane l are D rows 4*(l/16) + v, column l % 16.
+// (l / 16) * KPL .. + KPL-1 of the current K step.  Accumulator value v of lane l
+// is D[out_row(l / 16, v)][l % 16]: rows 4*(l/16) + v for the FP32-accumulating
+// instructions, rows (l/16) + 4*v for the FP64 one (checked on gfx950 by a
+// lane-layout probe of the builtins).
 template <typename TC> struct Mfma;
 
 template <> struct Mfma<double> {
@@ -78,6 +80,7 @@ template <> struct Mfma<double> {
   __device__ static inline acc mma(frag a, frag b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int out_row(int g, int v) { return g + 4 * v; }
   __device__ static inline elem from_f64(double x) { return x; }
   __device__ static inline elem zero() { return 0.0; }
 };
@@ -92,6 +95,7 @@ template <> struct Mfma<float> {
   __device__ static inline acc mma(frag a, frag b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int out_row(int g, int v) { return 4 * g + v; }
   __device__ static inline elem from_f64(double x) { return (float)x; }
   __device__ static inline elem zero() { return 0.0f; }
 };
@@ -108,6 +112,7 @@ template <> struct Mfma<bf16> {
   __device__ static inline acc mma(frag a, frag b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int out_row(int g, int v) { return 4 * g + v; }
   __device__ static inline elem from_f64(double x) { return float_to_bf16_bits((float)x); }
   __device__ static inline elem zero() { return 0; }
 };
@@ -213,7 +218,7 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
       }
     }
     // ---- accumulators -> global, rows j < n; lane holds column (lane & 15) of
-    // each 16-column tile ct and rows 16*wave + 4*(lane>>4) + v.
+    // each 16-column tile ct and rows row0 + 16*wave + out_row(lane>>4, v).
 #pragma unroll
     for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
       int64_t c = c0 + ct * 16 + (lane & 15);
@@ -229,7 +234,7 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int j = row0 + wave * 16 + (lane >> 4) * 4 + v;
+        int j = row0 + wave * 16 + MF::out_row(lane >> 4, v);
         if (j < n) {
           int64_t a = base + (int64_t)j * step;
           double y = (double)acc[ct][v];
