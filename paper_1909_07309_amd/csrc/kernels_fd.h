@@ -81,6 +81,8 @@ template <> struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   __device__ static inline int out_row(int g, int v) { return g + 4 * v; }
+  __device__ static inline frag make(const elem *v) { return v[0]; }
+  __device__ static inline double to_f64(elem x) { return x; }
   __device__ static inline elem from_f64(double x) { return x; }
   __device__ static inline elem zero() { return 0.0; }
 };
@@ -96,6 +98,8 @@ template <> struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static inline int out_row(int g, int v) { return 4 * g + v; }
+  __device__ static inline frag make(const elem *v) { return v[0]; }
+  __device__ static inline double to_f64(elem x) { return (double)x; }
   __device__ static inline elem from_f64(double x) { return (float)x; }
   __device__ static inline elem zero() { return 0.0f; }
 };
@@ -113,6 +117,15 @@ template <> struct Mfma<bf16> {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
   __device__ static inline int out_row(int g, int v) { return 4 * g + v; }
+  __device__ static inline frag make(const elem *v) {
+    frag r;
+    r[0] = (short)v[0];
+    r[1] = (short)v[1];
+    r[2] = (short)v[2];
+    r[3] = (short)v[3];
+    return r;
+  }
+  __device__ static inline double to_f64(elem x) { return (double)bf16_bits_to_float(x); }
   __device__ static inline elem from_f64(double x) { return float_to_bf16_bits((float)x); }
   __device__ static inline elem zero() { return 0; }
 };
@@ -246,6 +259,190 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
   }
 }
 
+// ------------------------------------------------ mode GEMM, small-n variant
+// Same contract as mode_gemm for n <= GEMM2_MAX_N (at most four 16-row MFMA
+// tiles plus a fringe of n % 16 rows):
+//  * block = 4 waves, persistent over column tiles (grid-stride);
+//  * wave w owns MFMA output rows 16w..16w+15 (w < n/16) and keeps its A
+//    operand (those rows of Op, all k) in registers for the whole kernel;
+//  * the fringe rows 16*(n/16) .. n-1 are computed on the vector ALU, four
+//    lanes per column splitting k, reduced with cross-lane shuffles;
+//  * the next column tile is prefetched into registers while the current one
+//    is multiplied, so HBM loads overlap MFMA work.
+// Dynamic LDS: GEMM_TILE_COLS * ld elements (the X tile only).
+constexpr int GEMM2_MAX_N = 79;
+constexpr int GEMM2_THREADS = 256;
+constexpr int GEMM2_MAXL = (GEMM_TILE_COLS * 80 + GEMM2_THREADS - 1) / GEMM2_THREADS;  // 20
+
+template <typename Tin, typename Tout, typename TC>
+__global__ void __launch_bounds__(GEMM2_THREADS)
+mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
+                const typename Mfma<TC>::elem *__restrict__ Op, int n, int64_t inner,
+                int64_t total_cols, const double *__restrict__ in_scale,
+                const double *__restrict__ out_scale, int64_t nscale) {
+  typedef Mfma<TC> MF;
+  typedef typename MF::elem E;
+  constexpr int KSMAX = (GEMM2_MAX_N + MF::KSTEP - 1) / MF::KSTEP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  E *tile = reinterpret_cast<E *>(smem);  // [GEMM_TILE_COLS][ld]
+  const int ld = lds_ld<TC>(n);
+  const int kpad = round_up(n, MF::KSTEP);
+  const int ksteps = kpad / MF::KSTEP;
+  const int q = n >> 4;           // MFMA row tiles
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ntiles = (total_cols + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
+  const int64_t slab = (int64_t)n * inner;
+  const uint32_t uinner = (uint32_t)inner;
+  const float rn = 1.0f / (float)n;
+
+  // zero the k padding once; tile loads only ever write k < n
+  for (int e = tid; e < GEMM_TILE_COLS * (kpad - n); e += GEMM2_THREADS) {
+    int col = e / (kpad - n), k = n + e % (kpad - n);
+    tile[(size_t)col * ld + k] = MF::zero();
+  }
+  // A operand of this wave's row tile, all k steps, kept in registers
+  typename MF::frag afr[KSMAX];
+  {
+    const int j = wave * 16 + (lane & 15);
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      E tmp[MF::KPL];
+#pragma unroll
+      for (int u = 0; u < MF::KPL; ++u) {
+        int k = s * MF::KSTEP + (lane >> 4) * MF::KPL + u;
+        tmp[u] = (wave < q && j < n && k < n && s < ksteps) ? Op[(size_t)j * n + k] : MF::zero();
+      }
+      afr[s] = MF::make(tmp);
+    }
+  }
+
+  // per-thread slice of a tile: element e -> (col, k)
+  auto load_tile = [&](int64_t c0, double (&reg)[GEMM2_MAXL]) {
+    if (inner == 1) {
+      const int64_t base = c0 * n;
+      const int64_t lim = (total_cols - c0) * n;  // valid flat elements in this tile
+#pragma unroll
+      for (int s = 0; s < GEMM2_MAXL; ++s) {
+        int e = tid + s * GEMM2_THREADS;
+        double x = 0.0;
+        if (e < GEMM_TILE_COLS * n && e < lim) {
+          int64_t a = base + e;
+          x = Conv<Tin>::to_f64(in[a]);
+          if (in_scale) x *= in_scale[a % nscale];
+        }
+        reg[s] = x;
+      }
+    } else {
+      const int col = tid & (GEMM_TILE_COLS - 1);
+      const int64_t c = c0 + col;
+      const bool valid = c < total_cols;
+      int64_t b = 0;
+      if (valid) {
+        uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
+        b = (int64_t)o * slab + i;
+      }
+#pragma unroll
+      for (int s = 0; s < GEMM2_MAXL; ++s) {
+        int k = (tid >> 6) + s * (GEMM2_THREADS / GEMM_TILE_COLS);
+        double x = 0.0;
+        if (valid && k < n) {
+          int64_t a = b + (int64_t)k * inner;
+          x = Conv<Tin>::to_f64(in[a]);
+          if (in_scale) x *= in_scale[a % nscale];
+        }
+        reg[s] = x;
+      }
+    }
+  };
+  auto store_tile = [&](const double (&reg)[GEMM2_MAXL]) {
+    if (inner == 1) {
+#pragma unroll
+      for (int s = 0; s < GEMM2_MAXL; ++s) {
+        int e = tid + s * GEMM2_THREADS;
+        if (e < GEMM_TILE_COLS * n) {
+          int col = (int)(((float)e + 0.5f) * rn);  // exact: e < 2^13, n <= 79
+          int k = e - col * n;
+          tile[(size_t)col * ld + k] = MF::from_f64(reg[s]);
+        }
+      }
+    } else {
+      const int col = tid & (GEMM_TILE_COLS - 1);
+#pragma unroll
+      for (int s = 0; s < GEMM2_MAXL; ++s) {
+        int k = (tid >> 6) + s * (GEMM2_THREADS / GEMM_TILE_COLS);
+        if (k < n) tile[(size_t)col * ld + k] = MF::from_f64(reg[s]);
+      }
+    }
+  };
+  auto out_addr = [&](int64_t c, int j) -> int64_t {
+    if (inner == 1) return c * n + j;
+    uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
+    return (int64_t)o * slab + (int64_t)j * inner + i;
+  };
+
+  double reg[GEMM2_MAXL];
+  int64_t t = blockIdx.x;
+  if (t < ntiles) load_tile(t * GEMM_TILE_COLS, reg);
+  for (; t < ntiles; t += gridDim.x) {
+    const int64_t c0 = t * GEMM_TILE_COLS;
+    __syncthreads();             // previous tile fully read
+    store_tile(reg);
+    __syncthreads();
+    if (t + gridDim.x < ntiles) load_tile((t + gridDim.x) * GEMM_TILE_COLS, reg);  // prefetch
+    // ---- MFMA rows
+    if (wave < q) {
+      typename MF::acc acc[GEMM_TILE_COLS / 16];
+#pragma unroll
+      for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct)
+        for (int v = 0; v < 4; ++v) acc[ct][v] = 0;
+      const E *bcol = tile + (size_t)(lane & 15) * ld + (lane >> 4) * MF::KPL;
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s) {
+        if (s < ksteps) {
+#pragma unroll
+          for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
+            typename MF::frag b = MF::load(bcol + (size_t)ct * 16 * ld + s * MF::KSTEP);
+            acc[ct] = MF::mma(afr[s], b, acc[ct]);
+          }
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
+        int64_t c = c0 + ct * 16 + (lane & 15);
+        if (c >= total_cols) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int j = wave * 16 + MF::out_row(lane >> 4, v);
+          int64_t a = out_addr(c, j);
+          double y = (double)acc[ct][v];
+          if (out_scale) y *= out_scale[a % nscale];
+          out[a] = Conv<Tout>::from_f64(y);
+        }
+      }
+    }
+    // ---- fringe rows on the vector ALU: wave w takes columns 16w..16w+15,
+    // lane -> (column lane & 15, k quarter lane >> 4)
+    for (int jr = q * 16; jr < n; ++jr) {
+      const int col = wave * 16 + (lane & 15);
+      const int kq = lane >> 4;
+      const int kb = (n * kq) >> 2, ke = (n * (kq + 1)) >> 2;
+      const E *xcol = tile + (size_t)col * ld;
+      double sum = 0.0;
+      for (int k = kb; k < ke; ++k)
+        sum += MF::to_f64(Op[(size_t)jr * n + k]) * MF::to_f64(xcol[k]);
+      sum += __shfl_xor(sum, 16, 64);
+      sum += __shfl_xor(sum, 32, 64);
+      int64_t c = c0 + col;
+      if (kq == 0 && c < total_cols) {
+        int64_t a = out_addr(c, jr);
+        double y = sum;
+        if (out_scale) y *= out_scale[a % nscale];
+        out[a] = Conv<Tout>::from_f64(y);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------- time solves
 // For each spatial eigen-index k (and right-hand side), solve
 //   (gamma W + nu lam_k M) q = r   along t (stride ns between consecutive t),
@@ -334,6 +531,160 @@ __global__ void time_band_solve(const Tio *__restrict__ in, Tio *__restrict__ ou
     for (int a = P - 1; a >= 1; --a) qn[a] = qn[a - 1];
     qn[0] = qi;
     q[(int64_t)i * ns] = Conv<Tio>::from_f64((double)qi);
+  }
+}
+
+
+// ----------------------------------------------- time solves, register form
+// Same systems as time_band_solve for a compile-time number of rows NT and
+// bandwidth P, with no scratch memory: each lane keeps its right-hand side /
+// forward-substituted values y_0..y_{NT-1} in registers and stores only a
+// checkpoint of the elimination state (the previous P rows of the U factor)
+// every C rows.  Back substitution walks the segments backwards, refactoring
+// each segment from its checkpoint (the same arithmetic in the same order, so
+// the U entries are bit-identical to the forward sweep) and substituting.
+// HBM traffic is the compulsory read of r and write of q.
+template <typename TC, int P> struct ElimState {
+  TC rp[P];          // rp[d-1] = 1 / u[i-d][i-d]
+  TC u[P][P];        // u[d-1][c] = u[i-d][i-d+c], c = 1 .. P-1 (index 0 unused)
+};
+
+// Factor row i given the state of rows i-P..i-1; returns the new row's U
+// entries (row[P] = pivot, row[P+c] = u[i][i+c]) and the multipliers l[dist-1].
+template <typename TC, int P>
+__device__ inline void factor_row(int i, const ElimState<TC, P> &st, const TC *__restrict__ wb,
+                                  const TC *__restrict__ mb, TC gamma, TC nul, TC (&row)[2 * P + 1],
+                                  TC (&l)[P]) {
+  constexpr int B = 2 * P + 1;
+#pragma unroll
+  for (int m = 0; m < B; ++m) row[m] = gamma * wb[i * B + m] + nul * mb[i * B + m];
+#pragma unroll
+  for (int dist = P; dist >= 1; --dist) {
+    l[dist - 1] = 0;
+    if (i - dist >= 0) {
+      const int j = i - dist;
+      TC lv = row[P - dist] * st.rp[dist - 1];
+      l[dist - 1] = lv;
+#pragma unroll
+      for (int c = 1; c < P; ++c) row[P - dist + c] -= lv * st.u[dist - 1][c];
+      // outermost superdiagonal of row j is the untouched matrix entry
+      TC ujP = gamma * wb[j * B + 2 * P] + nul * mb[j * B + 2 * P];
+      row[P - dist + P] -= lv * ujP;
+    }
+  }
+}
+
+template <typename TC, int P>
+__device__ inline void push_row(ElimState<TC, P> &st, const TC (&row)[2 * P + 1], TC rp) {
+#pragma unroll
+  for (int a = P - 1; a >= 1; --a) {
+    st.rp[a] = st.rp[a - 1];
+#pragma unroll
+    for (int c = 1; c < P; ++c) st.u[a][c] = st.u[a - 1][c];
+  }
+  st.rp[0] = rp;
+#pragma unroll
+  for (int c = 1; c < P; ++c) st.u[0][c] = row[P + c];
+}
+
+template <typename Tio, typename TC, int NT, int P, int C, bool YREG>
+__global__ void __launch_bounds__(256)
+time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const double *__restrict__ lam,
+                    const TC *__restrict__ wb, const TC *__restrict__ mb, TC gamma, TC nu, int64_t ns,
+                    int nrhs, TC *__restrict__ ysc, int *__restrict__ flag) {
+  // YREG: forward-substituted values stay in registers; otherwise they go to
+  // ysc ([rhs][t][k], compute type; may alias `out` when Tio == TC) and are
+  // read back in reverse order by the backward sweep.
+  constexpr int B = 2 * P + 1;
+  constexpr int NSEG = (NT + C - 1) / C;
+  constexpr int NY = YREG ? NT : 1;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ns * nrhs) return;
+  int64_t rhs = g / ns, k = g - rhs * ns;
+  const Tio *r = in + rhs * ns * NT + k;
+  Tio *q = out + rhs * ns * NT + k;
+  TC *ys = ysc + rhs * ns * NT + k;
+  const TC nul = nu * (TC)lam[k];
+  TC y[NY];
+  if (YREG) {
+#pragma unroll
+    for (int i = 0; i < NY; ++i) y[i] = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
+  }
+  TC yp[P];  // previous P forward-substituted values (YREG == false)
+#pragma unroll
+  for (int a = 0; a < P; ++a) yp[a] = 0;
+  ElimState<TC, P> st;
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    st.rp[a] = 0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) st.u[a][c] = 0;
+  }
+  ElimState<TC, P> ck[NSEG];
+  bool bad = false;
+  // forward sweep: factor and forward-substitute, checkpoint every C rows
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    if (i % C == 0) ck[i / C] = st;
+    TC row[B], l[P];
+    factor_row<TC, P>(i, st, wb, mb, gamma, nul, row, l);
+    if (YREG) {
+#pragma unroll
+      for (int dist = P; dist >= 1; --dist)
+        if (i - dist >= 0) y[i] -= l[dist - 1] * y[i - dist];
+    } else {
+      TC yi = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
+#pragma unroll
+      for (int dist = P; dist >= 1; --dist)
+        if (i - dist >= 0) yi -= l[dist - 1] * yp[dist - 1];
+#pragma unroll
+      for (int a = P - 1; a >= 1; --a) yp[a] = yp[a - 1];
+      yp[0] = yi;
+      ys[(int64_t)i * ns] = yi;
+    }
+    if (!(row[P] > (TC)0)) bad = true;
+    push_row<TC, P>(st, row, (TC)1 / row[P]);
+  }
+  if (bad) *flag = 1;
+  // backward sweep over segments.  nul and the band pointers pass through an
+  // empty asm so the compiler cannot reuse the forward sweep's rows (which
+  // would keep the whole U factor live); the recomputed values are bit-identical.
+  TC nul2 = nul;
+  asm volatile("" : "+v"(nul2));
+  const TC *wb2 = wb, *mb2 = mb;
+  asm volatile("" : "+s"(wb2), "+s"(mb2));
+  TC qn[P];  // qn[c-1] = q[i+c]
+#pragma unroll
+  for (int a = 0; a < P; ++a) qn[a] = 0;
+#pragma unroll
+  for (int sgi = NSEG - 1; sgi >= 0; --sgi) {
+    const int i0 = sgi * C;
+    const int i1 = (i0 + C < NT) ? i0 + C : NT;
+    TC su[C][P];   // su[i-i0][0] = 1/pivot, su[i-i0][c] = u[i][i+c] (c < P)
+    ElimState<TC, P> s2 = ck[sgi];
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      TC row[B], l[P];
+      factor_row<TC, P>(i, s2, wb2, mb2, gamma, nul2, row, l);
+      TC rp = (TC)1 / row[P];
+      su[i - i0][0] = rp;
+#pragma unroll
+      for (int c = 1; c < P; ++c) su[i - i0][c] = row[P + c];
+      push_row<TC, P>(s2, row, rp);
+    }
+#pragma unroll
+    for (int i = i1 - 1; i >= i0; --i) {
+      TC acc = YREG ? y[YREG ? i : 0] : ys[(int64_t)i * ns];
+#pragma unroll
+      for (int c = 1; c < P; ++c) acc -= su[i - i0][c] * qn[c - 1];
+      TC uP = gamma * wb2[i * B + 2 * P] + nul2 * mb2[i * B + 2 * P];
+      acc -= uP * qn[P - 1];
+      TC qi = acc * su[i - i0][0];
+#pragma unroll
+      for (int a = P - 1; a >= 1; --a) qn[a] = qn[a - 1];
+      qn[0] = qi;
+      q[(int64_t)i * ns] = Conv<Tio>::from_f64((double)qi);
+    }
   }
 }
 

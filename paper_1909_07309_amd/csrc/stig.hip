@@ -44,6 +44,7 @@ stig_status fail(stig_status s, const std::string &msg) {
 
 constexpr int MAX_P = 5;
 constexpr size_t GEMM_LDS_LIMIT = 160 * 1024;
+constexpr int64_t GEMM2_GRID = 1024;  // persistent blocks of the small-n GEMM
 
 struct DevBuf {
   void *p = nullptr;
@@ -226,6 +227,17 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
                              const double *out_scale) {
   typedef typename Mfma<TC>::elem E;
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
+  if (n <= GEMM2_MAX_N) {
+    const int ld = lds_ld<TC>(n);
+    size_t lds = (size_t)GEMM_TILE_COLS * ld * sizeof(E);
+    int64_t ntiles = (total_cols + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
+    unsigned grid = (unsigned)std::min<int64_t>(ntiles, GEMM2_GRID);
+    ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
+    hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC>), dim3(grid), dim3(GEMM2_THREADS), lds,
+                       p->stream, in, out, op, n, inner, total_cols, in_scale, out_scale, p->N);
+    HIP_TRY(hipGetLastError());
+    return STIG_OK;
+  }
   const int jt = (n + 15) / 16;
   const int ld = lds_ld<TC>(n);
   // as many 16-row output tiles per block as fit in LDS (all of them when possible,
@@ -271,8 +283,42 @@ stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int t
   return STIG_OK;
 }
 
+template <typename Tio, typename TC, int NT, int P, int C>
+stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  // FP64 keeps the forward-substituted values in the output buffer (registers
+  // would spill); FP32 keeps them in registers.
+  constexpr bool YREG = !std::is_same<TC, double>::value;
+  TC *ysc = nullptr;
+  if (!YREG) {
+    if (std::is_same<Tio, TC>::value) ysc = (TC *)out;
+    else {
+      STIG_TRY(p->tscr.ensure((size_t)p->N * nrhs * sizeof(TC)));
+      ysc = p->tscr.as<TC>();
+    }
+  }
+  const TC *wb, *mb;
+  if (std::is_same<TC, double>::value) {
+    wb = (const TC *)(transpose ? p->tWT64.p : p->tW64.p);
+    mb = (const TC *)p->tM64.p;
+  } else {
+    wb = (const TC *)(transpose ? p->tWT32.p : p->tW32.p);
+    mb = (const TC *)p->tM32.p;
+  }
+  int64_t work = p->Ns * nrhs;
+  ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
+  hipLaunchKernelGGL((time_band_solve_reg<Tio, TC, NT, P, C, YREG>), dim3(grid_for(work, 256)),
+                     dim3(256), 0, p->stream, in, out, p->lam.as<double>(), wb, mb, (TC)p->gamma,
+                     (TC)p->nu, p->Ns, nrhs, ysc, p->flag.as<int>());
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
 template <typename Tio, typename TC>
 stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
+  if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 14>(p, in, out, nrhs, transpose);
+  if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 12>(p, in, out, nrhs, transpose);
+  if (p->nt == 9 && p->pt == 2) return launch_time_reg<Tio, TC, 9, 2, 3>(p, in, out, nrhs, transpose);
   STIG_TRY(p->tscr.ensure((size_t)(p->pt + 1) * p->N * nrhs * sizeof(TC)));
   switch (p->pt) {
     case 1: return launch_time_p<Tio, TC, 1>(p, in, out, nrhs, transpose);

@@ -33,7 +33,8 @@ def _setup(name, n_el, **kw):
 
 # sizes span one and several 16-row MFMA tiles, 64-column tiles and ragged tails
 SHAPES = [("square_p2_n8", None), ("square_p2_n8", 17), ("cube_p3_n64", 5),
-          ("cube_p3_n64", 14), ("cube_p3_n64", 31), ("annulus_p4_n128", 20)]
+          ("cube_p3_n64", 14), ("cube_p3_n64", 31), ("cube_p3_n64", 48), ("annulus_p4_n128", 20),
+          ("annulus_p4_n128", 90)]
 
 
 @pytest.mark.parametrize("name,n_el", SHAPES)
