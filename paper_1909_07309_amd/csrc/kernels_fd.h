@@ -132,6 +132,12 @@ template <> struct Mfma<bf16> {
 
 __host__ __device__ constexpr inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
+// Read-only coefficient tables (band rows, shifts) are read through the constant
+// address space: uniform indices then compile to scalar loads instead of vector
+// loads that the kernel would have to wait on row by row.
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ inline cptr<T> as_const(const T *p) { return (cptr<T>)p; }
+
 // Leading dimension (in elements) of an LDS tile holding k = 0 .. kpad-1 per
 // column, padded so consecutive columns start in different LDS banks.
 template <typename TC> __host__ __device__ inline int lds_ld(int n) {
@@ -184,14 +190,11 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
       for (int e = tid; e < GEMM_TILE_COLS * kpad; e += nthr) {
         int col = e / kpad, k = e - col * kpad;
         int64_t c = c0 + col;
-        E v = MF::zero();
-        if (c < total_cols && k < n) {
-          int64_t a = c * n + k;
-          double x = Conv<Tin>::to_f64(in[a]);
-          if (in_scale) x *= in_scale[a % nscale];
-          v = MF::from_f64(x);
-        }
-        tile[(size_t)col * ld + k] = v;
+        bool ok = c < total_cols && k < n;
+        int64_t a = ok ? c * n + k : 0;
+        double x = Conv<Tin>::to_f64(in[a]);
+        if (in_scale) x *= in_scale[a % nscale];
+        tile[(size_t)col * ld + k] = ok ? MF::from_f64(x) : MF::zero();
       }
     } else {
       // nthr is a multiple of 64, so each thread always touches the same column
@@ -204,14 +207,11 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
         base = (int64_t)o * slab + i;
       }
       for (int k = tid / GEMM_TILE_COLS; k < kpad; k += nthr / GEMM_TILE_COLS) {
-        E v = MF::zero();
-        if (valid && k < n) {
-          int64_t a = base + (int64_t)k * inner;
-          double x = Conv<Tin>::to_f64(in[a]);
-          if (in_scale) x *= in_scale[a % nscale];
-          v = MF::from_f64(x);
-        }
-        tile[(size_t)col * ld + k] = v;
+        bool ok = valid && k < n;
+        int64_t a = ok ? base + (int64_t)k * inner : 0;
+        double x = Conv<Tin>::to_f64(in[a]);
+        if (in_scale) x *= in_scale[a % nscale];
+        tile[(size_t)col * ld + k] = ok ? MF::from_f64(x) : MF::zero();
       }
     }
     __syncthreads();
@@ -259,186 +259,126 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
   }
 }
 
-// ------------------------------------------------ mode GEMM, small-n variant
-// Same contract as mode_gemm for n <= GEMM2_MAX_N (at most four 16-row MFMA
-// tiles plus a fringe of n % 16 rows):
-//  * block = 4 waves, persistent over column tiles (grid-stride);
-//  * wave w owns MFMA output rows 16w..16w+15 (w < n/16) and keeps its A
-//    operand (those rows of Op, all k) in registers for the whole kernel;
-//  * the fringe rows 16*(n/16) .. n-1 are computed on the vector ALU, four
-//    lanes per column splitting k, reduced with cross-lane shuffles;
-//  * the next column tile is prefetched into registers while the current one
-//    is multiplied, so HBM loads overlap MFMA work.
-// Dynamic LDS: GEMM_TILE_COLS * ld elements (the X tile only).
+// ------------------------------------------------ mode GEMM, streaming form
+// Same contract as mode_gemm, for n <= GEMM2_MAX_N.  No tile staging and no
+// block barriers in the main loop: every wave streams its own 16-column strips.
+//  * Op (n x n, zero padded to kpad columns) is copied to LDS once per block;
+//  * a wave loads the B operand X[k][c0..c0+15] for all k straight from global
+//    memory in the MFMA operand layout (lane: column lane & 15, k-slice lane >> 4),
+//    multiplies it by the n/16 full 16-row tiles of Op (A operand from LDS),
+//  * and computes the n % 16 fringe rows on the vector ALU from the same B
+//    registers, reduced across the four k-slices with cross-lane shuffles.
+// Latency is hidden by occupancy (many independent waves per SIMD).
+// Dynamic LDS: 16 * ceil(n/16) * ld elements.
 constexpr int GEMM2_MAX_N = 79;
 constexpr int GEMM2_THREADS = 256;
-constexpr int GEMM2_MAXL = (GEMM_TILE_COLS * 80 + GEMM2_THREADS - 1) / GEMM2_THREADS;  // 20
 
-template <typename Tin, typename Tout, typename TC>
+// NC = n as a compile-time constant (0: n taken from the argument).  With NC
+// fixed, the MFMA chain has no runtime guards, so the accumulators stay in
+// place instead of being copied at every branch.
+template <typename Tin, typename Tout, typename TC, int NC>
 __global__ void __launch_bounds__(GEMM2_THREADS)
 mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
-                const typename Mfma<TC>::elem *__restrict__ Op, int n, int64_t inner,
-                int64_t total_cols, const double *__restrict__ in_scale,
-                const double *__restrict__ out_scale, int64_t nscale) {
+                const typename Mfma<TC>::elem *__restrict__ Op, int n_arg, int64_t inner,
+                int64_t total_cols) {
   typedef Mfma<TC> MF;
   typedef typename MF::elem E;
-  constexpr int KSMAX = (GEMM2_MAX_N + MF::KSTEP - 1) / MF::KSTEP;
+  constexpr int NMAX = NC ? NC : GEMM2_MAX_N;
+  constexpr int KSMAX = (NMAX + MF::KSTEP - 1) / MF::KSTEP;
+  constexpr int QMAX = NMAX / 16;
+  const int n = NC ? NC : n_arg;
   extern __shared__ __align__(16) unsigned char smem[];
-  E *tile = reinterpret_cast<E *>(smem);  // [GEMM_TILE_COLS][ld]
   const int ld = lds_ld<TC>(n);
+  E *opl = reinterpret_cast<E *>(smem);  // [16*ceil(n/16)][ld]
   const int kpad = round_up(n, MF::KSTEP);
   const int ksteps = kpad / MF::KSTEP;
-  const int q = n >> 4;           // MFMA row tiles
+  const int q = n >> 4;
+  const int nrows = round_up(n, 16);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t ntiles = (total_cols + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
+  for (int e = tid; e < nrows * kpad; e += GEMM2_THREADS) {
+    int j = e / kpad, k = e - j * kpad;
+    bool ok = j < n && k < n;
+    E v = Op[ok ? (size_t)j * n + k : 0];
+    opl[(size_t)j * ld + k] = ok ? v : MF::zero();
+  }
+  __syncthreads();
+
+  const int64_t nstrips = (total_cols + 15) >> 4;
   const int64_t slab = (int64_t)n * inner;
   const uint32_t uinner = (uint32_t)inner;
-  const float rn = 1.0f / (float)n;
-
-  // zero the k padding once; tile loads only ever write k < n
-  for (int e = tid; e < GEMM_TILE_COLS * (kpad - n); e += GEMM2_THREADS) {
-    int col = e / (kpad - n), k = n + e % (kpad - n);
-    tile[(size_t)col * ld + k] = MF::zero();
-  }
-  // A operand of this wave's row tile, all k steps, kept in registers
-  typename MF::frag afr[KSMAX];
-  {
-    const int j = wave * 16 + (lane & 15);
+  const int col = lane & 15, kg = lane >> 4;
+  const int64_t wstride = (int64_t)gridDim.x * (GEMM2_THREADS / 64);
+  for (int64_t strip = (int64_t)blockIdx.x * (GEMM2_THREADS / 64) + wave; strip < nstrips;
+       strip += wstride) {
+    const int64_t c = strip * 16 + col;
+    const bool cvalid = c < total_cols;
+    int64_t base, step;
+    if (inner == 1) {
+      base = c * n;
+      step = 1;
+    } else {
+      uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
+      base = (int64_t)o * slab + i;
+      step = inner;
+    }
+    // ---- B operand for all k steps (branch-free loads)
+    E bv[KSMAX][MF::KPL];
 #pragma unroll
-    for (int s = 0; s < KSMAX; ++s) {
-      E tmp[MF::KPL];
+    for (int s = 0; s < KSMAX; ++s)
 #pragma unroll
       for (int u = 0; u < MF::KPL; ++u) {
-        int k = s * MF::KSTEP + (lane >> 4) * MF::KPL + u;
-        tmp[u] = (wave < q && j < n && k < n && s < ksteps) ? Op[(size_t)j * n + k] : MF::zero();
+        int k = s * MF::KSTEP + kg * MF::KPL + u;
+        bool ok = cvalid && k < n;
+        int64_t a = ok ? base + (int64_t)k * step : 0;
+        double x = Conv<Tin>::to_f64(in[a]);
+        bv[s][u] = ok ? MF::from_f64(x) : MF::zero();
       }
-      afr[s] = MF::make(tmp);
-    }
-  }
-
-  // per-thread slice of a tile: element e -> (col, k)
-  auto load_tile = [&](int64_t c0, double (&reg)[GEMM2_MAXL]) {
-    if (inner == 1) {
-      const int64_t base = c0 * n;
-      const int64_t lim = (total_cols - c0) * n;  // valid flat elements in this tile
+    // ---- full 16-row tiles on MFMA
+    typename MF::acc acc[QMAX];
 #pragma unroll
-      for (int s = 0; s < GEMM2_MAXL; ++s) {
-        int e = tid + s * GEMM2_THREADS;
-        double x = 0.0;
-        if (e < GEMM_TILE_COLS * n && e < lim) {
-          int64_t a = base + e;
-          x = Conv<Tin>::to_f64(in[a]);
-          if (in_scale) x *= in_scale[a % nscale];
-        }
-        reg[s] = x;
-      }
-    } else {
-      const int col = tid & (GEMM_TILE_COLS - 1);
-      const int64_t c = c0 + col;
-      const bool valid = c < total_cols;
-      int64_t b = 0;
-      if (valid) {
-        uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
-        b = (int64_t)o * slab + i;
-      }
+    for (int t = 0; t < QMAX; ++t)
+      for (int v = 0; v < 4; ++v) acc[t][v] = 0;
 #pragma unroll
-      for (int s = 0; s < GEMM2_MAXL; ++s) {
-        int k = (tid >> 6) + s * (GEMM2_THREADS / GEMM_TILE_COLS);
-        double x = 0.0;
-        if (valid && k < n) {
-          int64_t a = b + (int64_t)k * inner;
-          x = Conv<Tin>::to_f64(in[a]);
-          if (in_scale) x *= in_scale[a % nscale];
-        }
-        reg[s] = x;
-      }
-    }
-  };
-  auto store_tile = [&](const double (&reg)[GEMM2_MAXL]) {
-    if (inner == 1) {
+    for (int s = 0; s < KSMAX; ++s) {
+      if (s < ksteps) {
+        typename MF::frag b = MF::make(bv[s]);
 #pragma unroll
-      for (int s = 0; s < GEMM2_MAXL; ++s) {
-        int e = tid + s * GEMM2_THREADS;
-        if (e < GEMM_TILE_COLS * n) {
-          int col = (int)(((float)e + 0.5f) * rn);  // exact: e < 2^13, n <= 79
-          int k = e - col * n;
-          tile[(size_t)col * ld + k] = MF::from_f64(reg[s]);
-        }
-      }
-    } else {
-      const int col = tid & (GEMM_TILE_COLS - 1);
-#pragma unroll
-      for (int s = 0; s < GEMM2_MAXL; ++s) {
-        int k = (tid >> 6) + s * (GEMM2_THREADS / GEMM_TILE_COLS);
-        if (k < n) tile[(size_t)col * ld + k] = MF::from_f64(reg[s]);
-      }
-    }
-  };
-  auto out_addr = [&](int64_t c, int j) -> int64_t {
-    if (inner == 1) return c * n + j;
-    uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
-    return (int64_t)o * slab + (int64_t)j * inner + i;
-  };
-
-  double reg[GEMM2_MAXL];
-  int64_t t = blockIdx.x;
-  if (t < ntiles) load_tile(t * GEMM_TILE_COLS, reg);
-  for (; t < ntiles; t += gridDim.x) {
-    const int64_t c0 = t * GEMM_TILE_COLS;
-    __syncthreads();             // previous tile fully read
-    store_tile(reg);
-    __syncthreads();
-    if (t + gridDim.x < ntiles) load_tile((t + gridDim.x) * GEMM_TILE_COLS, reg);  // prefetch
-    // ---- MFMA rows
-    if (wave < q) {
-      typename MF::acc acc[GEMM_TILE_COLS / 16];
-#pragma unroll
-      for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct)
-        for (int v = 0; v < 4; ++v) acc[ct][v] = 0;
-      const E *bcol = tile + (size_t)(lane & 15) * ld + (lane >> 4) * MF::KPL;
-#pragma unroll
-      for (int s = 0; s < KSMAX; ++s) {
-        if (s < ksteps) {
-#pragma unroll
-          for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
-            typename MF::frag b = MF::load(bcol + (size_t)ct * 16 * ld + s * MF::KSTEP);
-            acc[ct] = MF::mma(afr[s], b, acc[ct]);
+        for (int t = 0; t < QMAX; ++t)
+          if (t < q) {
+            typename MF::frag a =
+                MF::load(opl + (size_t)(16 * t + col) * ld + s * MF::KSTEP + kg * MF::KPL);
+            acc[t] = MF::mma(a, b, acc[t]);
           }
-        }
       }
+      // keep each k step's A reads next to their MFMAs (otherwise the scheduler
+      // hoists every LDS read of the loop and the register count quadruples)
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
-      for (int ct = 0; ct < GEMM_TILE_COLS / 16; ++ct) {
-        int64_t c = c0 + ct * 16 + (lane & 15);
-        if (c >= total_cols) continue;
+    for (int t = 0; t < QMAX; ++t) {
+      if (t < q && cvalid) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          int j = wave * 16 + MF::out_row(lane >> 4, v);
-          int64_t a = out_addr(c, j);
-          double y = (double)acc[ct][v];
-          if (out_scale) y *= out_scale[a % nscale];
-          out[a] = Conv<Tout>::from_f64(y);
+          int j = 16 * t + MF::out_row(kg, v);
+          int64_t a = base + (int64_t)j * step;
+          out[a] = Conv<Tout>::from_f64((double)acc[t][v]);
         }
       }
     }
-    // ---- fringe rows on the vector ALU: wave w takes columns 16w..16w+15,
-    // lane -> (column lane & 15, k quarter lane >> 4)
-    for (int jr = q * 16; jr < n; ++jr) {
-      const int col = wave * 16 + (lane & 15);
-      const int kq = lane >> 4;
-      const int kb = (n * kq) >> 2, ke = (n * (kq + 1)) >> 2;
-      const E *xcol = tile + (size_t)col * ld;
+    // ---- fringe rows on the vector ALU from the B registers
+    for (int jr = 16 * q; jr < n; ++jr) {
+      const E *orow = opl + (size_t)jr * ld + kg * MF::KPL;
       double sum = 0.0;
-      for (int k = kb; k < ke; ++k)
-        sum += MF::to_f64(Op[(size_t)jr * n + k]) * MF::to_f64(xcol[k]);
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s)
+        if (s < ksteps) {
+#pragma unroll
+          for (int u = 0; u < MF::KPL; ++u)
+            sum += MF::to_f64(orow[s * MF::KSTEP + u]) * MF::to_f64(bv[s][u]);
+        }
       sum += __shfl_xor(sum, 16, 64);
       sum += __shfl_xor(sum, 32, 64);
-      int64_t c = c0 + col;
-      if (kq == 0 && c < total_cols) {
-        int64_t a = out_addr(c, jr);
-        double y = sum;
-        if (out_scale) y *= out_scale[a % nscale];
-        out[a] = Conv<Tout>::from_f64(y);
-      }
+      if (kg == 0 && cvalid) out[base + (int64_t)jr * step] = Conv<Tout>::from_f64(sum);
     }
   }
 }
@@ -466,6 +406,7 @@ __global__ void time_band_solve(const Tio *__restrict__ in, Tio *__restrict__ ou
   Tio *q = out + rhs * ns * nt + k;
   TC *sc = scratch + rhs * ns * nt * (P + 1) + k;
   const TC lk = (TC)lam[k];
+  cptr<TC> wbc = as_const(wb), mbc = as_const(mb);
   // rolling state of the previous P rows: U entries (c = 1..P), reciprocal pivot, y
   TC pu[P][P + 1];   // pu[dist-1][c] = u[i-dist][i-dist+c], c = 1..P (index 0 unused)
   TC prp[P], py[P];
@@ -480,7 +421,7 @@ __global__ void time_band_solve(const Tio *__restrict__ in, Tio *__restrict__ ou
   for (int i = 0; i < nt; ++i) {
     TC row[B];
 #pragma unroll
-    for (int m = 0; m < B; ++m) row[m] = gamma * wb[i * B + m] + nu * lk * mb[i * B + m];
+    for (int m = 0; m < B; ++m) row[m] = gamma * wbc[i * B + m] + nu * lk * mbc[i * B + m];
     TC y = Conv<Tio>::to_f64(r[(int64_t)i * ns]);
     // eliminate with rows j = i-P .. i-1 (increasing j): dist = P .. 1
 #pragma unroll
@@ -524,7 +465,7 @@ __global__ void time_band_solve(const Tio *__restrict__ in, Tio *__restrict__ ou
 #pragma unroll
     for (int c = 1; c < P; ++c) acc -= s[(int64_t)(c - 1) * ns] * qn[c - 1];
     // outermost superdiagonal: untouched entry
-    TC uP = gamma * wb[i * B + 2 * P] + nu * lk * mb[i * B + 2 * P];
+    TC uP = gamma * wbc[i * B + 2 * P] + nu * lk * mbc[i * B + 2 * P];
     acc -= uP * qn[P - 1];
     TC qi = acc * s[(int64_t)(P - 1) * ns];
 #pragma unroll
@@ -552,9 +493,8 @@ template <typename TC, int P> struct ElimState {
 // Factor row i given the state of rows i-P..i-1; returns the new row's U
 // entries (row[P] = pivot, row[P+c] = u[i][i+c]) and the multipliers l[dist-1].
 template <typename TC, int P>
-__device__ inline void factor_row(int i, const ElimState<TC, P> &st, const TC *__restrict__ wb,
-                                  const TC *__restrict__ mb, TC gamma, TC nul, TC (&row)[2 * P + 1],
-                                  TC (&l)[P]) {
+__device__ inline void factor_row(int i, const ElimState<TC, P> &st, cptr<TC> wb, cptr<TC> mb,
+                                  TC gamma, TC nul, TC (&row)[2 * P + 1], TC (&l)[P]) {
   constexpr int B = 2 * P + 1;
 #pragma unroll
   for (int m = 0; m < B; ++m) row[m] = gamma * wb[i * B + m] + nul * mb[i * B + m];
@@ -605,10 +545,19 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   Tio *q = out + rhs * ns * NT + k;
   TC *ys = ysc + rhs * ns * NT + k;
   const TC nul = nu * (TC)lam[k];
+  cptr<TC> wbc = as_const(wb), mbc = as_const(mb);
   TC y[NY];
   if (YREG) {
 #pragma unroll
     for (int i = 0; i < NY; ++i) y[i] = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
+  }
+  // YREG == false: all right-hand-side loads are issued up front into rr, which
+  // the forward sweep consumes (its registers free up as the checkpoints grow)
+  constexpr int NR = YREG ? 1 : NT;
+  TC rr[NR];
+  if (!YREG) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) rr[i] = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
   }
   TC yp[P];  // previous P forward-substituted values (YREG == false)
 #pragma unroll
@@ -627,13 +576,13 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   for (int i = 0; i < NT; ++i) {
     if (i % C == 0) ck[i / C] = st;
     TC row[B], l[P];
-    factor_row<TC, P>(i, st, wb, mb, gamma, nul, row, l);
+    factor_row<TC, P>(i, st, wbc, mbc, gamma, nul, row, l);
     if (YREG) {
 #pragma unroll
       for (int dist = P; dist >= 1; --dist)
         if (i - dist >= 0) y[i] -= l[dist - 1] * y[i - dist];
     } else {
-      TC yi = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
+      TC yi = rr[YREG ? 0 : i];
 #pragma unroll
       for (int dist = P; dist >= 1; --dist)
         if (i - dist >= 0) yi -= l[dist - 1] * yp[dist - 1];
@@ -651,8 +600,9 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   // would keep the whole U factor live); the recomputed values are bit-identical.
   TC nul2 = nul;
   asm volatile("" : "+v"(nul2));
-  const TC *wb2 = wb, *mb2 = mb;
-  asm volatile("" : "+s"(wb2), "+s"(mb2));
+  const TC *wb2p = wb, *mb2p = mb;
+  asm volatile("" : "+s"(wb2p), "+s"(mb2p));
+  cptr<TC> wb2 = as_const(wb2p), mb2 = as_const(mb2p);
   TC qn[P];  // qn[c-1] = q[i+c]
 #pragma unroll
   for (int a = 0; a < P; ++a) qn[a] = 0;
@@ -661,6 +611,11 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
     const int i0 = sgi * C;
     const int i1 = (i0 + C < NT) ? i0 + C : NT;
     TC su[C][P];   // su[i-i0][0] = 1/pivot, su[i-i0][c] = u[i][i+c] (c < P)
+    TC yseg[YREG ? 1 : C];
+    if (!YREG) {  // prefetch this segment's forward-substituted values
+#pragma unroll
+      for (int i = i0; i < i1; ++i) yseg[YREG ? 0 : i - i0] = ys[(int64_t)i * ns];
+    }
     ElimState<TC, P> s2 = ck[sgi];
 #pragma unroll
     for (int i = i0; i < i1; ++i) {
@@ -674,7 +629,7 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
     }
 #pragma unroll
     for (int i = i1 - 1; i >= i0; --i) {
-      TC acc = YREG ? y[YREG ? i : 0] : ys[(int64_t)i * ns];
+      TC acc = YREG ? y[YREG ? i : 0] : yseg[YREG ? 0 : i - i0];
 #pragma unroll
       for (int c = 1; c < P; ++c) acc -= su[i - i0][c] * qn[c - 1];
       TC uP = gamma * wb2[i * B + 2 * P] + nul2 * mb2[i * B + 2 * P];

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels_fd.h"
+
 namespace stig {
 
 // Axis with inner stride > 1: one thread per column (o, i), sliding a register
@@ -38,10 +40,11 @@ __global__ void band_pass_strided(const double *__restrict__ in1, const double *
     w1[m] = (j >= 0 && j < n) ? in1[base + (int64_t)j * inner] : 0.0;
     w2[m] = (in2 && j >= 0 && j < n) ? in2[base + (int64_t)j * inner] : 0.0;
   }
+  cptr<double> cBa = as_const(Ba), cBb = as_const(Bb), cBc = as_const(Bc);
   for (int j = 0; j < n; ++j) {
-    const double *ra = Ba ? Ba + (size_t)j * B : nullptr;
-    const double *rb = Bb ? Bb + (size_t)j * B : nullptr;
-    const double *rc = Bc ? Bc + (size_t)j * B : nullptr;
+    cptr<double> ra = cBa + (size_t)j * B;
+    cptr<double> rb = cBb + (size_t)j * B;
+    cptr<double> rc = cBc + (size_t)j * B;
     int64_t a = base + (int64_t)j * inner;
     if (out1) {
       double s = 0.0;

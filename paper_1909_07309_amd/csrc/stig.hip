@@ -227,14 +227,22 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
                              const double *out_scale) {
   typedef typename Mfma<TC>::elem E;
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
-  if (n <= GEMM2_MAX_N) {
+  if (n <= GEMM2_MAX_N && !in_scale && !out_scale) {
     const int ld = lds_ld<TC>(n);
-    size_t lds = (size_t)GEMM_TILE_COLS * ld * sizeof(E);
-    int64_t ntiles = (total_cols + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS;
-    unsigned grid = (unsigned)std::min<int64_t>(ntiles, GEMM2_GRID);
+    size_t lds = (size_t)round_up(n, 16) * ld * sizeof(E);
+    int64_t nstrips = (total_cols + 15) / 16;
+    unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID);
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
-    hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC>), dim3(grid), dim3(GEMM2_THREADS), lds,
-                       p->stream, in, out, op, n, inner, total_cols, in_scale, out_scale, p->N);
+    // compile-time sizes of the workloads' spatial directions, runtime n otherwise
+    if (n == 65)
+      hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC, 65>), dim3(grid), dim3(GEMM2_THREADS), lds,
+                         p->stream, in, out, op, n, inner, total_cols);
+    else if (n == 49)
+      hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC, 49>), dim3(grid), dim3(GEMM2_THREADS), lds,
+                         p->stream, in, out, op, n, inner, total_cols);
+    else
+      hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC, 0>), dim3(grid), dim3(GEMM2_THREADS), lds,
+                         p->stream, in, out, op, n, inner, total_cols);
     HIP_TRY(hipGetLastError());
     return STIG_OK;
   }
