@@ -26,13 +26,16 @@ struct bf16 {
   uint16_t bits;
 };
 
+// Round to nearest even; NaN stays NaN (quiet bit forced), +-Inf stays Inf.
+// Branch-free so that conversions do not split the surrounding load batches.
 __device__ __host__ inline uint16_t float_to_bf16_bits(float f) {
   union { float f; uint32_t u; } v;
   v.f = f;
   uint32_t u = v.u;
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
+  uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  uint32_t special = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  bool nonfinite = (u & 0x7f800000u) == 0x7f800000u;
+  return (uint16_t)(nonfinite ? special : rounded);
 }
 __device__ __host__ inline float bf16_bits_to_float(uint16_t b) {
   union { float f; uint32_t u; } v;
@@ -288,15 +291,15 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   constexpr int QMAX = NMAX / 16;
   const int n = NC ? NC : n_arg;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ld = lds_ld<TC>(n);
-  E *opl = reinterpret_cast<E *>(smem);  // [16*ceil(n/16)][ld]
-  const int kpad = round_up(n, MF::KSTEP);
-  const int ksteps = kpad / MF::KSTEP;
-  const int q = n >> 4;
-  const int nrows = round_up(n, 16);
+  // Op tile in LDS, sized for NMAX (the runtime-n variant reads the full NMAX
+  // range unguarded; every entry with j >= n or k >= n is zero)
+  constexpr int NROWS = (NMAX + 15) / 16 * 16;
+  constexpr int KPADM = KSMAX * MF::KSTEP;
+  const int ld = lds_ld<TC>(NMAX);
+  E *opl = reinterpret_cast<E *>(smem);  // [NROWS][ld]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < nrows * kpad; e += GEMM2_THREADS) {
-    int j = e / kpad, k = e - j * kpad;
+  for (int e = tid; e < NROWS * KPADM; e += GEMM2_THREADS) {
+    int j = e / KPADM, k = e - j * KPADM;
     bool ok = j < n && k < n;
     E v = Op[ok ? (size_t)j * n + k : 0];
     opl[(size_t)j * ld + k] = ok ? v : MF::zero();
@@ -308,11 +311,8 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   const uint32_t uinner = (uint32_t)inner;
   const int col = lane & 15, kg = lane >> 4;
   const int64_t wstride = (int64_t)gridDim.x * (GEMM2_THREADS / 64);
-  for (int64_t strip = (int64_t)blockIdx.x * (GEMM2_THREADS / 64) + wave; strip < nstrips;
-       strip += wstride) {
-    const int64_t c = strip * 16 + col;
-    const bool cvalid = c < total_cols;
-    int64_t base, step;
+  // column c -> (base address, stride along the contracted axis)
+  auto locate = [&](int64_t c, int64_t &base, int64_t &step) {
     if (inner == 1) {
       base = c * n;
       step = 1;
@@ -321,8 +321,13 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       base = (int64_t)o * slab + i;
       step = inner;
     }
-    // ---- B operand for all k steps (branch-free loads)
-    E bv[KSMAX][MF::KPL];
+  };
+  // B operand of one strip for all k steps (branch-free loads)
+  auto load_b = [&](int64_t strip, E (&bv)[KSMAX][MF::KPL]) {
+    const int64_t c = strip * 16 + col;
+    const bool cvalid = strip < nstrips && c < total_cols;
+    int64_t base, step;
+    locate(cvalid ? c : 0, base, step);
 #pragma unroll
     for (int s = 0; s < KSMAX; ++s)
 #pragma unroll
@@ -333,53 +338,75 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
         double x = Conv<Tin>::to_f64(in[a]);
         bv[s][u] = ok ? MF::from_f64(x) : MF::zero();
       }
-    // ---- full 16-row tiles on MFMA
+  };
+  // Process one strip whose B operand is already in registers: full row tiles
+  // on MFMA (the Op fragments of k step s+1 are read from LDS while the MFMAs of
+  // step s run), then the fringe rows on the vector ALU, then the stores.
+  auto process = [&](int64_t strip, const E (&bv)[KSMAX][MF::KPL]) {
+    const int64_t c = strip * 16 + col;
+    const bool cvalid = c < total_cols;
+    int64_t base, step;
+    locate(cvalid ? c : 0, base, step);
     typename MF::acc acc[QMAX];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
       for (int v = 0; v < 4; ++v) acc[t][v] = 0;
+    const E *abase = opl + (size_t)col * ld + kg * MF::KPL;
+    typename MF::frag acur[QMAX], anext[QMAX];
+#pragma unroll
+    for (int t = 0; t < QMAX; ++t) anext[t] = MF::load(abase + (size_t)16 * t * ld);
 #pragma unroll
     for (int s = 0; s < KSMAX; ++s) {
-      if (s < ksteps) {
-        typename MF::frag b = MF::make(bv[s]);
+#pragma unroll
+      for (int t = 0; t < QMAX; ++t) acur[t] = anext[t];
+      if (s + 1 < KSMAX) {
 #pragma unroll
         for (int t = 0; t < QMAX; ++t)
-          if (t < q) {
-            typename MF::frag a =
-                MF::load(opl + (size_t)(16 * t + col) * ld + s * MF::KSTEP + kg * MF::KPL);
-            acc[t] = MF::mma(a, b, acc[t]);
-          }
+          anext[t] = MF::load(abase + (size_t)16 * t * ld + (s + 1) * MF::KSTEP);
       }
-      // keep each k step's A reads next to their MFMAs (otherwise the scheduler
-      // hoists every LDS read of the loop and the register count quadruples)
+      typename MF::frag b = MF::make(bv[s]);
+#pragma unroll
+      for (int t = 0; t < QMAX; ++t) acc[t] = MF::mma(acur[t], b, acc[t]);
+      // one k step of lookahead only: without this fence the scheduler hoists
+      // every LDS read of the loop and the register count quadruples
       __builtin_amdgcn_sched_barrier(0);
     }
+    if (cvalid) {
 #pragma unroll
-    for (int t = 0; t < QMAX; ++t) {
-      if (t < q && cvalid) {
+      for (int t = 0; t < QMAX; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           int j = 16 * t + MF::out_row(kg, v);
-          int64_t a = base + (int64_t)j * step;
-          out[a] = Conv<Tout>::from_f64((double)acc[t][v]);
+          if (j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64((double)acc[t][v]);
         }
-      }
     }
-    // ---- fringe rows on the vector ALU from the B registers
-    for (int jr = 16 * q; jr < n; ++jr) {
+    // fringe rows on the vector ALU from the B registers
+#pragma unroll
+    for (int jr = 16 * QMAX; jr < NMAX; ++jr) {
       const E *orow = opl + (size_t)jr * ld + kg * MF::KPL;
       double sum = 0.0;
 #pragma unroll
       for (int s = 0; s < KSMAX; ++s)
-        if (s < ksteps) {
 #pragma unroll
-          for (int u = 0; u < MF::KPL; ++u)
-            sum += MF::to_f64(orow[s * MF::KSTEP + u]) * MF::to_f64(bv[s][u]);
-        }
+        for (int u = 0; u < MF::KPL; ++u)
+          sum += MF::to_f64(orow[s * MF::KSTEP + u]) * MF::to_f64(bv[s][u]);
       sum += __shfl_xor(sum, 16, 64);
       sum += __shfl_xor(sum, 32, 64);
-      if (kg == 0 && cvalid) out[base + (int64_t)jr * step] = Conv<Tout>::from_f64(sum);
+      if (kg == 0 && cvalid && jr < n) out[base + (int64_t)jr * step] = Conv<Tout>::from_f64(sum);
     }
+  };
+  // one strip in flight per wave while the current one is multiplied
+  int64_t strip = (int64_t)blockIdx.x * (GEMM2_THREADS / 64) + wave;
+  E bnext[KSMAX][MF::KPL];
+  load_b(strip, bnext);
+  for (; strip < nstrips; strip += wstride) {
+    E bv[KSMAX][MF::KPL];
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+#pragma unroll
+      for (int u = 0; u < MF::KPL; ++u) bv[s][u] = bnext[s][u];
+    load_b(strip + wstride, bnext);
+    process(strip, bv);
   }
 }
 
@@ -492,8 +519,8 @@ template <typename TC, int P> struct ElimState {
 
 // Factor row i given the state of rows i-P..i-1; returns the new row's U
 // entries (row[P] = pivot, row[P+c] = u[i][i+c]) and the multipliers l[dist-1].
-template <typename TC, int P>
-__device__ inline void factor_row(int i, const ElimState<TC, P> &st, cptr<TC> wb, cptr<TC> mb,
+template <typename TC, int P, typename Ptr>
+__device__ inline void factor_row(int i, const ElimState<TC, P> &st, Ptr wb, Ptr mb,
                                   TC gamma, TC nul, TC (&row)[2 * P + 1], TC (&l)[P]) {
   constexpr int B = 2 * P + 1;
 #pragma unroll
@@ -512,6 +539,21 @@ __device__ inline void factor_row(int i, const ElimState<TC, P> &st, cptr<TC> wb
       row[P - dist + P] -= lv * ujP;
     }
   }
+}
+
+// 1/x for the pivots: hardware reciprocal refined by two Newton steps
+// (r <- r (2 - x r)), accurate to a few ulp; pivots are positive and far from
+// the range limits.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
+}
+__device__ inline float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  r = r * (2.0f - x * r);
+  return r;
 }
 
 template <typename TC, int P>
@@ -551,14 +593,6 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
 #pragma unroll
     for (int i = 0; i < NY; ++i) y[i] = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
   }
-  // YREG == false: all right-hand-side loads are issued up front into rr, which
-  // the forward sweep consumes (its registers free up as the checkpoints grow)
-  constexpr int NR = YREG ? 1 : NT;
-  TC rr[NR];
-  if (!YREG) {
-#pragma unroll
-    for (int i = 0; i < NR; ++i) rr[i] = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
-  }
   TC yp[P];  // previous P forward-substituted values (YREG == false)
 #pragma unroll
   for (int a = 0; a < P; ++a) yp[a] = 0;
@@ -571,28 +605,55 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   }
   ElimState<TC, P> ck[NSEG];
   bool bad = false;
-  // forward sweep: factor and forward-substitute, checkpoint every C rows
+  // forward sweep: factor and forward-substitute, checkpoint every C rows.
+  // YREG == false: right-hand sides are read one segment ahead (rnext) so the
+  // loads overlap the elimination without holding all NT values in registers.
+  constexpr int CR = YREG ? 1 : C;
+  TC rseg[CR], rnext[CR];
+  if (!YREG) {
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    if (i % C == 0) ck[i / C] = st;
-    TC row[B], l[P];
-    factor_row<TC, P>(i, st, wbc, mbc, gamma, nul, row, l);
-    if (YREG) {
+    for (int u = 0; u < CR; ++u) rnext[u] = (TC)Conv<Tio>::to_f64(r[(int64_t)(u < NT ? u : 0) * ns]);
+  }
 #pragma unroll
-      for (int dist = P; dist >= 1; --dist)
-        if (i - dist >= 0) y[i] -= l[dist - 1] * y[i - dist];
-    } else {
-      TC yi = rr[YREG ? 0 : i];
+  for (int sg = 0; sg < NSEG; ++sg) {
+    const int i0 = sg * C;
+    const int i1 = (i0 + C < NT) ? i0 + C : NT;
+    ck[sg] = st;
+    if (!YREG) {
 #pragma unroll
-      for (int dist = P; dist >= 1; --dist)
-        if (i - dist >= 0) yi -= l[dist - 1] * yp[dist - 1];
+      for (int u = 0; u < CR; ++u) rseg[u] = rnext[u];
+      if (sg + 1 < NSEG) {
 #pragma unroll
-      for (int a = P - 1; a >= 1; --a) yp[a] = yp[a - 1];
-      yp[0] = yi;
-      ys[(int64_t)i * ns] = yi;
+        for (int u = 0; u < CR; ++u) {
+          int i = i1 + u;
+          rnext[u] = (TC)Conv<Tio>::to_f64(r[(int64_t)(i < NT ? i : 0) * ns]);
+        }
+      }
     }
-    if (!(row[P] > (TC)0)) bad = true;
-    push_row<TC, P>(st, row, (TC)1 / row[P]);
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      TC row[B], l[P];
+      factor_row<TC, P>(i, st, wbc, mbc, gamma, nul, row, l);
+      if (YREG) {
+#pragma unroll
+        for (int dist = P; dist >= 1; --dist)
+          if (i - dist >= 0) y[YREG ? i : 0] -= l[dist - 1] * y[YREG && i >= dist ? i - dist : 0];
+      } else {
+        TC yi = rseg[YREG ? 0 : i - i0];
+#pragma unroll
+        for (int dist = P; dist >= 1; --dist)
+          if (i - dist >= 0) yi -= l[dist - 1] * yp[dist - 1];
+#pragma unroll
+        for (int a = P - 1; a >= 1; --a) yp[a] = yp[a - 1];
+        yp[0] = yi;
+        ys[(int64_t)i * ns] = yi;
+      }
+      if (!(row[P] > (TC)0)) bad = true;
+      push_row<TC, P>(st, row, recip(row[P]));
+      // one row at a time: stops the scheduler from computing every row's
+      // matrix entries up front (hundreds of live registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   if (bad) *flag = 1;
   // backward sweep over segments.  nul and the band pointers pass through an
@@ -621,11 +682,12 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
     for (int i = i0; i < i1; ++i) {
       TC row[B], l[P];
       factor_row<TC, P>(i, s2, wb2, mb2, gamma, nul2, row, l);
-      TC rp = (TC)1 / row[P];
+      TC rp = recip(row[P]);
       su[i - i0][0] = rp;
 #pragma unroll
       for (int c = 1; c < P; ++c) su[i - i0][c] = row[P + c];
       push_row<TC, P>(s2, row, rp);
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = i1 - 1; i >= i0; --i) {

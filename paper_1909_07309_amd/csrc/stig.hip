@@ -228,8 +228,9 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   typedef typename Mfma<TC>::elem E;
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
   if (n <= GEMM2_MAX_N && !in_scale && !out_scale) {
-    const int ld = lds_ld<TC>(n);
-    size_t lds = (size_t)round_up(n, 16) * ld * sizeof(E);
+    // LDS as sized inside mode_gemm_small: compile-time n for 65 / 49, else GEMM2_MAX_N
+    const int nm = (n == 65 || n == 49) ? n : GEMM2_MAX_N;
+    size_t lds = (size_t)round_up(nm, 16) * lds_ld<TC>(nm) * sizeof(E);
     int64_t nstrips = (total_cols + 15) / 16;
     unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID);
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
@@ -324,8 +325,8 @@ stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int
 template <typename Tio, typename TC>
 stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
   // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
-  if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 14>(p, in, out, nrhs, transpose);
-  if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 12>(p, in, out, nrhs, transpose);
+  if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose);
+  if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose);
   if (p->nt == 9 && p->pt == 2) return launch_time_reg<Tio, TC, 9, 2, 3>(p, in, out, nrhs, transpose);
   STIG_TRY(p->tscr.ensure((size_t)(p->pt + 1) * p->N * nrhs * sizeof(TC)));
   switch (p->pt) {
