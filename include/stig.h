@@ -118,6 +118,54 @@ stig_status stig_set_diag_scaling(stig_plan *plan, const double *D);
 stig_status stig_set_A_csr(stig_plan *plan, const int64_t *rowptr,
                            const int32_t *col, const double *val, int64_t nnz);
 
+/* Optional: the geometry-aware scaling of eq. prec_geo computed by the library
+ * when the true system has the same time factors as the plan and spatial
+ * factors M_s, K_s (any sparsity, e.g. a non-separable conductivity): with the
+ * host diagonals dMs, dKs (N_s doubles each, [x_d]..[x_1]) of M_s and K_s,
+ *   D[t][s] = (gamma W_tt dMs_s + nu M_tt dKs_s) / (gamma W_tt dMs~_s + nu M_tt dKs~_s),
+ * where dMs~, dKs~ are the diagonals of the plan's Kronecker factors.  Then as
+ * stig_set_diag_scaling(D).  STIG_EBREAKDOWN if a diagonal is not positive. */
+stig_status stig_set_diag_scaling_kron(stig_plan *plan, const double *dMs, const double *dKs);
+
+/* ---------------------------------------------- 2D spatial assembly, full CSR */
+
+/* Spatial stiffness and mass on the unit square in parametric coordinates
+ * (Section 4.3: the geometry and coefficients enter through the coefficient
+ * matrix), for the Dirichlet-restricted open uniform B-spline space of degree p
+ * with n_el elements per direction (n = n_el + p - 2 unknowns per direction,
+ * unknown s = i_1 + n i_2):
+ *   K_ij = int c11 d1B_i d1B_j + c22 d2B_i d2B_j,   M_ij = int c33 B_i B_j,
+ * from coefficient values at the tensor Gauss grid (host, [q2][q1] with
+ * n_el * nq points per direction, as stig_quadrature).  Output CSR (host):
+ * rowptr (n^2 + 1), col (int32, sorted), valK, valM over the B-spline overlap
+ * pattern.  With rowptr == NULL only *nnz is returned (size query). */
+stig_status stig_assemble_2d(int n_el, int p, int nq, const double *c11, const double *c22,
+                             const double *c33, int64_t *rowptr, int32_t *col, double *valK,
+                             double *valM, int64_t *nnz);
+
+/* Separable approximation of eq. separation from element-midpoint samples
+ * (host, [e2][e1], n1 x n2 elements) of the diagonal coefficients C11, C22 and
+ * C33: C33 ~ phi1(e1) phi2(e2), C11 ~ Phi1(e1) phi2(e2), C22 ~ phi1(e1) Phi2(e2),
+ * by rank-one fits in log space (exact for separable samples).  Outputs host. */
+stig_status stig_separate_2d(int n1, int n2, const double *C11, const double *C22,
+                             const double *C33, double *phi1, double *phi2, double *Phi1,
+                             double *Phi2);
+
+/* Row pointers (host, n_t * ns + 1) of the space-time CSR of
+ * W (x) M_s + M_t (x) K_s for banded time factors of bandwidth p_t and a spatial
+ * pattern with host row pointers rowptr2d (ns + 1). */
+stig_status stig_kron_csr_rowptr(int n_t, int p_t, int64_t ns, const int64_t *rowptr2d,
+                                 int64_t *rowptr);
+
+/* Fill (device) col/val of that CSR: rowptr (device, from stig_kron_csr_rowptr),
+ * spatial pattern and values (device: rowptr2d, col2d, valM2d, valK2d) and the
+ * dense host time factors Wt, Mt (n_t x n_t, bandwidth p_t of the plan).  The
+ * columns are int32 (N < 2^31).  Synchronises. */
+stig_status stig_kron_csr_fill(stig_plan *plan, const int64_t *rowptr, int32_t *col, double *val,
+                               const int64_t *rowptr2d, const int32_t *col2d,
+                               const double *valM2d, const double *valK2d, const double *Wt,
+                               const double *Mt);
+
 /* ---------------------------------------------------------------- hot path */
 
 /* s = A-hat^{-1} r (transpose = 0) or s = A-hat^{-T} r (transpose = 1) for nrhs
@@ -141,6 +189,18 @@ stig_status stig_matvec_A(stig_plan *plan, const double *x, double *y, int nrhs,
  * function with coefficients z (used to build smooth synthetic sources).
  * Uses the factors given to stig_setup_1d_pencils. */
 stig_status stig_apply_mass(stig_plan *plan, const double *z, double *y, int nrhs);
+
+/* Initial-datum lifting (Section 3.1, non-homogeneous initial condition), read
+ * discretely: the initial datum is u_0(x) = sum_i c0_i B_i(x) times the removed
+ * first time B-spline.  Its contribution to the kept equations is
+ *     y = A_{I,0} c0 = gamma (a (x) M_s) c0 + nu (b (x) K_s) c0,
+ * with a (host, n_t) the column of the unrestricted W_t that belongs to the
+ * removed first time function, restricted to the kept rows, and b (host, n_t)
+ * the same column of the unrestricted M_t.  c0: device, nrhs * N_s doubles
+ * ([rhs][x_d]..[x_1]); y: device, nrhs * N doubles.  The system solved for the
+ * kept unknowns is then A u = f - y. */
+stig_status stig_lift_apply(stig_plan *plan, const double *a_col, const double *b_col,
+                            const double *c0, double *y, int nrhs);
 
 /* Spatial part of the initial-datum lifting (Section 3.1, non-homogeneous
  * initial condition): with a (host, n_t) = column of the unrestricted W for the

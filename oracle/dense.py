@@ -52,7 +52,7 @@ def unit_cube_system(d, n_el, p, T=1.0, gamma=1.0, nu=1.0):
     return kron_system(Wt, Mt, [K] * d, [M] * d, gamma, nu)
 
 
-def brute_force_system(d, n_el, p, T=1.0, gamma=1.0, nu=1.0, nq=None):
+def brute_force_system(d, n_el, p, T=1.0, gamma=1.0, nu=1.0, nq=None, full_time=False):
     """A_{ij} = int_0^T int_Omega (gamma d_t B_j B_i + nu grad B_j . grad B_i) on Omega = (0,1)^d.
 
     B_i(x, t) is the product of the restricted 1D B-splines (eq. tens-prod-space-parametric,
@@ -68,8 +68,11 @@ def brute_force_system(d, n_el, p, T=1.0, gamma=1.0, nu=1.0, nq=None):
     # [q, i]: keep spatial functions 2..m-1 and time functions 2..m (Section 2.2)
     Bs = bs.basis(xs, p, qs)[:, 1:-1]
     Ds = bs.basis_derivative(xs, p, qs)[:, 1:-1]
-    Bt = bs.basis(xt, p, qt)[:, 1:]
-    Dt = bs.basis_derivative(xt, p, qt)[:, 1:]
+    # full_time=True keeps the first time function too (its block column is the
+    # initial-datum lifting operator)
+    t0 = 0 if full_time else 1
+    Bt = bs.basis(xt, p, qt)[:, t0:]
+    Dt = bs.basis_derivative(xt, p, qt)[:, t0:]
 
     # Multivariate basis on the full tensor grid: for each factor (time, x_d, ..., x_1)
     # take either the value or the derivative of the 1D function, multiply them

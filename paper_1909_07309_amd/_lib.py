@@ -43,12 +43,19 @@ SIGNATURES = {
     "stig_matvec_A": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int]),
     "stig_apply_mass": (C.c_int, [_vp, _vp, _vp, C.c_int]),
     "stig_lift_adjoint": (C.c_int, [_vp, _dp, _dp, _vp, _vp, C.c_int]),
+    "stig_lift_apply": (C.c_int, [_vp, _dp, _dp, _vp, _vp, C.c_int]),
     "stig_gmres_solve": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_double, C.c_int,
                                    C.c_int, C.c_int, C.c_int, C.POINTER(StigInfo)]),
     "stig_plan_device_bytes": (C.c_size_t, [_vp]),
     "stig_profile_enable": (C.c_int, [_vp, C.c_int]),
     "stig_profile_reset": (C.c_int, [_vp]),
     "stig_profile_get": (C.c_int, [_vp, C.c_int, _dp, _dp, C.POINTER(C.c_longlong)]),
+    "stig_set_diag_scaling_kron": (C.c_int, [_vp, _dp, _dp]),
+    "stig_assemble_2d": (C.c_int, [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _vp, _vp, _dp, _dp,
+                                   C.POINTER(C.c_int64)]),
+    "stig_separate_2d": (C.c_int, [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+    "stig_kron_csr_rowptr": (C.c_int, [C.c_int, C.c_int, C.c_int64, _vp, _vp]),
+    "stig_kron_csr_fill": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, _dp]),
     "stig_quadrature": (C.c_int, [C.c_int, C.c_int, C.c_double, _dp, _dp]),
     "stig_assemble_1d": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_int, _dp, C.c_int, _dp]),
     "stig_load_1d": (C.c_int, [C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp]),

@@ -140,6 +140,20 @@ class Plan:
                                       _dev(g, nrhs * self.N_s, "g"), nrhs))
         return g
 
+    def lift_apply(self, a_col, b_col, c0, y=None):
+        """y = A_{I,0} c0 (initial-datum lifting), c0 of shape [rhs][x_d]..[x_1]."""
+        nrhs = c0.numel() // self.N_s
+        a_col = np.ascontiguousarray(a_col, dtype=np.float64)
+        b_col = np.ascontiguousarray(b_col, dtype=np.float64)
+        assert a_col.shape == (self.n_t,) and b_col.shape == (self.n_t,)
+        if y is None:
+            y = torch.empty((nrhs,) + self.shape, dtype=torch.float64, device=c0.device)
+        self._sync_stream()
+        check(lib().stig_lift_apply(self._h, dptr(a_col), dptr(b_col),
+                                    _dev(c0, nrhs * self.N_s, "c0"), _dev(y, nrhs * self.N, "y"),
+                                    nrhs))
+        return y
+
     def gmres_solve(self, f, u=None, restart=30, rtol=1e-8, maxit=300, flexible=False,
                     transpose=False, prec="fp64", allow_not_converged=False):
         nrhs = self._nrhs(f)
@@ -174,6 +188,34 @@ class Plan:
             out[name] = (ms.value, by.value, n.value)
         return out
 
+    def set_diag_scaling_kron(self, dMs, dKs):
+        dMs = np.ascontiguousarray(dMs, dtype=np.float64).ravel()
+        dKs = np.ascontiguousarray(dKs, dtype=np.float64).ravel()
+        assert dMs.size == self.N_s and dKs.size == self.N_s
+        self._sync_stream()
+        check(lib().stig_set_diag_scaling_kron(self._h, dptr(dMs), dptr(dKs)))
+
+    def kron_csr(self, space_csr, Wt, Mt, device="cuda"):
+        """Build W (x) M_s + Mt (x) K_s as a device CSR (int64 rowptr, int32 col, f64 val) from
+        a host spatial CSR (rowptr, col, valK, valM) and dense host time factors."""
+        rp2, c2, vK, vM = space_csr
+        Ns = rp2.size - 1
+        rowptr = np.empty(self.n_t * Ns + 1, dtype=np.int64)
+        check(lib().stig_kron_csr_rowptr(self.n_t, self.p_t, Ns, rp2.ctypes.data_as(C.c_void_p),
+                                         rowptr.ctypes.data_as(C.c_void_p)))
+        nnz = int(rowptr[-1])
+        d_rowptr = torch.from_numpy(rowptr).to(device)
+        d_col = torch.empty(nnz, dtype=torch.int32, device=device)
+        d_val = torch.empty(nnz, dtype=torch.float64, device=device)
+        t = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in (rp2, c2, vM, vK)]
+        Wt = np.ascontiguousarray(Wt, dtype=np.float64)
+        Mt = np.ascontiguousarray(Mt, dtype=np.float64)
+        self._sync_stream()
+        check(lib().stig_kron_csr_fill(self._h, C.c_void_p(d_rowptr.data_ptr()),
+                                       C.c_void_p(d_col.data_ptr()), C.c_void_p(d_val.data_ptr()),
+                                       *[C.c_void_p(x.data_ptr()) for x in t], dptr(Wt), dptr(Mt)))
+        return d_rowptr, d_col, d_val
+
     def device_bytes(self):
         return int(lib().stig_plan_device_bytes(self._h))
 
@@ -205,6 +247,32 @@ def load_1d(n_el, p, fvals, nq, length=1.0):
     out = np.empty(n_el + p)
     check(lib().stig_load_1d(n_el, p, float(length), dptr(fvals), int(nq), dptr(out)))
     return out
+
+
+def assemble_2d(n_el, p, nq, c11, c22, c33):
+    """Host CSR (rowptr int64, col int32, valK, valM) of the 2D parametric stiffness / mass."""
+    c11, c22, c33 = (np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (c11, c22, c33))
+    nnz = C.c_int64()
+    check(lib().stig_assemble_2d(n_el, p, nq, None, None, None, None, None, None, None,
+                                 C.byref(nnz)))
+    n = n_el + p - 2
+    rowptr = np.empty(n * n + 1, dtype=np.int64)
+    col = np.empty(nnz.value, dtype=np.int32)
+    valK = np.empty(nnz.value)
+    valM = np.empty(nnz.value)
+    check(lib().stig_assemble_2d(n_el, p, nq, dptr(c11), dptr(c22), dptr(c33),
+                                 rowptr.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p),
+                                 dptr(valK), dptr(valM), C.byref(nnz)))
+    return rowptr, col, valK, valM
+
+
+def separate_2d(C11, C22, C33):
+    """(phi1, phi2, Phi1, Phi2) from element-midpoint samples shaped [e2][e1]."""
+    C11, C22, C33 = (np.ascontiguousarray(a, dtype=np.float64) for a in (C11, C22, C33))
+    n2, n1 = C33.shape
+    out = [np.empty(n1), np.empty(n2), np.empty(n1), np.empty(n2)]
+    check(lib().stig_separate_2d(n1, n2, dptr(C11), dptr(C22), dptr(C33), *[dptr(o) for o in out]))
+    return tuple(out)
 
 
 def sym_eig(K, M):

@@ -159,6 +159,114 @@ void load_1d(int n_el, int p, double length, const double *fvals, int nq, double
     }
 }
 
+int64_t assemble_2d(int n_el, int p, int nq, const double *c11, const double *c22,
+                    const double *c33, int64_t *rowptr, int32_t *col, double *valK, double *valM) {
+  // Restricted (Dirichlet) tensor-product space on (0,1)^2, n = n_el + p - 2 per
+  // direction, unknown s = i1 + n * i2.  Pattern: all j with |i1-j1| <= p and
+  // |i2-j2| <= p inside the grid (the overlap pattern of the B-splines).
+  const int n = n_el + p - 2;
+  const int64_t Ns = (int64_t)n * n;
+  if (!rowptr) {  // size query
+    int64_t nnz = 0;
+    for (int i2 = 0; i2 < n; ++i2)
+      for (int i1 = 0; i1 < n; ++i1) {
+        int w1 = std::min(n - 1, i1 + p) - std::max(0, i1 - p) + 1;
+        int w2 = std::min(n - 1, i2 + p) - std::max(0, i2 - p) + 1;
+        nnz += (int64_t)w1 * w2;
+      }
+    return nnz;
+  }
+  rowptr[0] = 0;
+  for (int64_t s = 0; s < Ns; ++s) {
+    int i1 = (int)(s % n), i2 = (int)(s / n);
+    int64_t k = rowptr[s];
+    for (int j2 = std::max(0, i2 - p); j2 <= std::min(n - 1, i2 + p); ++j2)
+      for (int j1 = std::max(0, i1 - p); j1 <= std::min(n - 1, i1 + p); ++j1) {
+        col[k] = j1 + n * j2;
+        valK[k] = 0.0;
+        valM[k] = 0.0;
+        ++k;
+      }
+    rowptr[s + 1] = k;
+  }
+  // element loop: local functions e + a (unrestricted) -> restricted e + a - 1
+  std::vector<double> x, w;
+  element_quadrature(n_el, nq, 1.0, x, w);
+  std::vector<double> N1((size_t)nq * (p + 1)), D1((size_t)nq * (p + 1));
+  std::vector<double> N2((size_t)nq * (p + 1)), D2((size_t)nq * (p + 1));
+  const int nqt = n_el * nq;  // points per direction
+  for (int e2 = 0; e2 < n_el; ++e2) {
+    for (int k2 = 0; k2 < nq; ++k2)
+      span_basis(e2, n_el, p, 1.0, x[(size_t)e2 * nq + k2], &N2[(size_t)k2 * (p + 1)],
+                 &D2[(size_t)k2 * (p + 1)]);
+    for (int e1 = 0; e1 < n_el; ++e1) {
+      for (int k1 = 0; k1 < nq; ++k1)
+        span_basis(e1, n_el, p, 1.0, x[(size_t)e1 * nq + k1], &N1[(size_t)k1 * (p + 1)],
+                   &D1[(size_t)k1 * (p + 1)]);
+      for (int a2 = 0; a2 <= p; ++a2)
+        for (int a1 = 0; a1 <= p; ++a1) {
+          int i1 = e1 + a1 - 1, i2 = e2 + a2 - 1;
+          if (i1 < 0 || i1 >= n || i2 < 0 || i2 >= n) continue;
+          int64_t row = (int64_t)i1 + (int64_t)n * i2;
+          for (int b2 = 0; b2 <= p; ++b2)
+            for (int b1 = 0; b1 <= p; ++b1) {
+              int j1 = e1 + b1 - 1, j2 = e2 + b2 - 1;
+              if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n) continue;
+              double kv = 0.0, mv = 0.0;
+              for (int k2 = 0; k2 < nq; ++k2)
+                for (int k1 = 0; k1 < nq; ++k1) {
+                  size_t g = (size_t)(e2 * nq + k2) * nqt + (size_t)(e1 * nq + k1);
+                  double ww = w[(size_t)e2 * nq + k2] * w[(size_t)e1 * nq + k1];
+                  double n1a = N1[k1 * (p + 1) + a1], n1b = N1[k1 * (p + 1) + b1];
+                  double n2a = N2[k2 * (p + 1) + a2], n2b = N2[k2 * (p + 1) + b2];
+                  double d1a = D1[k1 * (p + 1) + a1], d1b = D1[k1 * (p + 1) + b1];
+                  double d2a = D2[k2 * (p + 1) + a2], d2b = D2[k2 * (p + 1) + b2];
+                  kv += ww * (c11[g] * d1a * d1b * n2a * n2b + c22[g] * n1a * n1b * d2a * d2b);
+                  mv += ww * c33[g] * n1a * n1b * n2a * n2b;
+                }
+              // locate column (j1, j2) in row's pattern
+              int lo1 = std::max(0, i1 - p), lo2 = std::max(0, i2 - p);
+              int wd1 = std::min(n - 1, i1 + p) - lo1 + 1;
+              int64_t k = rowptr[row] + (int64_t)(j2 - lo2) * wd1 + (j1 - lo1);
+              valK[k] += kv;
+              valM[k] += mv;
+            }
+        }
+    }
+  }
+  return rowptr[Ns];
+}
+
+void separate_2d(int n1, int n2, const double *C11, const double *C22, const double *C33,
+                 double *phi1, double *phi2, double *Phi1, double *Phi2) {
+  // Rank-one fits in log space of element-midpoint samples [e2][e1]:
+  //   log phi1(e1) = mean_e2 log C33,  log phi2(e2) = mean_e1 log C33 - mean log C33,
+  //   log Phi1(e1) = mean_e2 log(C11 / phi2),  log Phi2(e2) = mean_e1 log(C22 / phi1).
+  // Exact whenever the sampled coefficient is itself a product of univariate factors.
+  double tot = 0.0;
+  std::vector<double> r1(n1, 0.0), r2(n2, 0.0);
+  for (int e2 = 0; e2 < n2; ++e2)
+    for (int e1 = 0; e1 < n1; ++e1) {
+      double l = std::log(C33[(size_t)e2 * n1 + e1]);
+      r1[e1] += l;
+      r2[e2] += l;
+      tot += l;
+    }
+  tot /= (double)n1 * n2;
+  for (int e1 = 0; e1 < n1; ++e1) phi1[e1] = std::exp(r1[e1] / n2);
+  for (int e2 = 0; e2 < n2; ++e2) phi2[e2] = std::exp(r2[e2] / n1 - tot);
+  for (int e1 = 0; e1 < n1; ++e1) {
+    double acc = 0.0;
+    for (int e2 = 0; e2 < n2; ++e2) acc += std::log(C11[(size_t)e2 * n1 + e1] / phi2[e2]);
+    Phi1[e1] = std::exp(acc / n2);
+  }
+  for (int e2 = 0; e2 < n2; ++e2) {
+    double acc = 0.0;
+    for (int e1 = 0; e1 < n1; ++e1) acc += std::log(C22[(size_t)e2 * n1 + e1] / phi1[e1]);
+    Phi2[e2] = std::exp(acc / n1);
+  }
+}
+
 // Returns false if M is not positive definite.
 bool sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
   std::vector<double> L((size_t)n * n, 0.0);

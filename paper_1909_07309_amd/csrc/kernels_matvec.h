@@ -115,20 +115,59 @@ __global__ void time_weighted_sum(const double *__restrict__ in, double *__restr
   out[g] = acc;
 }
 
+// Outer product along t: out[rhs][t][s] = wa[t] * a[rhs][s] + wb[t] * b[rhs][s].
+__global__ void time_outer2(const double *__restrict__ a, const double *__restrict__ b,
+                            const double *__restrict__ wa, const double *__restrict__ wb,
+                            double *__restrict__ out, int nt, int64_t ns, int nrhs) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ns * nrhs) return;
+  int64_t rhs = g / ns, s = g - rhs * ns;
+  double av = a[g], bv = b[g];
+  double *o = out + rhs * ns * nt + s;
+  for (int t = 0; t < nt; ++t) o[(int64_t)t * ns] = wa[t] * av + wb[t] * bv;
+}
+
+// Entries of A = W (x) M_s + Mt (x) K_s as CSR, one thread per row (t, s):
+// for each time neighbour t' in the band and each entry (s, s') of the spatial
+// pattern, column t' * ns + s' and value W[t][t'] M_s[s][s'] + Mt[t][t'] K_s[s][s'].
+// Time bands as rows of 2P+1 coefficients (zero outside the matrix).
+__global__ void kron_csr_fill(const int64_t *__restrict__ rowptr, int32_t *__restrict__ col,
+                              double *__restrict__ val, const int64_t *__restrict__ rp2,
+                              const int32_t *__restrict__ col2, const double *__restrict__ m2,
+                              const double *__restrict__ k2, const double *__restrict__ wb,
+                              const double *__restrict__ mb, int P, int nt, int64_t ns) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ns * nt) return;
+  int64_t t = r / ns, s = r - t * ns;
+  int64_t k = rowptr[r];
+  const int B = 2 * P + 1;
+  for (int64_t tp = t - P; tp <= t + P; ++tp) {
+    if (tp < 0 || tp >= nt) continue;
+    double wv = wb[t * B + (tp - t) + P], mv = mb[t * B + (tp - t) + P];
+    for (int64_t e = rp2[s]; e < rp2[s + 1]; ++e) {
+      col[k] = (int32_t)(tp * ns + col2[e]);
+      val[k] = wv * m2[e] + mv * k2[e];
+      ++k;
+    }
+  }
+}
+
 // y = A x for a CSR matrix (int64 row pointers, int32 columns).  One wavefront
 // per row: rows of the space-time quarter-annulus operator hold ~700 entries.
 __global__ void csr_spmv(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                          const double *__restrict__ val, const double *__restrict__ x,
                          double *__restrict__ y, int64_t nrows) {
-  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (row >= nrows) return;
-  int64_t b = rowptr[row], e = rowptr[row + 1];
-  double s = 0.0;
-  for (int64_t k = b + lane; k < e; k += 64) s += val[k] * x[col[k]];
+  const int lane = threadIdx.x & 63;
+  const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < nrows;
+       row += wstride) {
+    int64_t b = rowptr[row], e = rowptr[row + 1];
+    double s = 0.0;
+    for (int64_t k = b + lane; k < e; k += 64) s += val[k] * x[col[k]];
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) y[row] = s;
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) y[row] = s;
+  }
 }
 
 }  // namespace stig

@@ -92,6 +92,8 @@ struct stig_plan {
   DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
   DevBuf sK[3], sM[3];    // spatial bands (matvec, mass apply)
   DevBuf dmh;             // D^{-1/2}, N doubles (optional)
+  // host copies of the diagonals of the 1D factors (geometry scaling)
+  std::vector<double> dK1[3], dM1[3], dWt, dMt;
   bool has_dmh = false;
   const int64_t *csr_rowptr = nullptr;
   const int32_t *csr_col = nullptr;
@@ -757,6 +759,12 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     STIG_TRY(extract_band(M1d[l], n, p->ps, mb, "spatial mass"));
     STIG_TRY(upload(p->sK[l], kb, s));
     STIG_TRY(upload(p->sM[l], mb, s));
+    p->dK1[l].resize(n);
+    p->dM1[l].resize(n);
+    for (int i = 0; i < n; ++i) {
+      p->dK1[l][i] = K1d[l][(size_t)i * n + i];
+      p->dM1[l][i] = M1d[l][(size_t)i * n + i];
+    }
     HIP_TRY(hipStreamSynchronize(s));  // host vectors go out of scope
   }
   // lambda_k = sum_l lambda_{l, i_l}, k = i_1 + n_1 (i_2 + n_2 i_3)
@@ -779,6 +787,12 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
   STIG_TRY(extract_band(Wt, nt, P, wb, "W_t"));
   STIG_TRY(extract_band(WT.data(), nt, P, wtb, "W_t"));
   STIG_TRY(extract_band(Mt, nt, P, mb, "M_t"));
+  p->dWt.resize(nt);
+  p->dMt.resize(nt);
+  for (int i = 0; i < nt; ++i) {
+    p->dWt[i] = Wt[(size_t)i * nt + i];
+    p->dMt[i] = Mt[(size_t)i * nt + i];
+  }
   STIG_TRY(upload(p->tW64, wb, s));
   STIG_TRY(upload(p->tWT64, wtb, s));
   STIG_TRY(upload(p->tM64, mb, s));
@@ -822,6 +836,99 @@ stig_status stig_set_diag_scaling(stig_plan *p, const double *D) {
                      p->dmh.as<double>(), p->N);
   HIP_TRY(hipGetLastError());
   p->has_dmh = true;
+  return STIG_OK;
+}
+
+stig_status stig_set_diag_scaling_kron(stig_plan *p, const double *dMs, const double *dKs) {
+  STIG_TRY(check_plan(p, true));
+  if (!dMs || !dKs) return fail(STIG_EINVAL, "null diagonal");
+  std::vector<double> D((size_t)p->N);
+  for (int64_t s = 0; s < p->Ns; ++s) {
+    // diagonals of M-tilde_s = (x)_l M_l and K-tilde_s = sum_l (.. K_l ..)
+    double dm = 1.0, dk = 0.0;
+    int64_t r = s;
+    int idx[3] = {0, 0, 0};
+    for (int l = 0; l < p->d; ++l) {
+      idx[l] = (int)(r % p->n[l]);
+      r /= p->n[l];
+    }
+    for (int l = 0; l < p->d; ++l) dm *= p->dM1[l][idx[l]];
+    for (int l = 0; l < p->d; ++l) {
+      double term = p->dK1[l][idx[l]];
+      for (int m = 0; m < p->d; ++m)
+        if (m != l) term *= p->dM1[m][idx[m]];
+      dk += term;
+    }
+    for (int t = 0; t < p->nt; ++t) {
+      double num = p->gamma * p->dWt[t] * dMs[s] + p->nu * p->dMt[t] * dKs[s];
+      double den = p->gamma * p->dWt[t] * dm + p->nu * p->dMt[t] * dk;
+      if (!(num > 0.0) || !(den > 0.0))
+        return fail(STIG_EBREAKDOWN, "non-positive diagonal in the geometry scaling");
+      D[(size_t)t * p->Ns + s] = num / den;
+    }
+  }
+  DevBuf Dd;
+  STIG_TRY(upload(Dd, D, p->stream));
+  STIG_TRY(stig_set_diag_scaling(p, Dd.as<double>()));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return STIG_OK;
+}
+
+stig_status stig_assemble_2d(int n_el, int p, int nq, const double *c11, const double *c22,
+                             const double *c33, int64_t *rowptr, int32_t *col, double *valK,
+                             double *valM, int64_t *nnz) {
+  if (n_el < 1 || p < 1 || p > 16 || nq < 1 || !nnz) return fail(STIG_EINVAL, "bad 2D assembly");
+  if (rowptr && (!col || !valK || !valM || !c11 || !c22 || !c33))
+    return fail(STIG_EINVAL, "null 2D assembly array");
+  *nnz = assemble_2d(n_el, p, nq, c11, c22, c33, rowptr, col, valK, valM);
+  return STIG_OK;
+}
+
+stig_status stig_separate_2d(int n1, int n2, const double *C11, const double *C22,
+                             const double *C33, double *phi1, double *phi2, double *Phi1,
+                             double *Phi2) {
+  if (n1 < 1 || n2 < 1 || !C11 || !C22 || !C33 || !phi1 || !phi2 || !Phi1 || !Phi2)
+    return fail(STIG_EINVAL, "bad separation arguments");
+  for (int64_t i = 0; i < (int64_t)n1 * n2; ++i)
+    if (!(C11[i] > 0) || !(C22[i] > 0) || !(C33[i] > 0))
+      return fail(STIG_EINVAL, "coefficients must be positive");
+  separate_2d(n1, n2, C11, C22, C33, phi1, phi2, Phi1, Phi2);
+  return STIG_OK;
+}
+
+stig_status stig_kron_csr_rowptr(int n_t, int p_t, int64_t ns, const int64_t *rowptr2d,
+                                 int64_t *rowptr) {
+  if (n_t < 1 || p_t < 0 || ns < 1 || !rowptr2d || !rowptr) return fail(STIG_EINVAL, "bad rowptr");
+  rowptr[0] = 0;
+  int64_t k = 0;
+  for (int t = 0; t < n_t; ++t) {
+    int nb = std::min(n_t - 1, t + p_t) - std::max(0, t - p_t) + 1;
+    for (int64_t s = 0; s < ns; ++s) {
+      k += (int64_t)nb * (rowptr2d[s + 1] - rowptr2d[s]);
+      rowptr[(int64_t)t * ns + s + 1] = k;
+    }
+  }
+  return STIG_OK;
+}
+
+stig_status stig_kron_csr_fill(stig_plan *p, const int64_t *rowptr, int32_t *col, double *val,
+                               const int64_t *rowptr2d, const int32_t *col2d, const double *valM2d,
+                               const double *valK2d, const double *Wt, const double *Mt) {
+  STIG_TRY(check_plan(p, false));
+  if (!rowptr || !col || !val || !rowptr2d || !col2d || !valM2d || !valK2d || !Wt || !Mt)
+    return fail(STIG_EINVAL, "null CSR build argument");
+  if (p->N >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "int32 columns cannot index N");
+  std::vector<double> wb, mb;
+  STIG_TRY(extract_band(Wt, p->nt, p->pt, wb, "W_t"));
+  STIG_TRY(extract_band(Mt, p->nt, p->pt, mb, "M_t"));
+  DevBuf dw, dm;
+  STIG_TRY(upload(dw, wb, p->stream));
+  STIG_TRY(upload(dm, mb, p->stream));
+  hipLaunchKernelGGL(kron_csr_fill, dim3(grid_for(p->N, 256)), dim3(256), 0, p->stream, rowptr,
+                     col, val, rowptr2d, col2d, valM2d, valK2d, dw.as<double>(), dm.as<double>(),
+                     p->pt, p->nt, p->Ns);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(p->stream));
   return STIG_OK;
 }
 
@@ -893,6 +1000,35 @@ stig_status stig_lift_adjoint(stig_plan *p, const double *a_col, const double *b
   STIG_TRY(spatial_chain(p, p->lift1.as<double>(), ts, true, &sa, &sb, bufs));
   hipLaunchKernelGGL(stig::axpby, dim3(grid_for(ts, 256, 8192)), dim3(256), 0, p->stream, g, sb,
                      g, 1.0, -p->nu, ts);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(p->stream));  // wa, wbv freed on return
+  return STIG_OK;
+}
+
+stig_status stig_lift_apply(stig_plan *p, const double *a_col, const double *b_col,
+                            const double *c0, double *y, int nrhs) {
+  STIG_TRY(check_plan(p, true));
+  if (!a_col || !b_col || !c0 || !y || nrhs < 1) return fail(STIG_EINVAL, "bad lift arguments");
+  const int64_t ts = p->Ns * nrhs;
+  std::vector<double> ab(a_col, a_col + p->nt), bb(b_col, b_col + p->nt);
+  for (auto &v : ab) v *= p->gamma;
+  for (auto &v : bb) v *= p->nu;
+  DevBuf wa, wbv;
+  STIG_TRY(upload(wa, ab, p->stream));
+  STIG_TRY(upload(wbv, bb, p->stream));
+  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+  for (auto *b : bufs) STIG_TRY(b->ensure(ts * sizeof(double)));
+  STIG_TRY(p->lift0.ensure(ts * sizeof(double)));
+  const double *ma, *dummy, *sa, *sb;
+  STIG_TRY(spatial_chain(p, c0, ts, false, &ma, &dummy, bufs));
+  // keep M_s c0 aside before the buffers are reused by the stiffness chain
+  hipLaunchKernelGGL(stig::axpby, dim3(grid_for(ts, 256, 8192)), dim3(256), 0, p->stream, ma,
+                     nullptr, p->lift0.as<double>(), 1.0, 0.0, ts);
+  HIP_TRY(hipGetLastError());
+  STIG_TRY(spatial_chain(p, c0, ts, true, &sa, &sb, bufs));
+  hipLaunchKernelGGL(time_outer2, dim3(grid_for(ts, 256)), dim3(256), 0, p->stream,
+                     p->lift0.as<double>(), sb, wa.as<double>(), wbv.as<double>(), y, p->nt, p->Ns,
+                     nrhs);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(p->stream));  // wa, wbv freed on return
   return STIG_OK;

@@ -1,6 +1,7 @@
 // Internal declarations shared by the host translation units of libstig.
 #pragma once
 
+#include <cstdint>
 #include <vector>
 
 namespace stig {
@@ -22,6 +23,15 @@ void assemble_1d(int n_el, int p, double length, int kind, const double *weight,
 
 // Load vector from values of f at the element quadrature points.
 void load_1d(int n_el, int p, double length, const double *fvals, int nq, double *out);
+
+// 2D stiffness / mass on the restricted tensor space from coefficient samples at
+// the tensor Gauss grid (see stig_assemble_2d); rowptr == nullptr: size query.
+int64_t assemble_2d(int n_el, int p, int nq, const double *c11, const double *c22,
+                    const double *c33, int64_t *rowptr, int32_t *col, double *valK, double *valM);
+
+// Separable (rank-one, log-space) approximation of sampled coefficients.
+void separate_2d(int n1, int n2, const double *C11, const double *C22, const double *C33,
+                 double *phi1, double *phi2, double *Phi1, double *Phi2);
 
 // K U = M U Lambda, U^T M U = I, ascending; false if M is not SPD.
 bool sym_eig(int n, const double *K, const double *M, double *U, double *lam);

@@ -258,3 +258,45 @@ def test_pins_catch_dropped_spatial_stiffness_term():
     Ks_wrong = np.kron(M, K)          # missing K (x) M
     A_wrong = np.kron(Wt, Ms) + np.kron(Mt, Ks_wrong)
     assert np.abs(A_wrong - dense.brute_force_system(2, 3, 2)).max() > 1e-3
+
+
+# ------------------------------------------------------------------- adjoint
+
+def test_lifting_block_matches_brute_force_quadrature():
+    """A_{I,0} (the first time function's block column) from the unrestricted bilinear form."""
+    from oracle.adjoint import DenseAdjoint
+    d, n_el, p = 2, 3, 2
+    adj = DenseAdjoint(d, n_el, p, gamma=0.7, nu=1.3)
+    full = dense.brute_force_system(d, n_el, p, gamma=0.7, nu=1.3, full_time=True)
+    Ns = adj.Ms.shape[0]
+    assert np.abs(full[Ns:, :Ns] - adj.AI0).max() < 1e-13
+    assert np.abs(full[Ns:, Ns:] - adj.A).max() < 1e-13
+
+
+def test_adjoint_gradients_match_central_differences():
+    """L is quadratic in (f, c0): central differences equal the directional derivative."""
+    from oracle.adjoint import DenseAdjoint
+    adj = DenseAdjoint(3, 2, 2)
+    N, Ns = adj.A.shape[0], adj.Ms.shape[0]
+    rng = np.random.default_rng(3)
+    f, c0, tgt = rng.standard_normal(N), rng.standard_normal(Ns), rng.standard_normal(N)
+    gf, gc = adj.gradients(f, c0, tgt)
+    for _ in range(4):
+        df, dc = rng.standard_normal(N), rng.standard_normal(Ns)
+        h = 1e-3
+        fd = (adj.loss(f + h * df, c0 + h * dc, tgt) - adj.loss(f - h * df, c0 - h * dc, tgt)) / (2 * h)
+        an = gf @ df + gc @ dc
+        assert abs(fd - an) <= 1e-9 * abs(an)
+
+
+def test_pins_catch_wrong_lifting_sign():
+    from oracle.adjoint import DenseAdjoint
+    adj = DenseAdjoint(2, 3, 2)
+    N, Ns = adj.A.shape[0], adj.Ms.shape[0]
+    rng = np.random.default_rng(5)
+    f, c0, tgt = rng.standard_normal(N), rng.standard_normal(Ns), rng.standard_normal(N)
+    _, gc = adj.gradients(f, c0, tgt)
+    dc = rng.standard_normal(Ns)
+    h = 1e-3
+    fd = (adj.loss(f, c0 + h * dc, tgt) - adj.loss(f, c0 - h * dc, tgt)) / (2 * h)
+    assert abs(fd - (-gc) @ dc) > 1e-3 * abs(fd)      # the flipped sign is caught
