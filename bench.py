@@ -54,6 +54,47 @@ def cpu_baseline(w, f_host, target_s=12.0):
                "s_per_apply": dt}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fd_apply_cube_p3_n64.json")
+KERNEL_SOURCES = ["paper_1909_07309_amd/csrc/kernels_fd.h", "paper_1909_07309_amd/csrc/stig.hip"]
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize_counters(fetch_csv, write_csv, copy_bytes):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
+    `bench.py --calibration-copy` into per-kernel HBM bytes per launch, scaled by
+    what the counters read for the calibration copy of known size."""
+    import csv
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            acc.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k or "elementwise" in k]
+    # calibration: the largest copy dispatch moves copy_bytes in and copy_bytes out
+    cf = max(max(fetch[k]) for k in copy) / copy_bytes
+    cw = max(max(write[k]) for k in copy) / copy_bytes
+    out = {"fingerprint": kernel_fingerprint(), "copy_bytes": copy_bytes,
+           "fetch_scale": cf, "write_scale": cw, "kernels": {}}
+    for k in fetch:
+        if k in copy or k not in write:
+            continue
+        f = sum(fetch[k]) / len(fetch[k]) / cf
+        w = sum(write[k]) / len(write[k]) / cw
+        out["kernels"][k] = {"fetch_bytes": f, "write_bytes": w, "dispatches": len(fetch[k])}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,7 +102,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-kernel HBM traffic file from two --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        out = summarize_counters(*args.summarize_counters, copy_bytes=float(1 << 30))
+        json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+        print(json.dumps(out, indent=1))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -78,6 +128,12 @@ def main():
     f = source(w, plan)
     torch.cuda.synchronize()
     s = torch.empty_like(f)
+    if args.calibration_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def timed_applies(prec, steps, warmup, profile=False):
         for _ in range(warmup):
@@ -109,8 +165,18 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["share"])
     ms_l, by_l = prof[dom][0] / prof[dom][2], prof[dom][1] / prof[dom][2]
     achieved = by_l / (ms_l * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("fingerprint") == kernel_fingerprint():
+            # the dominant class's kernels at this workload's FP64 launch shape
+            key = {"mode_gemm": "stig::mode_gemm_small<double, double, double, 65>",
+                   "time_solve": "stig::time_band_solve_reg<double, double, 66, 3, 11, false>"}.get(dom)
+            k = t["kernels"].get(key)
+            if k:
+                traffic = k["fetch_bytes"] + k["write_bytes"]
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "bytes_per_launch": by_l, "ms_per_launch": ms_l}
     # whole-apply view: FP64 flops 4*d*n_s per unknown for the transforms (+ time solves)
     flops = (4 * w.d * w.n_s + 8 * w.p + 2) * w.N
