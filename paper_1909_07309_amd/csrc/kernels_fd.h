@@ -505,41 +505,17 @@ __global__ void time_band_solve(const Tio *__restrict__ in, Tio *__restrict__ ou
 
 // ----------------------------------------------- time solves, register form
 // Same systems as time_band_solve for a compile-time number of rows NT and
-// bandwidth P, with no scratch memory: each lane keeps its right-hand side /
-// forward-substituted values y_0..y_{NT-1} in registers and stores only a
-// checkpoint of the elimination state (the previous P rows of the U factor)
-// every C rows.  Back substitution walks the segments backwards, refactoring
-// each segment from its checkpoint (the same arithmetic in the same order, so
-// the U entries are bit-identical to the forward sweep) and substituting.
-// HBM traffic is the compulsory read of r and write of q.
+// bandwidth P, with no scratch memory: each lane keeps only a checkpoint of the
+// elimination state (the previous P rows of the U factor) every C rows.  Back
+// substitution walks the segments backwards, refactoring each segment from its
+// checkpoint (the same arithmetic in the same order, so the U entries are
+// bit-identical to the forward sweep) and substituting.  HBM traffic is the
+// compulsory read of r and write of q (plus, with YREG false, one write and one
+// read of the forward-substituted values through the output buffer).
 template <typename TC, int P> struct ElimState {
   TC rp[P];          // rp[d-1] = 1 / u[i-d][i-d]
-  TC u[P][P];        // u[d-1][c] = u[i-d][i-d+c], c = 1 .. P-1 (index 0 unused)
+  TC u[P][P + 1];    // u[d-1][c] = u[i-d][i-d+c], c = 1 .. P (index 0 unused)
 };
-
-// Factor row i given the state of rows i-P..i-1; returns the new row's U
-// entries (row[P] = pivot, row[P+c] = u[i][i+c]) and the multipliers l[dist-1].
-template <typename TC, int P, typename Ptr>
-__device__ inline void factor_row(int i, const ElimState<TC, P> &st, Ptr wb, Ptr mb,
-                                  TC gamma, TC nul, TC (&row)[2 * P + 1], TC (&l)[P]) {
-  constexpr int B = 2 * P + 1;
-#pragma unroll
-  for (int m = 0; m < B; ++m) row[m] = gamma * wb[i * B + m] + nul * mb[i * B + m];
-#pragma unroll
-  for (int dist = P; dist >= 1; --dist) {
-    l[dist - 1] = 0;
-    if (i - dist >= 0) {
-      const int j = i - dist;
-      TC lv = row[P - dist] * st.rp[dist - 1];
-      l[dist - 1] = lv;
-#pragma unroll
-      for (int c = 1; c < P; ++c) row[P - dist + c] -= lv * st.u[dist - 1][c];
-      // outermost superdiagonal of row j is the untouched matrix entry
-      TC ujP = gamma * wb[j * B + 2 * P] + nul * mb[j * B + 2 * P];
-      row[P - dist + P] -= lv * ujP;
-    }
-  }
-}
 
 // 1/x for the pivots: hardware reciprocal refined by two Newton steps
 // (r <- r (2 - x r)), accurate to a few ulp; pivots are positive and far from
@@ -556,17 +532,52 @@ __device__ inline float recip(float x) {
   return r;
 }
 
+// Band coefficients of one row (W and M entries at offsets -P..P).
+template <typename TC, int P> struct RowCoef {
+  TC w[2 * P + 1], m[2 * P + 1];
+};
+template <typename TC, int P>
+__device__ inline void load_coef(RowCoef<TC, P> &c, cptr<TC> wb, cptr<TC> mb, int i) {
+#pragma unroll
+  for (int k = 0; k < 2 * P + 1; ++k) {
+    c.w[k] = wb[i * (2 * P + 1) + k];
+    c.m[k] = mb[i * (2 * P + 1) + k];
+  }
+}
+
+// Factor row i (coefficients cf) against the state of rows i-P..i-1.  Returns
+// the eliminated row (row[P] = pivot, row[P+c] = u[i][i+c]) and multipliers.
+// The outermost superdiagonal u[j][j+P] of an earlier row j is the untouched
+// matrix entry, carried in the state.
+template <typename TC, int P>
+__device__ inline void factor_row(int i, const ElimState<TC, P> &st, const RowCoef<TC, P> &cf,
+                                  TC gamma, TC nul, TC (&row)[2 * P + 1], TC (&l)[P]) {
+  constexpr int B = 2 * P + 1;
+#pragma unroll
+  for (int m = 0; m < B; ++m) row[m] = gamma * cf.w[m] + nul * cf.m[m];
+#pragma unroll
+  for (int dist = P; dist >= 1; --dist) {
+    l[dist - 1] = 0;
+    if (i - dist >= 0) {
+      TC lv = row[P - dist] * st.rp[dist - 1];
+      l[dist - 1] = lv;
+#pragma unroll
+      for (int c = 1; c <= P; ++c) row[P - dist + c] -= lv * st.u[dist - 1][c];
+    }
+  }
+}
+
 template <typename TC, int P>
 __device__ inline void push_row(ElimState<TC, P> &st, const TC (&row)[2 * P + 1], TC rp) {
 #pragma unroll
   for (int a = P - 1; a >= 1; --a) {
     st.rp[a] = st.rp[a - 1];
 #pragma unroll
-    for (int c = 1; c < P; ++c) st.u[a][c] = st.u[a - 1][c];
+    for (int c = 1; c <= P; ++c) st.u[a][c] = st.u[a - 1][c];
   }
   st.rp[0] = rp;
 #pragma unroll
-  for (int c = 1; c < P; ++c) st.u[0][c] = row[P + c];
+  for (int c = 1; c <= P; ++c) st.u[0][c] = row[P + c];
 }
 
 template <typename Tio, typename TC, int NT, int P, int C, bool YREG>
@@ -576,8 +587,7 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
                     int nrhs, TC *__restrict__ ysc, int *__restrict__ flag) {
   // YREG: forward-substituted values stay in registers; otherwise they go to
   // ysc ([rhs][t][k], compute type; may alias `out` when Tio == TC) and are
-  // read back in reverse order by the backward sweep.
-  constexpr int B = 2 * P + 1;
+  // read back segment by segment by the backward sweep.
   constexpr int NSEG = (NT + C - 1) / C;
   constexpr int NY = YREG ? NT : 1;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -587,13 +597,20 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   Tio *q = out + rhs * ns * NT + k;
   TC *ys = ysc + rhs * ns * NT + k;
   const TC nul = nu * (TC)lam[k];
-  cptr<TC> wbc = as_const(wb), mbc = as_const(mb);
+  const cptr<TC> wbc = as_const(wb), mbc = as_const(mb);
+  // all right-hand-side loads up front (YREG) or one segment ahead (otherwise)
   TC y[NY];
   if (YREG) {
 #pragma unroll
     for (int i = 0; i < NY; ++i) y[i] = (TC)Conv<Tio>::to_f64(r[(int64_t)i * ns]);
   }
-  TC yp[P];  // previous P forward-substituted values (YREG == false)
+  constexpr int CR = YREG ? 1 : C;
+  TC rseg[CR], rnext[CR];
+  if (!YREG) {
+#pragma unroll
+    for (int u = 0; u < CR; ++u) rnext[u] = (TC)Conv<Tio>::to_f64(r[(int64_t)(u < NT ? u : 0) * ns]);
+  }
+  TC yp[P];
 #pragma unroll
   for (int a = 0; a < P; ++a) yp[a] = 0;
   ElimState<TC, P> st;
@@ -601,19 +618,13 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   for (int a = 0; a < P; ++a) {
     st.rp[a] = 0;
 #pragma unroll
-    for (int c = 0; c < P; ++c) st.u[a][c] = 0;
+    for (int c = 0; c <= P; ++c) st.u[a][c] = 0;
   }
   ElimState<TC, P> ck[NSEG];
   bool bad = false;
-  // forward sweep: factor and forward-substitute, checkpoint every C rows.
-  // YREG == false: right-hand sides are read one segment ahead (rnext) so the
-  // loads overlap the elimination without holding all NT values in registers.
-  constexpr int CR = YREG ? 1 : C;
-  TC rseg[CR], rnext[CR];
-  if (!YREG) {
-#pragma unroll
-    for (int u = 0; u < CR; ++u) rnext[u] = (TC)Conv<Tio>::to_f64(r[(int64_t)(u < NT ? u : 0) * ns]);
-  }
+  RowCoef<TC, P> cf, cfn;
+  load_coef<TC, P>(cfn, wbc, mbc, 0);
+  // forward sweep: factor and forward-substitute, checkpoint every C rows
 #pragma unroll
   for (int sg = 0; sg < NSEG; ++sg) {
     const int i0 = sg * C;
@@ -632,8 +643,10 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
     }
 #pragma unroll
     for (int i = i0; i < i1; ++i) {
-      TC row[B], l[P];
-      factor_row<TC, P>(i, st, wbc, mbc, gamma, nul, row, l);
+      cf = cfn;
+      if (i + 1 < NT) load_coef<TC, P>(cfn, wbc, mbc, i + 1);  // next row's coefficients
+      TC row[2 * P + 1], l[P];
+      factor_row<TC, P>(i, st, cf, gamma, nul, row, l);
       if (YREG) {
 #pragma unroll
         for (int dist = P; dist >= 1; --dist)
@@ -651,7 +664,7 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
       if (!(row[P] > (TC)0)) bad = true;
       push_row<TC, P>(st, row, recip(row[P]));
       // one row at a time: stops the scheduler from computing every row's
-      // matrix entries up front (hundreds of live registers)
+      // entries up front (hundreds of live registers)
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -663,7 +676,7 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   asm volatile("" : "+v"(nul2));
   const TC *wb2p = wb, *mb2p = mb;
   asm volatile("" : "+s"(wb2p), "+s"(mb2p));
-  cptr<TC> wb2 = as_const(wb2p), mb2 = as_const(mb2p);
+  const cptr<TC> wb2 = as_const(wb2p), mb2 = as_const(mb2p);
   TC qn[P];  // qn[c-1] = q[i+c]
 #pragma unroll
   for (int a = 0; a < P; ++a) qn[a] = 0;
@@ -671,21 +684,24 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   for (int sgi = NSEG - 1; sgi >= 0; --sgi) {
     const int i0 = sgi * C;
     const int i1 = (i0 + C < NT) ? i0 + C : NT;
-    TC su[C][P];   // su[i-i0][0] = 1/pivot, su[i-i0][c] = u[i][i+c] (c < P)
+    TC su[C][P + 1];  // su[i-i0][0] = 1/pivot, su[i-i0][c] = u[i][i+c] (c = 1..P)
     TC yseg[YREG ? 1 : C];
-    if (!YREG) {  // prefetch this segment's forward-substituted values
+    if (!YREG) {  // this segment's forward-substituted values
 #pragma unroll
       for (int i = i0; i < i1; ++i) yseg[YREG ? 0 : i - i0] = ys[(int64_t)i * ns];
     }
     ElimState<TC, P> s2 = ck[sgi];
+    load_coef<TC, P>(cfn, wb2, mb2, i0);
 #pragma unroll
     for (int i = i0; i < i1; ++i) {
-      TC row[B], l[P];
-      factor_row<TC, P>(i, s2, wb2, mb2, gamma, nul2, row, l);
+      cf = cfn;
+      if (i + 1 < i1) load_coef<TC, P>(cfn, wb2, mb2, i + 1);
+      TC row[2 * P + 1], l[P];
+      factor_row<TC, P>(i, s2, cf, gamma, nul2, row, l);
       TC rp = recip(row[P]);
       su[i - i0][0] = rp;
 #pragma unroll
-      for (int c = 1; c < P; ++c) su[i - i0][c] = row[P + c];
+      for (int c = 1; c <= P; ++c) su[i - i0][c] = row[P + c];
       push_row<TC, P>(s2, row, rp);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -693,9 +709,7 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
     for (int i = i1 - 1; i >= i0; --i) {
       TC acc = YREG ? y[YREG ? i : 0] : yseg[YREG ? 0 : i - i0];
 #pragma unroll
-      for (int c = 1; c < P; ++c) acc -= su[i - i0][c] * qn[c - 1];
-      TC uP = gamma * wb2[i * B + 2 * P] + nul2 * mb2[i * B + 2 * P];
-      acc -= uP * qn[P - 1];
+      for (int c = 1; c <= P; ++c) acc -= su[i - i0][c] * qn[c - 1];
       TC qi = acc * su[i - i0][0];
 #pragma unroll
       for (int a = P - 1; a >= 1; --a) qn[a] = qn[a - 1];
