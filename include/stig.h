@@ -83,6 +83,22 @@ void stig_plan_destroy(stig_plan *plan);
 /* Change the stream later calls are ordered on. */
 stig_status stig_set_stream(stig_plan *plan, void *stream);
 
+/* Kernel choices of apply_Pinv (stig_set_option).  Every choice computes the
+ * same result up to rounding order.
+ *   STIG_OPT_PLANE_FUSION: 1 (default) = the mode-1 and mode-2 products of
+ *     steps 2 and 4 (Section 2.3, Algorithm 1) in one fused pass per plane when
+ *     n_s[0] == n_s[1] <= 80 and no diagonal scaling is set; 0 = one pass per mode.
+ *   STIG_OPT_TIME_KERNEL: how the shifted time systems of step 3 are eliminated
+ *     for the register-resident shapes (n_t, p_t) = (66, 3), (50, 3), (9, 2):
+ *     0 (default) = right-looking with window-state checkpoints, the forward
+ *     substitution redone segment by segment in the backward sweep (nothing
+ *     stored); 3 = the same with the forward-substituted values stored and read
+ *     back; 1 = left-looking, U-row checkpoints; 2 = the generic kernel with
+ *     scratch memory (the one every other shape uses).
+ * Unknown options or values: STIG_EINVAL. */
+enum { STIG_OPT_PLANE_FUSION = 0, STIG_OPT_TIME_KERNEL = 1 };
+stig_status stig_set_option(stig_plan *plan, int option, int value);
+
 /* ------------------------------------------------------------------ setup */
 
 /* Step 1 of Algorithm 1 (Section 4.4) for the banded-time form of A-hat^{-1}.
@@ -237,7 +253,8 @@ enum {
   STIG_K_BAND_PASS = 2,   /* banded mode products of the matvec / mass apply */
   STIG_K_KRYLOV = 3,      /* Arnoldi dot products and updates */
   STIG_K_CSR = 4,         /* CSR matvec */
-  STIG_NUM_KERNEL_KINDS = 5
+  STIG_K_PLANE_GEMM = 5,  /* fused mode-1/mode-2 MFMA products of the FD apply */
+  STIG_NUM_KERNEL_KINDS = 6
 };
 
 /* on != 0: every kernel launch of the plan is bracketed by two HIP events on

@@ -35,6 +35,7 @@ SIGNATURES = {
     "stig_plan_create": (C.c_int, [C.POINTER(_vp), C.c_int, _ip, C.c_int, C.c_int, C.c_int, _vp]),
     "stig_plan_destroy": (None, [_vp]),
     "stig_set_stream": (C.c_int, [_vp, _vp]),
+    "stig_set_option": (C.c_int, [_vp, C.c_int, C.c_int]),
     "stig_setup_1d_pencils": (C.c_int, [_vp, C.POINTER(_dp), C.POINTER(_dp), _dp, _dp,
                                         C.c_double, C.c_double]),
     "stig_set_diag_scaling": (C.c_int, [_vp, _vp]),

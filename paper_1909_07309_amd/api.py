@@ -170,7 +170,21 @@ class Plan:
                    "relres_true": info.relres_true, "relres_est": info.relres_est,
                    "t_solve_ms": info.t_solve_ms, "converged": code == 0}
 
-    KERNEL_KINDS = ("mode_gemm", "time_solve", "band_pass", "krylov", "csr")
+    KERNEL_KINDS = ("mode_gemm", "time_solve", "band_pass", "krylov", "csr", "plane_gemm")
+
+    OPTIONS = {"plane_fusion": 0, "time_kernel": 1}
+    TIME_KERNELS = {"right_looking": 0, "left_looking": 1, "generic": 2, "right_looking_stored": 3}
+
+    def set_option(self, name, value):
+        """Kernel choices of apply_Pinv (same results up to rounding order):
+        plane_fusion (bool, default True), time_kernel ("right_looking" default,
+        "right_looking_stored", "left_looking", "generic")."""
+        if name == "time_kernel" and isinstance(value, str):
+            value = self.TIME_KERNELS[value]
+        check(lib().stig_set_option(self._h, self.OPTIONS[name], int(value)))
+
+    def set_plane_fusion(self, on=True):
+        self.set_option("plane_fusion", bool(on))
 
     def profile_enable(self, on=True):
         self._sync_stream()

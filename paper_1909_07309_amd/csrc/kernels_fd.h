@@ -719,4 +719,272 @@ time_band_solve_reg(const Tio *__restrict__ in, Tio *__restrict__ out, const dou
   }
 }
 
+
+// ------------------------------------- time solves, right-looking register form
+// Same systems and contract as time_band_solve_reg, eliminated right-looking:
+// the elimination state at pivot i is the P x P window S[a][b] = entry
+// (i+a, i+b) of the partially eliminated matrix (rows i .. i+P-1 after the
+// pivots before i).  Entries of those rows further right are still the
+// original matrix entries, so S is the whole state: P*P values per checkpoint
+// instead of the previous P rows of U.  Pivot i gives the U row u[i][i+b]
+// = S[0][b] (b < P), u[i][i+P] = original entry, and multipliers
+// l_a = S[a][0] / u[i][i] for the P rows below it.
+//
+// The matrix entries pivot i needs (column i+P of rows i..i+P-1, row i+P up
+// to the diagonal) come from a step record: rec[i*RS + e] (W) and
+// rec[i*RS + RH + e] (M), e = 0..2P, stored contiguously so that one pivot
+// costs two scalar loads.
+template <int P> struct StepRec {
+  static constexpr int RH = (2 * P + 1 + 3) / 4 * 4;  // W half (padded)
+  static constexpr int RS = 2 * RH;                   // record stride
+};
+
+// Segments of the backward sweep.  While segment s is substituted the lane
+// holds the checkpoints of segments 1..s (P*P values each) and P+1 values per
+// row of segment s (1/pivot, u[i][i+1..i+P-1], y_i); segment lengths shrink
+// with s so that this total is about the same for every segment.
+template <int NT, int P, int NSEG> struct SegPlan {
+  static constexpr int start(int s) {
+    if (s <= 0) return 0;
+    if (s >= NSEG) return NT;
+    double B = ((P + 1.0) * NT + P * P * NSEG * (NSEG - 1) / 2.0) / NSEG;
+    double acc = 0;
+    for (int t = 0; t < s; ++t) acc += (B - P * P * t) / (P + 1.0);
+    int v = (int)(acc + 0.5);
+    return v < NT ? v : NT;
+  }
+  static constexpr int len(int s) { return start(s + 1) - start(s); }
+  static constexpr int maxlen() {
+    int m = 0;
+    for (int s = 0; s < NSEG; ++s) m = len(s) > m ? len(s) : m;
+    return m;
+  }
+};
+
+template <typename TC, int P> struct Window {
+  TC s[P][P];
+};
+
+// One step record in registers (scalar registers: the address is uniform).
+template <typename TC, int P> struct StepVals {
+  TC w[2 * P + 1], m[2 * P + 1];
+};
+template <typename TC, int NT, int P>
+__device__ inline void load_step(StepVals<TC, P> &v, cptr<TC> rec, int i) {
+#pragma unroll
+  for (int e = 0; e < 2 * P + 1; ++e) {
+    v.w[e] = (i < NT) ? rec[i * StepRec<P>::RS + e] : (TC)0;
+    v.m[e] = (i < NT) ? rec[i * StepRec<P>::RS + StepRec<P>::RH + e] : (TC)0;
+  }
+}
+
+// Window at pivot 0: the leading P x P block (band layout wb/mb).
+template <typename TC, int NT, int P>
+__device__ inline void first_window(Window<TC, P> &S, cptr<TC> wb, cptr<TC> mb, TC gamma, TC nul) {
+#pragma unroll
+  for (int a = 0; a < P; ++a)
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      const int o = a * (2 * P + 1) + P + (b - a);
+      S.s[a][b] = (a < NT && b < NT) ? gamma * wb[o] + nul * mb[o] : (TC)0;
+    }
+}
+
+// Eliminate pivot i with its step record sv: returns 1/pivot, the U row
+// (u[1..P-1]; u[i][i+P] is step entry 0) and the multipliers l[1..P] (rows
+// i+1 .. i+P); advances S to pivot i+1.
+template <typename TC, int NT, int P>
+__device__ inline void pivot_step(int i, Window<TC, P> &S, const StepVals<TC, P> &sv, TC gamma,
+                                  TC nul, TC &rp, TC (&u)[P + 1], TC (&l)[P + 1]) {
+  const bool inner = i + P < NT;  // row i+P exists
+  auto entry = [&](int e) { return inner ? gamma * sv.w[e] + nul * sv.m[e] : (TC)0; };
+  rp = recip(S.s[0][0]);
+#pragma unroll
+  for (int b = 1; b < P; ++b) u[b] = S.s[0][b];
+  u[P] = entry(0);
+#pragma unroll
+  for (int a = 1; a < P; ++a) l[a] = S.s[a][0] * rp;
+  l[P] = entry(P) * rp;
+  Window<TC, P> S2;
+#pragma unroll
+  for (int a = 1; a < P; ++a) {
+#pragma unroll
+    for (int b = 1; b < P; ++b) S2.s[a - 1][b - 1] = S.s[a][b] - l[a] * u[b];
+    S2.s[a - 1][P - 1] = entry(a) - l[a] * u[P];
+  }
+#pragma unroll
+  for (int b = 1; b <= P; ++b) S2.s[P - 1][b - 1] = entry(P + b) - l[P] * u[b];
+  S = S2;
+}
+
+// rec: step records (see StepRec); wb, mb: band rows (first window only).
+// YREC false: the forward-substituted values go to ysc ([rhs][t][k], compute
+// type; may alias out when Tio == TC) and are read back segment by segment.
+// YREC true: nothing is stored; the right-hand-side window is checkpointed with
+// S and the backward sweep redoes the forward substitution of each segment
+// from the input (read a second time, shortly after the first).
+template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC>
+__global__ void __launch_bounds__(256, sizeof(TC) == 8 ? 2 : (YREC ? 3 : 4))
+time_band_solve_rl(const Tio *__restrict__ in, Tio *__restrict__ out, const double *__restrict__ lam,
+                   const TC *__restrict__ rec, const TC *__restrict__ wb, const TC *__restrict__ mb,
+                   TC gamma_arg, TC nu, int64_t ns, int nrhs, TC *__restrict__ ysc,
+                   int *__restrict__ flag) {
+  typedef SegPlan<NT, P, NSEG> SP;
+  constexpr int LMAX = SP::maxlen();
+  constexpr int D = NT - P < 8 ? NT - P : 8;  // right-hand-side prefetch distance (rows)
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ns * nrhs) return;
+  int64_t rhs = g / ns, k = g - rhs * ns;
+  const Tio *r = in + rhs * ns * NT + k;
+  Tio *q = out + rhs * ns * NT + k;
+  TC *ys = YREC ? nullptr : ysc + rhs * ns * NT + k;
+  // gamma and nu*lambda_k live in vector registers, so that each matrix entry
+  // is one multiply and one fma with a single scalar operand each
+  TC gamma = gamma_arg, nul = nu * (TC)lam[k];
+  asm volatile("" : "+v"(gamma));
+  const cptr<TC> recc = as_const(rec), wbc = as_const(wb), mbc = as_const(mb);
+  auto rload = [&](const Tio *base, int i) {
+    return (TC)Conv<Tio>::to_f64(base[(int64_t)(i < NT ? i : 0) * ns]);
+  };
+  // the backward sweep's second read of the input: a relaxed atomic load, which
+  // the compiler does not merge with the first read (merging would keep every
+  // input value live across the whole forward sweep)
+  auto rload_again = [&](int i) {
+    const Tio *p = r + (int64_t)(i < NT ? i : 0) * ns;
+    Tio v;
+    __atomic_load(p, &v, __ATOMIC_RELAXED);
+    return (TC)Conv<Tio>::to_f64(v);
+  };
+
+  // ---- forward sweep: factor, forward-substitute, checkpoint at segment
+  // starts.  The right-hand side of row i+P enters the window at pivot i; it
+  // is loaded D rows ahead.
+  Window<TC, P> S;
+  first_window<TC, NT, P>(S, wbc, mbc, gamma, nul);
+  TC rw[P], rq[D > 0 ? D : 1];
+#pragma unroll
+  for (int a = 0; a < P; ++a) rw[a] = rload(r, a);
+#pragma unroll
+  for (int j = 0; j < D; ++j) rq[j] = rload(r, P + j);
+  Window<TC, P> ck[NSEG];
+  TC ckr[YREC ? NSEG : 1][P];
+  // pivot check without a per-row mask: smallest pivot, and a sum that turns
+  // NaN if any pivot is NaN or infinite
+  TC pmin = S.s[0][0], pnan = 0;
+  StepVals<TC, P> sv, svn;
+  load_step<TC, NT, P>(svn, recc, 0);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+#pragma unroll
+    for (int sg = 1; sg < NSEG; ++sg)
+      if (i == SP::start(sg)) {
+        ck[sg] = S;
+        if (YREC) {
+#pragma unroll
+          for (int a = 0; a < P; ++a) ckr[YREC ? sg : 0][a] = rw[a];
+        }
+      }
+    sv = svn;
+    if (i + 1 < NT) load_step<TC, NT, P>(svn, recc, i + 1);  // next pivot's entries
+    pmin = __builtin_fmin(pmin, S.s[0][0]);
+    pnan = S.s[0][0] * (TC)0 + pnan;
+    TC rp, uu[P + 1], l[P + 1];
+    pivot_step<TC, NT, P>(i, S, sv, gamma, nul, rp, uu, l);
+    const TC yi = rw[0];
+    if (!YREC) ys[(int64_t)i * ns] = yi;
+    TC rin = 0;
+    if (i + P < NT && D > 0) {
+      rin = rq[i % D];
+      if (i + P + D < NT) rq[i % D] = rload(r, i + P + D);
+    }
+#pragma unroll
+    for (int a = 1; a < P; ++a) rw[a - 1] = rw[a] - l[a] * yi;
+    rw[P - 1] = rin - l[P] * yi;
+    // the window is needed only at checkpoints when nothing is stored: pin it
+    // here so that the substitution is not postponed (which would keep every
+    // multiplier live until the backward sweep)
+#pragma unroll
+    for (int a = 0; a < P; ++a) asm volatile("" : "+v"(rw[a]));
+    // one pivot at a time: keeps the scheduler from hoisting every row's
+    // coefficient arithmetic (hundreds of live registers)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (!(pmin > (TC)0) || !(pnan == (TC)0)) *flag = 1;
+
+  // ---- backward sweep over segments: refactor the segment from its
+  // checkpoint (same arithmetic, bit-identical U and y), then substitute.
+  // gamma, nul and the pointers pass through an empty asm so that the compiler
+  // cannot reuse the forward sweep's values (that would keep all of U live).
+  TC gamma2 = gamma, nul2 = nul;
+  asm volatile("" : "+v"(gamma2), "+v"(nul2));
+  const TC *rec2p = rec, *wb2p = wb, *mb2p = mb;
+  asm volatile("" : "+s"(rec2p), "+s"(wb2p), "+s"(mb2p));
+  const cptr<TC> rec2 = as_const(rec2p), wb2 = as_const(wb2p), mb2 = as_const(mb2p);
+  TC qn[P];  // qn[b-1] = q[i+b]
+#pragma unroll
+  for (int a = 0; a < P; ++a) qn[a] = 0;
+#pragma unroll
+  for (int sgi = NSEG - 1; sgi >= 0; --sgi) {
+    const int i0 = SP::start(sgi), i1 = SP::start(sgi + 1);
+    // YREC: right-hand sides entering the window in this segment (rows
+    // i0+P .. i1-1+P) and, for the first segment, rows 0 .. P-1; otherwise
+    // the stored forward-substituted values
+    TC yseg[LMAX];
+    TC rw2[P];
+    if (YREC) {
+#pragma unroll
+      for (int i = i0; i < i1; ++i) yseg[i - i0] = (i + P < NT) ? rload_again(i + P) : (TC)0;
+      if (sgi == 0) {
+#pragma unroll
+        for (int a = 0; a < P; ++a) rw2[a] = rload_again(a);
+      } else {
+#pragma unroll
+        for (int a = 0; a < P; ++a) rw2[a] = ckr[YREC ? sgi : 0][a];
+      }
+    } else {
+#pragma unroll
+      for (int i = i0; i < i1; ++i) yseg[i - i0] = ys[(int64_t)i * ns];
+    }
+    Window<TC, P> S2;
+    if (sgi == 0) first_window<TC, NT, P>(S2, wb2, mb2, gamma2, nul2);
+    else S2 = ck[sgi];
+    TC su[LMAX][P];  // su[i-i0][0] = 1/pivot, su[i-i0][b] = u[i][i+b], b = 1..P-1
+    StepVals<TC, P> sv2, sv2n;
+    load_step<TC, NT, P>(sv2n, rec2, i0);
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      sv2 = sv2n;
+      if (i + 1 < i1) load_step<TC, NT, P>(sv2n, rec2, i + 1);
+      TC rp, uu[P + 1], l[P + 1];
+      pivot_step<TC, NT, P>(i, S2, sv2, gamma2, nul2, rp, uu, l);
+      su[i - i0][0] = rp;
+#pragma unroll
+      for (int b = 1; b < P; ++b) su[i - i0][b] = uu[b];
+      if (YREC) {  // forward substitution again: y_i replaces r_{i+P} in yseg
+        const TC yi = rw2[0];
+        const TC rin = yseg[i - i0];
+#pragma unroll
+        for (int a = 1; a < P; ++a) rw2[a - 1] = rw2[a] - l[a] * yi;
+        rw2[P - 1] = rin - l[P] * yi;
+        yseg[i - i0] = yi;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = i1 - 1; i >= i0; --i) {
+      TC acc = yseg[i - i0];
+#pragma unroll
+      for (int b = 1; b < P; ++b) acc -= su[i - i0][b] * qn[b - 1];
+      // u[i][i+P] is the untouched matrix entry (step entry 0)
+      if (i + P < NT)
+        acc -= (gamma2 * rec2[i * StepRec<P>::RS] + nul2 * rec2[i * StepRec<P>::RS + StepRec<P>::RH]) *
+               qn[P - 1];
+      TC qi = acc * su[i - i0][0];
+#pragma unroll
+      for (int a = P - 1; a >= 1; --a) qn[a] = qn[a - 1];
+      qn[0] = qi;
+      q[(int64_t)i * ns] = Conv<Tio>::from_f64((double)qi);
+    }
+  }
+}
 }  // namespace stig

@@ -16,6 +16,7 @@
 #include "kernels_fd.h"
 #include "kernels_krylov.h"
 #include "kernels_matvec.h"
+#include "kernels_plane.h"
 #include "stig_internal.h"
 
 using namespace stig;
@@ -83,18 +84,23 @@ struct stig_plan {
   int nt = 0, ps = 0, pt = 0;
   int64_t Ns = 0, N = 0;
   hipStream_t stream = nullptr;
+  int num_cu = 256;  // compute units of the plan's device
   bool ready = false;
   double gamma = 1.0, nu = 1.0;
   // eigenvectors: [l] -> U_l and U_l^T in FP64, FP32, BF16 (row-major n x n)
   DevBuf U64[3], UT64[3], U32[3], UT32[3], U16[3], UT16[3];
   DevBuf lam;            // Ns doubles: lambda_k = sum_l lambda_{l,i_l}
   DevBuf tW64, tWT64, tM64, tW32, tWT32, tM32;  // time bands (unscaled)
+  DevBuf tR64[2], tR32[2];  // step records of [W; M] and [W^T; M] (right-looking solve)
   DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
   DevBuf sK[3], sM[3];    // spatial bands (matvec, mass apply)
   DevBuf dmh;             // D^{-1/2}, N doubles (optional)
   // host copies of the diagonals of the 1D factors (geometry scaling)
   std::vector<double> dK1[3], dM1[3], dWt, dMt;
   bool has_dmh = false;
+  bool plane_fusion = true;  // fused x/y products in the FD apply
+  int time_kernel = 0;        // 0 right-looking, 1 left-looking register form, 2 generic
+  bool time_recompute = true; // right-looking: redo the forward substitution backward
   const int64_t *csr_rowptr = nullptr;
   const int32_t *csr_col = nullptr;
   const double *csr_val = nullptr;
@@ -202,6 +208,25 @@ stig_status extract_band(const double *A, int n, int P, std::vector<double> &ban
   return STIG_OK;
 }
 
+// Step records of the right-looking time elimination (StepRec): for pivot i,
+// entry e < P is A[i+e][i+P] and entry P+b (b = 0..P) is A[i+P][i+b], zero
+// where row i+P does not exist; W entries, then M entries at offset RH.
+std::vector<double> step_records(const std::vector<double> &wband, const std::vector<double> &mband,
+                                 int n, int P) {
+  const int B = 2 * P + 1, RH = (B + 3) / 4 * 4, RS = 2 * RH;
+  std::vector<double> rec((size_t)n * RS, 0.0);
+  for (int i = 0; i < n; ++i) {
+    if (i + P >= n) continue;
+    for (int part = 0; part < 2; ++part) {
+      const std::vector<double> &band = part ? mband : wband;
+      double *o = rec.data() + (size_t)i * RS + part * RH;
+      for (int e = 0; e < P; ++e) o[e] = band[(size_t)(i + e) * B + P + (P - e)];
+      for (int b = 0; b <= P; ++b) o[P + b] = band[(size_t)(i + P) * B + P + (b - P)];
+    }
+  }
+  return rec;
+}
+
 template <typename T> std::vector<T> convert(const std::vector<double> &v);
 template <> std::vector<double> convert(const std::vector<double> &v) { return v; }
 template <> std::vector<float> convert(const std::vector<double> &v) {
@@ -275,6 +300,48 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   return STIG_OK;
 }
 
+// Fused x/y products of every plane: Y_o = Op_y X_o Op_x^T (n_x = n_y = n).
+template <typename Tin, typename Tout, typename TC, int NC>
+stig_status launch_plane_nc(stig_plan *p, const Tin *in, Tout *out,
+                            const typename Mfma<TC>::elem *opx,
+                            const typename Mfma<TC>::elem *opy, int n, int64_t planes) {
+  typedef typename Mfma<TC>::elem E;
+  constexpr int NMAX = NC ? NC : PLANE_MAX_N;
+  constexpr int NR = NMAX / 16 * 16 + NMAX % 16;
+  constexpr int threads = 64 * (NMAX / 16);
+  const size_t lds = (size_t)(2 * NR + 1) * lds_ld<TC>(NR) * sizeof(E);
+  auto kern = mode_gemm_plane<Tin, Tout, TC, NC>;
+  static int per_cu = 0;  // per instantiation: resident blocks per CU
+  if (per_cu == 0) {
+    if (lds > 65536)
+      HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds));
+    per_cu = std::max(nb, 1);
+  }
+  // persistent blocks, every block with the same number of planes (+-1)
+  int64_t grid = std::min<int64_t>(planes, (int64_t)per_cu * p->num_cu);
+  int64_t per = (planes + grid - 1) / grid;
+  grid = (planes + per - 1) / per;
+  ProfScope ps(p, STIG_K_PLANE_GEMM, (double)planes * n * n * (sizeof(Tin) + sizeof(Tout)));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, p->stream, in, out, opx, opy,
+                     n, planes);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tin, typename Tout, typename TC>
+stig_status launch_plane(stig_plan *p, const Tin *in, Tout *out,
+                         const typename Mfma<TC>::elem *opx, const typename Mfma<TC>::elem *opy,
+                         int n, int64_t planes) {
+  if (n < 1 || n > PLANE_MAX_N) return fail(STIG_EINVAL, "plane size out of range");
+  if (planes < 1) return STIG_OK;
+  if (n == 65) return launch_plane_nc<Tin, Tout, TC, 65>(p, in, out, opx, opy, n, planes);
+  if (n == 49) return launch_plane_nc<Tin, Tout, TC, 49>(p, in, out, opx, opy, n, planes);
+  return launch_plane_nc<Tin, Tout, TC, 0>(p, in, out, opx, opy, n, planes);
+}
+
 template <typename Tio, typename TC, int P>
 stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
   const TC *wb, *mb;
@@ -324,12 +391,55 @@ stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int
   return STIG_OK;
 }
 
+template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC>
+stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  // forward-substituted values (YREC false): in the output buffer when it has
+  // the compute type, else in compute-type scratch
+  TC *ysc = nullptr;
+  if (!YREC) {
+    if (std::is_same<Tio, TC>::value) ysc = (TC *)out;
+    else {
+      STIG_TRY(p->tscr.ensure((size_t)p->N * nrhs * sizeof(TC)));
+      ysc = p->tscr.as<TC>();
+    }
+  }
+  const TC *wb, *mb;
+  if (std::is_same<TC, double>::value) {
+    wb = (const TC *)(transpose ? p->tWT64.p : p->tW64.p);
+    mb = (const TC *)p->tM64.p;
+  } else {
+    wb = (const TC *)(transpose ? p->tWT32.p : p->tW32.p);
+    mb = (const TC *)p->tM32.p;
+  }
+  int64_t work = p->Ns * nrhs;
+  ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
+  const TC *rec = std::is_same<TC, double>::value ? (const TC *)p->tR64[transpose ? 1 : 0].p
+                                                  : (const TC *)p->tR32[transpose ? 1 : 0].p;
+  hipLaunchKernelGGL((time_band_solve_rl<Tio, TC, NT, P, NSEG, YREC>), dim3(grid_for(work, 256)),
+                     dim3(256), 0, p->stream, in, out, p->lam.as<double>(), rec, wb, mb,
+                     (TC)p->gamma, (TC)p->nu, p->Ns, nrhs, ysc, p->flag.as<int>());
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tio, typename TC, int NT, int P, int NSEG>
+stig_status launch_time_rl2(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  if (p->time_recompute) return launch_time_rl<Tio, TC, NT, P, NSEG, true>(p, in, out, nrhs, transpose);
+  return launch_time_rl<Tio, TC, NT, P, NSEG, false>(p, in, out, nrhs, transpose);
+}
+
 template <typename Tio, typename TC>
 stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
   // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
-  if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose);
-  if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose);
-  if (p->nt == 9 && p->pt == 2) return launch_time_reg<Tio, TC, 9, 2, 3>(p, in, out, nrhs, transpose);
+  if (p->time_kernel == 1) {
+    if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose);
+    if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose);
+    if (p->nt == 9 && p->pt == 2) return launch_time_reg<Tio, TC, 9, 2, 3>(p, in, out, nrhs, transpose);
+  } else if (p->time_kernel == 0) {
+    if (p->nt == 66 && p->pt == 3) return launch_time_rl2<Tio, TC, 66, 3, 7>(p, in, out, nrhs, transpose);
+    if (p->nt == 50 && p->pt == 3) return launch_time_rl2<Tio, TC, 50, 3, 6>(p, in, out, nrhs, transpose);
+    if (p->nt == 9 && p->pt == 2) return launch_time_rl2<Tio, TC, 9, 2, 2>(p, in, out, nrhs, transpose);
+  }
   STIG_TRY(p->tscr.ensure((size_t)(p->pt + 1) * p->N * nrhs * sizeof(TC)));
   switch (p->pt) {
     case 1: return launch_time_p<Tio, TC, 1>(p, in, out, nrhs, transpose);
@@ -360,7 +470,8 @@ template <typename TC> struct TimeCompute { typedef float type; };
 template <> struct TimeCompute<double> { typedef double type; };
 
 // Steps 2-4 of Algorithm 1 with storage type S for the intermediates and compute
-// type TC for the GEMMs.
+// type TC for the GEMMs.  Modes 1 and 2 go through the fused plane kernel when
+// they have the same size n <= PLANE_MAX_N and no diagonal scaling is set.
 template <typename S, typename TC>
 stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int transpose) {
   const int64_t tot = p->N * nrhs;
@@ -369,9 +480,20 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
   S *buf[2] = {p->s0.as<S>(), p->s1.as<S>()};
   int cur = 0;
   const double *scale = p->has_dmh ? p->dmh.as<double>() : nullptr;
+  const bool fuse = p->d >= 2 && p->n[0] == p->n[1] && p->n[0] <= PLANE_MAX_N && !scale &&
+                    p->plane_fusion;
   // step 2: forward spatial transform, X x_l U_l^T for l = 1..d
   int64_t inner = 1;
-  for (int l = 0; l < p->d; ++l) {
+  int l0 = 0;
+  if (fuse) {
+    int n = p->n[0];
+    STIG_TRY((launch_plane<double, S, TC>(p, r, buf[cur], OpSet<TC>::UT(p, 0), OpSet<TC>::UT(p, 1),
+                                           n, tot / ((int64_t)n * n))));
+    cur ^= 1;
+    inner = (int64_t)n * n;
+    l0 = 2;
+  }
+  for (int l = l0; l < p->d; ++l) {
     int n = p->n[l];
     int64_t cols = tot / n;
     if (l == 0)
@@ -389,7 +511,7 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
                                                             transpose)));
   cur ^= 1;
   // step 4: back transform, x_l U_l for l = d..1
-  for (int l = p->d - 1; l >= 0; --l) {
+  for (int l = p->d - 1; l >= l0; --l) {
     int n = p->n[l];
     inner /= n;
     int64_t cols = tot / n;
@@ -401,6 +523,11 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
                                             inner, cols, nullptr, nullptr)));
       cur ^= 1;
     }
+  }
+  if (fuse) {
+    int n = p->n[0];
+    STIG_TRY((launch_plane<S, double, TC>(p, buf[cur ^ 1], s, OpSet<TC>::U(p, 0), OpSet<TC>::U(p, 1),
+                                           n, tot / ((int64_t)n * n))));
   }
   return STIG_OK;
 }
@@ -716,11 +843,32 @@ stig_status stig_plan_create(stig_plan **out, int d, const int *n_s, int n_t, in
   p->pt = p_t;
   p->N = p->Ns * n_t;
   p->stream = (hipStream_t)stream;
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+    p->num_cu = cu;
+  (void)hipGetLastError();
   *out = p;
   return STIG_OK;
 }
 
 void stig_plan_destroy(stig_plan *plan) { delete plan; }
+
+stig_status stig_set_option(stig_plan *plan, int option, int value) {
+  STIG_TRY(check_plan(plan, false));
+  switch (option) {
+    case STIG_OPT_PLANE_FUSION:
+      if (value != 0 && value != 1) return fail(STIG_EINVAL, "plane fusion takes 0 or 1");
+      plan->plane_fusion = value != 0;
+      return STIG_OK;
+    case STIG_OPT_TIME_KERNEL:
+      if (value < 0 || value > 3) return fail(STIG_EINVAL, "time kernel takes 0 .. 3");
+      plan->time_kernel = value == 3 ? 0 : value;
+      plan->time_recompute = value != 3;
+      return STIG_OK;
+  }
+  return fail(STIG_EINVAL, "unknown option");
+}
 
 stig_status stig_set_stream(stig_plan *plan, void *stream) {
   STIG_TRY(check_plan(plan, false));
@@ -799,6 +947,11 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
   STIG_TRY(upload(p->tW32, convert<float>(wb), s));
   STIG_TRY(upload(p->tWT32, convert<float>(wtb), s));
   STIG_TRY(upload(p->tM32, convert<float>(mb), s));
+  for (int tr = 0; tr < 2; ++tr) {
+    std::vector<double> rec = step_records(tr ? wtb : wb, mb, nt, P);
+    STIG_TRY(upload(p->tR64[tr], rec, s));
+    STIG_TRY(upload(p->tR32[tr], convert<float>(rec), s));
+  }
   std::vector<double> gw(wb), gwt(wtb), nm(mb);
   for (auto &v : gw) v *= gamma;
   for (auto &v : gwt) v *= gamma;
@@ -1097,6 +1250,7 @@ size_t stig_plan_device_bytes(const stig_plan *p) {
   if (!p) return 0;
   size_t t = 0;
   const DevBuf *bs[] = {&p->lam, &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
+                        &p->tR64[0], &p->tR64[1], &p->tR32[0], &p->tR32[1],
                         &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->s0, &p->s1, &p->tscr, &p->m0,
                         &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->w, &p->tmp, &p->partial,
                         &p->small, &p->flag, &p->lift0, &p->lift1};

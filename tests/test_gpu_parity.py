@@ -49,6 +49,54 @@ def test_apply_pinv_fp64_matches_oracle(name, n_el, transpose):
         assert _relmax(s[b], ref) <= 1e-12
 
 
+@pytest.mark.parametrize("n_el", [5, 14, 48, 64])
+def test_fused_plane_products_match_per_mode_passes(n_el):
+    """apply_Pinv with the fused mode-1/mode-2 plane kernel against one pass per
+    mode and against the oracle: n_s = 6, 15 (runtime size, zero padded), 49 and
+    65 (compile-time sizes 16q + 1 with vector-ALU fringes), every precision."""
+    w, fac, plan, pr = _setup("cube_p3_n64", n_el)
+    nrhs = 2 if n_el < 64 else 1
+    r = wl.random_tensor((nrhs,) + w.shape, 11)
+    rd = _dev(r)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, w.gamma, w.nu)
+    ref = np.stack([P.apply(r[b]) for b in range(nrhs)])
+    for prec in ("fp64", "fp32", "bf16"):
+        plan.set_plane_fusion(True)
+        sf = plan.apply_Pinv(rd, prec=prec).cpu().numpy()
+        plan.set_plane_fusion(False)
+        su = plan.apply_Pinv(rd, prec=prec).cpu().numpy()
+        plan.set_plane_fusion(True)
+        ef = np.linalg.norm(sf - ref) / np.linalg.norm(ref)
+        eu = np.linalg.norm(su - ref) / np.linalg.norm(ref)
+        if prec == "fp64":
+            assert _relmax(sf, ref) <= 1e-12 and _relmax(su, ref) <= 1e-12
+        else:
+            # same rounding points (intermediates stored / fed to MFMA in the
+            # low precision): the fused pass is no less accurate
+            assert ef <= 1.5 * eu + (1e-7 if prec == "fp32" else 1e-4), (prec, ef, eu)
+            assert ef <= (1e-5 if prec == "fp32" else 5e-2), (prec, ef)
+
+
+@pytest.mark.parametrize("name,n_el", [("square_p2_n8", None), ("cube_p3_n64", 48),
+                                        ("cube_p3_n64", 64)])
+@pytest.mark.parametrize("kernel", ["right_looking", "right_looking_stored", "left_looking",
+                                    "generic"])
+def test_time_kernels_match_oracle(name, n_el, kernel):
+    """Every elimination form of the shifted time systems (n_t = 9, 50, 66 have
+    register-resident kernels), plain and transposed, FP64 and FP32 compute."""
+    w, fac, plan, pr = _setup(name, n_el)
+    plan.set_option("time_kernel", kernel)
+    r = wl.random_tensor(w.shape, 13)
+    rd = _dev(r)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, w.gamma, w.nu)
+    for transpose in (False, True):
+        ref = P.apply(r, transpose=transpose)
+        s = plan.apply_Pinv(rd, transpose=transpose).cpu().numpy()
+        assert _relmax(s, ref) <= 1e-12, (kernel, transpose)
+        s32 = plan.apply_Pinv(rd, transpose=transpose, prec="fp32").cpu().numpy()
+        assert np.linalg.norm(s32 - ref) / np.linalg.norm(ref) <= 1e-5, (kernel, transpose)
+
+
 def test_apply_pinv_matches_dense_solve_tiny():
     w, fac, plan, pr = _setup("cube_p3_n64", 3)
     A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d)

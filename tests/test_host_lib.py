@@ -88,5 +88,11 @@ def test_argument_validation_without_gpu():
     assert lib.stig_apply_Pinv(h, C.c_void_p(8), C.c_void_p(16), 1, 0, 0) == -6
     assert b"setup" in lib.stig_last_error()
     assert lib.stig_gmres_solve(h, None, None, 1, 30, 1e-8, 10, 0, 0, 0, None) == -6
+    # kernel options: known values accepted, anything else rejected
+    assert lib.stig_set_option(h, 0, 0) == 0 and lib.stig_set_option(h, 0, 1) == 0
+    assert lib.stig_set_option(h, 0, 2) == -1
+    assert all(lib.stig_set_option(h, 1, v) == 0 for v in (0, 1, 2, 3))
+    assert lib.stig_set_option(h, 1, 4) == -1 and lib.stig_set_option(h, 1, -1) == -1
+    assert lib.stig_set_option(h, 7, 0) == -1
     lib.stig_plan_destroy(h)
     assert lib.stig_status_string(-4) == b"breakdown (non-positive pivot)"
