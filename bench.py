@@ -55,7 +55,8 @@ def cpu_baseline(w, f_host, target_s=12.0):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fd_apply_cube_p3_n64.json")
-KERNEL_SOURCES = ["paper_1909_07309_amd/csrc/kernels_fd.h", "paper_1909_07309_amd/csrc/stig.hip"]
+KERNEL_SOURCES = ["paper_1909_07309_amd/csrc/kernels_fd.h", "paper_1909_07309_amd/csrc/kernels_plane.h",
+                  "paper_1909_07309_amd/csrc/stig.hip"]
 
 
 def kernel_fingerprint():
@@ -153,33 +154,59 @@ def main():
             plan.profile_enable(False)
         return dt, prof
 
-    # ---- FP64 apply: the headline (event timing of each kernel over the same region)
-    dt, prof = timed_applies("fp64", args.steps, args.warmup, profile=True)
+    # ---- FP64 apply: the headline, timed without per-kernel events; then the
+    # same number of applies again with an event pair around every launch for
+    # the per-kernel breakdown and the roofline of the dominant kernel
+    dt, _ = timed_applies("fp64", args.steps, args.warmup)
     ms_per_step = dt / args.steps * 1e3
     value = w.N * args.steps / dt
     log(f"[bench] fp64 apply {ms_per_step:.3f} ms  {value:.3e} DoF/s")
-    kernels = {k: {"ms_per_launch": v[0] / v[2], "launches_per_step": v[2] / args.steps,
-                   "share": v[0] / sum(x[0] for x in prof.values()),
-                   "GBps": v[1] / (v[0] * 1e-3) / 1e9}
-               for k, v in prof.items() if v[2]}
+    _, prof = timed_applies("fp64", args.steps, 1, profile=True)
+    # algorithmic FP64 flops per unknown of one launch of each kernel class:
+    # a mode product is a length-n dot product per output (2n), the fused
+    # plane kernel does two of them (4n); the banded solve is counted as the
+    # elimination with precomputed factors (4 p_t + 1, negligible: HBM-bound)
+    flops_per_dof = {"mode_gemm": 2 * w.n_s, "plane_gemm": 4 * w.n_s, "time_solve": 4 * w.p + 1}
+    kernels = {}
+    for k, v in prof.items():
+        if not v[2]:
+            continue
+        ms_l, by_l = v[0] / v[2], v[1] / v[2]
+        fl_l = flops_per_dof.get(k, 0) * w.N
+        # the bound is the larger of the two time floors at peak
+        t_hbm, t_mfma = by_l / (HBM_PEAK_GBS * 1e9), fl_l / (FP64_PEAK_TFLOPS * 1e12)
+        kernels[k] = {"ms_per_launch": ms_l, "launches_per_step": v[2] / args.steps,
+                      "share": v[0] / sum(x[0] for x in prof.values()),
+                      "bytes_per_launch": by_l, "flops_per_launch": fl_l,
+                      "GBps": by_l / (ms_l * 1e-3) / 1e9,
+                      "TFLOPs": fl_l / (ms_l * 1e-3) / 1e12,
+                      "bound": "mfma" if t_mfma > t_hbm else "hbm"}
     dom = max(kernels, key=lambda k: kernels[k]["share"])
-    ms_l, by_l = prof[dom][0] / prof[dom][2], prof[dom][1] / prof[dom][2]
-    achieved = by_l / (ms_l * 1e-3) / 1e9
+    kd = kernels[dom]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         t = json.load(open(TRAFFIC_FILE))
         if t.get("fingerprint") == kernel_fingerprint():
-            # the dominant class's kernels at this workload's FP64 launch shape
+            # the dominant class's kernel at this workload's FP64 launch shape
             key = {"mode_gemm": "stig::mode_gemm_small<double, double, double, 65>",
-                   "time_solve": "stig::time_band_solve_reg<double, double, 66, 3, 11, false>"}.get(dom)
+                   "plane_gemm": "stig::mode_gemm_plane<double, double, double, 65>",
+                   "time_solve": "stig::time_band_solve_rl<double, double, 66, 3, 7, true>"}.get(dom)
             k = t["kernels"].get(key)
             if k:
                 traffic = k["fetch_bytes"] + k["write_bytes"]
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_launch": by_l, "ms_per_launch": ms_l}
+    if kd["bound"] == "mfma":
+        roofline = {"kernel": dom, "bound": "mfma", "achieved": kd["TFLOPs"],
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": kd["TFLOPs"] / FP64_PEAK_TFLOPS, "traffic": traffic,
+                    "flops_per_launch": kd["flops_per_launch"],
+                    "bytes_per_launch": kd["bytes_per_launch"], "ms_per_launch": kd["ms_per_launch"],
+                    "hbm_GBps": kd["GBps"]}
+    else:
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                    "bytes_per_launch": kd["bytes_per_launch"], "ms_per_launch": kd["ms_per_launch"]}
     # whole-apply view: FP64 flops 4*d*n_s per unknown for the transforms (+ time solves)
-    flops = (4 * w.d * w.n_s + 8 * w.p + 2) * w.N
+    flops = (4 * w.d * w.n_s + 4 * w.p + 1) * w.N
     apply_tflops = flops / (ms_per_step * 1e-3) / 1e12
 
     # ---- mixed-precision applies
