@@ -95,8 +95,12 @@ stig_status stig_set_stream(stig_plan *plan, void *stream);
  *     stored); 3 = the same with the forward-substituted values stored and read
  *     back; 1 = left-looking, U-row checkpoints; 2 = the generic kernel with
  *     scratch memory (the one every other shape uses).
+ *   STIG_OPT_PARITY_SPLIT: 1 (default) = where a spatial pencil is
+ *     persymmetric (stig_setup_1d_pencils then picks an eigenbasis of even and
+ *     odd modes), its mode products run as two half-size products around a
+ *     butterfly (sizes n_s = 32, 33, 64, 65); 0 = dense products.
  * Unknown options or values: STIG_EINVAL. */
-enum { STIG_OPT_PLANE_FUSION = 0, STIG_OPT_TIME_KERNEL = 1 };
+enum { STIG_OPT_PLANE_FUSION = 0, STIG_OPT_TIME_KERNEL = 1, STIG_OPT_PARITY_SPLIT = 2 };
 stig_status stig_set_option(stig_plan *plan, int option, int value);
 
 /* ------------------------------------------------------------------ setup */
@@ -297,6 +301,15 @@ stig_status stig_load_1d(int n_el, int p, double length, const double *fvals,
  * setup uses; exposed for testing. */
 stig_status stig_sym_eig(int n, const double *K, const double *M, double *U,
                          double *lam);
+
+/* The same eigenproblem for a persymmetric pencil (K[n-1-i][n-1-j] = K[i][j],
+ * likewise M, to 1e-13 relative), solved as two half-size pencils on the even
+ * and odd vectors: columns 0 .. n/2 + n%2 - 1 of U are even (U[n-1-x][k] =
+ * U[x][k]), the rest odd (U[n-1-x][k] = -U[x][k]), eigenvalues ascending within
+ * each group.  The basis stig_setup_1d_pencils uses for persymmetric factors;
+ * exposed for testing.  STIG_EINVAL if the pencil is not persymmetric. */
+stig_status stig_split_eig(int n, const double *K, const double *M, double *U,
+                           double *lam);
 
 const char *stig_status_string(stig_status status);
 const char *stig_last_error(void);

@@ -172,13 +172,14 @@ class Plan:
 
     KERNEL_KINDS = ("mode_gemm", "time_solve", "band_pass", "krylov", "csr", "plane_gemm")
 
-    OPTIONS = {"plane_fusion": 0, "time_kernel": 1}
+    OPTIONS = {"plane_fusion": 0, "time_kernel": 1, "parity_split": 2}
     TIME_KERNELS = {"right_looking": 0, "left_looking": 1, "generic": 2, "right_looking_stored": 3}
 
     def set_option(self, name, value):
         """Kernel choices of apply_Pinv (same results up to rounding order):
         plane_fusion (bool, default True), time_kernel ("right_looking" default,
-        "right_looking_stored", "left_looking", "generic")."""
+        "right_looking_stored", "left_looking", "generic"), parity_split (bool,
+        default True)."""
         if name == "time_kernel" and isinstance(value, str):
             value = self.TIME_KERNELS[value]
         check(lib().stig_set_option(self._h, self.OPTIONS[name], int(value)))
@@ -296,4 +297,15 @@ def sym_eig(K, M):
     U = np.empty((n, n))
     lam = np.empty(n)
     check(lib().stig_sym_eig(n, dptr(K), dptr(M), dptr(U), dptr(lam)))
+    return lam, U
+
+
+def split_eig(K, M):
+    """Eigenbasis of a persymmetric pencil, even modes first (see stig_split_eig)."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = K.shape[0]
+    U = np.empty((n, n))
+    lam = np.empty(n)
+    check(lib().stig_split_eig(n, dptr(K), dptr(M), dptr(U), dptr(lam)))
     return lam, U

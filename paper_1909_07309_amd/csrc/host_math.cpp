@@ -366,4 +366,62 @@ bool sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
   return true;
 }
 
+bool persymmetric(int n, const double *A, double tol) {
+  double amax = 0.0, dmax = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      amax = std::max(amax, std::abs(A[(size_t)i * n + j]));
+      dmax = std::max(dmax, std::abs(A[(size_t)i * n + j] - A[(size_t)(n - 1 - i) * n + (n - 1 - j)]));
+    }
+  return dmax <= tol * amax;
+}
+
+// Parity-split eigenbasis of a persymmetric pencil.  With the orthonormal
+// even / odd bases q_x = (e_x +- e_{n-1-x}) / sqrt(2) (x < m = n/2) and, for odd
+// n, the middle unit vector e_m (even), K and M become block diagonal; each
+// block is a symmetric definite pencil of its own.  Their eigenvectors, mapped
+// back, are eigenvectors of (K, M) that are exactly even or odd.
+bool split_eig(int n, const double *K, const double *M, double *U, double *lam) {
+  const int m = n / 2, odd = n & 1, ne = m + odd;
+  const double h = 1.0 / std::sqrt(2.0);
+  auto block = [&](const double *A, bool even, std::vector<double> &B) {
+    const int nb = even ? ne : m;
+    B.assign((size_t)nb * nb, 0.0);
+    const double sg = even ? 1.0 : -1.0;
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) {
+        const bool mi = odd && even && i == m, mj = odd && even && j == m;
+        double v;
+        if (mi && mj) v = A[(size_t)m * n + m];
+        else if (mi) v = h * (A[(size_t)m * n + j] + A[(size_t)m * n + (n - 1 - j)]);
+        else if (mj) v = h * (A[(size_t)i * n + m] + A[(size_t)(n - 1 - i) * n + m]);
+        else
+          v = 0.5 * (A[(size_t)i * n + j] + sg * A[(size_t)i * n + (n - 1 - j)] +
+                     sg * A[(size_t)(n - 1 - i) * n + j] + A[(size_t)(n - 1 - i) * n + (n - 1 - j)]);
+        B[(size_t)i * nb + j] = v;
+      }
+  };
+  std::vector<double> Ke, Me, Ko, Mo, Ve((size_t)ne * ne), Vo((size_t)m * m);
+  block(K, true, Ke);
+  block(M, true, Me);
+  block(K, false, Ko);
+  block(M, false, Mo);
+  if (!sym_eig(ne, Ke.data(), Me.data(), Ve.data(), lam)) return false;
+  if (m > 0 && !sym_eig(m, Ko.data(), Mo.data(), Vo.data(), lam + ne)) return false;
+  std::fill(U, U + (size_t)n * n, 0.0);
+  for (int k = 0; k < ne; ++k) {
+    for (int x = 0; x < m; ++x) {
+      U[(size_t)x * n + k] = h * Ve[(size_t)x * ne + k];
+      U[(size_t)(n - 1 - x) * n + k] = h * Ve[(size_t)x * ne + k];
+    }
+    if (odd) U[(size_t)m * n + k] = Ve[(size_t)m * ne + k];
+  }
+  for (int k = 0; k < m; ++k)
+    for (int x = 0; x < m; ++x) {
+      U[(size_t)x * n + ne + k] = h * Vo[(size_t)x * m + k];
+      U[(size_t)(n - 1 - x) * n + ne + k] = -h * Vo[(size_t)x * m + k];
+    }
+  return true;
+}
+
 }  // namespace stig

@@ -1,0 +1,359 @@
+// Fused x/y mode products with parity-split eigenbases in both directions.
+//
+// With n = 2M + ODD, NE = M + ODD, and the even modes of a direction before
+// its odd ones (see kernels_sym.h), the two-sided product of an n x n plane
+// decouples into four quadrants after a two-dimensional butterfly:
+//   forward  Y_ab = (U^a_y)^T B_ab U^b_x,  a, b in {even, odd},
+//            B_ab[y][x] = X[y][x] +-_b X[y][n-1-x] +-_a X[n-1-y][x] +-_ab X[n-1-y][n-1-x]
+//            (half coordinates y, x; on the middle row / column the mirror image
+//            is the point itself and is counted once),
+//   backward Z_ab = U^a_y Y_ab (U^b_x)^T, then X at the four mirror points is
+//            the signed sum of the four Z_ab at the half coordinates.
+// Each of the four waves of a block transforms one quadrant (sizes NE or M per
+// side): half the multiply-adds of the dense fused plane kernel.  The plane is
+// loaded orbit by orbit (the four mirror points of a half coordinate) so that
+// the butterfly happens in registers on the way into LDS.
+#pragma once
+
+#include "kernels_plane.h"
+
+namespace stig {
+
+// One quadrant: Out = OpY In OpX^T with In (16Q+RY) x (16Q+RX), OpX
+// (16Q+RX)^2 and OpY (16Q+RY)^2 in LDS (leading dimensions ldi, ldo, ldo).
+// store(row, col, value) receives every output entry.
+template <typename TC, int Q, int RY, int RX, typename StoreF>
+__device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi,
+                                      const typename Mfma<TC>::elem *opx,
+                                      const typename Mfma<TC>::elem *opy, int ldo, int c, int g,
+                                      StoreF store) {
+  typedef Mfma<TC> MF;
+  typedef typename MF::elem E;
+  typedef PlaneVal<TC> PV;
+  typedef typename PV::vt VT;
+  constexpr int KSTEP = MF::KSTEP, KPL = MF::KPL, KS = 16 * Q / KSTEP, SPT = 16 / KSTEP;
+  auto xor_sum = [](VT x) {
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+  };
+  const E *oxrow = opx + 16 * Q * ldo;  // RX: row 16Q of OpX
+  VT bxf[Q];                            // RX: column 16Q of OpX, rows 16j + c
+  VT oxff = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) bxf[j] = 0;
+  if constexpr (RX != 0) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) bxf[j] = PV::of(opx[(16 * j + c) * ldo + 16 * Q]);
+    oxff = PV::of(oxrow[16 * Q]);
+  }
+  // ---- product 1, every strip: Z[y][16j + c] for y < 16Q
+  typename MF::acc acc1[Q][Q];  // [strip j][row tile T]
+  VT zp[Q];                     // RX: partial sums of Z[16T + c][16Q]
+#pragma unroll
+  for (int T = 0; T < Q; ++T) {
+    zp[T] = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc1[j][T][v] = 0;
+        if constexpr (RX != 0)  // contraction index 16Q: rank-one start
+          acc1[j][T][v] = PV::of(in[(16 * T + MF::out_row(g, v)) * ldi + 16 * Q]) * bxf[j];
+      }
+  }
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    VT of[KPL];
+    if constexpr (RX != 0) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) of[u] = PV::of(oxrow[s * KSTEP + g * KPL + u]);
+    }
+    typename MF::frag bq[Q];  // B fragments of OpX rows 16j + c
+#pragma unroll
+    for (int j = 0; j < Q; ++j) bq[j] = MF::load(opx + (16 * j + c) * ldo + s * KSTEP + g * KPL);
+#pragma unroll
+    for (int T = 0; T < Q; ++T) {
+      typename MF::frag a = MF::load(in + (16 * T + c) * ldi + s * KSTEP + g * KPL);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) acc1[j][T] = MF::mma(a, bq[j], acc1[j][T]);
+      if constexpr (RX != 0) {
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) zp[T] += PV::get(a, u) * of[u];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // fringe of product 1: row 16Q of Z (zr, RY), column 16Q (zc via zp, RX),
+  // corner (zcc, RX and RY)
+  VT zr[Q], zcc = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) zr[j] = 0;
+  if constexpr (RY != 0) {
+    VT zc2 = 0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) {
+        const VT xv = PV::of(in[16 * Q * ldi + s * KSTEP + g * KPL + u]);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) zr[j] += xv * PV::of(opx[(16 * j + c) * ldo + s * KSTEP + g * KPL + u]);
+        if constexpr (RX != 0) zc2 += xv * PV::of(oxrow[s * KSTEP + g * KPL + u]);
+      }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) zr[j] = xor_sum(zr[j]);
+    if constexpr (RX != 0) {
+      const VT x64 = PV::of(in[16 * Q * ldi + 16 * Q]);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) zr[j] += x64 * bxf[j];
+      zcc = xor_sum(zc2) + x64 * oxff;
+    }
+  }
+  if constexpr (RX != 0) {
+#pragma unroll
+    for (int T = 0; T < Q; ++T) zp[T] = xor_sum(zp[T]) + PV::of(in[(16 * T + c) * ldi + 16 * Q]) * oxff;
+  }
+  // ---- product 2, strip by strip: Out = OpY Z
+  VT yc[Q], ycc = 0;  // RX: output column 16Q (rows 16t + c), corner
+#pragma unroll
+  for (int t = 0; t < Q; ++t) yc[t] = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    typename MF::acc acc2[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc2[t][v] = 0;
+        if constexpr (RY != 0)
+          acc2[t][v] = PV::of(opy[(16 * t + MF::out_row(g, v)) * ldo + 16 * Q]) * zr[j];
+      }
+    VT yr = 0;  // RY: output row 16Q of this strip
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int T = s / SPT, v0 = (s % SPT) * KPL;
+      E be[KPL];
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) be[u] = PV::to_elem(acc1[j][T][v0 + u]);
+      typename MF::frag b = MF::make(be);
+      const int kcol = 16 * T + MF::out_row(g, v0);  // contraction index of slot u: kcol + u
+      VT zc[KPL];
+      if constexpr (RX != 0) {
+        if (j == 0) {
+#pragma unroll
+          for (int u = 0; u < KPL; ++u) zc[u] = __shfl(zp[T], MF::out_row(g, v0 + u), 64);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        typename MF::frag a = MF::load(opy + (16 * t + c) * ldo + kcol);
+        acc2[t] = MF::mma(a, b, acc2[t]);
+        if constexpr (RX != 0) {
+          if (j == 0) {
+#pragma unroll
+            for (int u = 0; u < KPL; ++u) yc[t] += PV::get(a, u) * zc[u];
+          }
+        }
+      }
+      if constexpr (RY != 0) {
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) {
+          const VT oy = PV::of(opy[16 * Q * ldo + kcol + u]);
+          yr += oy * PV::of(be[u]);
+          if constexpr (RX != 0) {
+            if (j == 0) ycc += oy * zc[u];
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int t = 0; t < Q; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) store(16 * t + MF::out_row(g, v), 16 * j + c, (VT)acc2[t][v]);
+    if constexpr (RY != 0) {
+      yr = xor_sum(yr) + PV::of(opy[16 * Q * ldo + 16 * Q]) * zr[j];
+      if (g == 0) store(16 * Q, 16 * j + c, yr);
+    }
+  }
+  if constexpr (RX != 0) {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      VT y = xor_sum(yc[t]);
+      if constexpr (RY != 0) y += PV::of(opy[(16 * t + c) * ldo + 16 * Q]) * zcc;
+      if (g == 0) store(16 * t + c, 16 * Q, y);
+    }
+    if constexpr (RY != 0) {
+      ycc = xor_sum(ycc) + PV::of(opy[16 * Q * ldo + 16 * Q]) * zcc;
+      if (g == 0 && c == 0) store(16 * Q, 16 * Q, ycc);
+    }
+  }
+}
+
+// LDS leading dimensions: quadrant columns start at 0 (even) and PS_COLO (odd,
+// rounded up so that bf16 fragments stay 8-byte aligned).
+template <int M, bool ODD> struct PlaneSymDims {
+  static constexpr int NE = M + (ODD ? 1 : 0), N = 2 * M + (ODD ? 1 : 0);
+  static constexpr int COLO = (NE + 3) / 4 * 4;
+};
+template <typename TC, int M, bool ODD> __host__ __device__ constexpr int plane_sym_ldp() {
+  // odd stride in 4/8-byte words, a multiple of 4 elements for bf16
+  return sizeof(typename Mfma<TC>::elem) >= 4 ? ((PlaneSymDims<M, ODD>::COLO + M) | 1)
+                                              : (PlaneSymDims<M, ODD>::COLO + M + 4);
+}
+template <typename TC, int M, bool ODD> __host__ __device__ constexpr int plane_sym_ldo() {
+  return sizeof(typename Mfma<TC>::elem) >= 4 ? (PlaneSymDims<M, ODD>::NE | 1)
+                                              : ((PlaneSymDims<M, ODD>::NE + 3) / 4 * 4 + 4);
+}
+// LDS layout of mode_gemm_plane_sym: plane, OpY halves, OpX halves and, for
+// the backward pass when the accumulator is wider than the element, an
+// accumulator-precision copy of the quadrant results (16-byte aligned).
+template <typename TC, int M, bool ODD> __host__ __device__ constexpr size_t plane_sym_zoff() {
+  typedef PlaneSymDims<M, ODD> D;
+  return ((size_t)(D::N * plane_sym_ldp<TC, M, ODD>() + 2 * D::N * plane_sym_ldo<TC, M, ODD>()) *
+              sizeof(typename Mfma<TC>::elem) + 15) / 16 * 16;
+}
+template <typename TC, int M, bool ODD, bool FWD> __host__ __device__ constexpr size_t plane_sym_lds() {
+  typedef PlaneSymDims<M, ODD> D;
+  return plane_sym_zoff<TC, M, ODD>() +
+         ((!FWD && sizeof(typename Mfma<TC>::acc_elem) != sizeof(typename Mfma<TC>::elem))
+              ? (size_t)D::N * plane_sym_ldp<TC, M, ODD>() * sizeof(typename Mfma<TC>::acc_elem)
+              : 0);
+}
+
+// FWD: out = modal planes (even modes first along both axes) of the physical
+// planes in `in`; !FWD: the reverse.  opx*/opy*: half operators of directions
+// x and y (FWD: rows of U^T; !FWD: rows of U), even (NE x NE) and odd (M x M).
+// Block = 4 waves (one quadrant each); persistent over planes, the next
+// plane's loads in flight while the current one is transformed.
+template <typename Tin, typename Tout, typename TC, int M, bool ODD, bool FWD>
+__global__ void __launch_bounds__(256, 2)
+mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
+                    const typename Mfma<TC>::elem *__restrict__ opxE,
+                    const typename Mfma<TC>::elem *__restrict__ opxO,
+                    const typename Mfma<TC>::elem *__restrict__ opyE,
+                    const typename Mfma<TC>::elem *__restrict__ opyO, int64_t planes) {
+  typedef Mfma<TC> MF;
+  typedef typename MF::elem E;
+  typedef PlaneVal<TC> PV;
+  typedef typename PV::vt VT;
+  typedef typename MF::acc_elem AE;
+  typedef PlaneSymDims<M, ODD> D;
+  constexpr int NE = D::NE, N = D::N, COLO = D::COLO, Q = M / 16;
+  constexpr int KSTEP = MF::KSTEP, KPL = MF::KPL, KS = 16 * Q / KSTEP;
+  constexpr int LDP = plane_sym_ldp<TC, M, ODD>(), LDO = plane_sym_ldo<TC, M, ODD>();
+  constexpr int NT = 256;
+  constexpr int NORB = NE * NE;                  // orbits (forward loads)
+  constexpr int PER = FWD ? (NORB + NT - 1) / NT : (N * N + NT - 1) / NT;
+  constexpr int NLD = FWD ? 4 : 1;               // loads per item
+  static_assert(M % 16 == 0, "half size must be a multiple of 16");
+  extern __shared__ __align__(16) unsigned char smem[];
+  E *pl = reinterpret_cast<E *>(smem);           // [N][LDP] quadrant layout
+  E *oy = pl + N * LDP;                          // OpY even [NE][LDO], then odd [M][LDO]
+  E *ox = oy + N * LDO;                          // OpX likewise
+  AE *zb = (!FWD && sizeof(AE) != sizeof(E)) ? reinterpret_cast<AE *>(smem + plane_sym_zoff<TC, M, ODD>())
+                                             : reinterpret_cast<AE *>(pl);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int qa = w >> 1, qb = w & 1;  // quadrant: y parity, x parity (0 even)
+
+  for (int e = tid; e < NE * NE; e += NT) {
+    oy[(e / NE) * LDO + e % NE] = opyE[e];
+    ox[(e / NE) * LDO + e % NE] = opxE[e];
+  }
+  for (int e = tid; e < M * M; e += NT) {
+    oy[(NE + e / M) * LDO + e % M] = opyO[e];
+    ox[(NE + e / M) * LDO + e % M] = opxO[e];
+  }
+
+  // ---- plane loads: FWD orbit by orbit (four mirror points), !FWD plain
+  Tin pre[PER][NLD];
+  auto gload = [&](int64_t p) {
+    const bool pv = p < planes;
+    const Tin *src = in + (pv ? p : 0) * (int64_t)(N * N);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (FWD) {
+        const bool ok = pv && e < NORB;
+        const int yh = ok ? e / NE : 0, xh = ok ? e - (e / NE) * NE : 0;
+        const int y2 = N - 1 - yh, x2 = N - 1 - xh;
+        pre[i][0] = src[yh * N + xh];
+        pre[i][NLD > 1 ? 1 : 0] = src[yh * N + x2];
+        pre[i][NLD > 2 ? 2 : 0] = src[y2 * N + xh];
+        pre[i][NLD > 3 ? 3 : 0] = src[y2 * N + x2];
+      } else {
+        pre[i][0] = src[(pv && e < N * N) ? e : 0];
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (FWD) {
+        if (e < NORB) {
+          const int yh = e / NE, xh = e - yh * NE;
+          const bool xm = ODD && xh == M, ym = ODD && yh == M;  // middle column / row
+          const double a = Conv<Tin>::to_f64(pre[i][0]), b = Conv<Tin>::to_f64(pre[i][NLD > 1 ? 1 : 0]);
+          const double cc = Conv<Tin>::to_f64(pre[i][NLD > 2 ? 2 : 0]);
+          const double d = Conv<Tin>::to_f64(pre[i][NLD > 3 ? 3 : 0]);
+          const double e1 = xm ? a : a + b, o1 = a - b;   // row yh
+          const double e2 = xm ? cc : cc + d, o2 = cc - d;  // row N-1-yh
+          pl[yh * LDP + xh] = MF::from_f64(ym ? e1 : e1 + e2);
+          if (!xm) pl[yh * LDP + COLO + xh] = MF::from_f64(ym ? o1 : o1 + o2);
+          if (!ym) pl[(NE + yh) * LDP + xh] = MF::from_f64(e1 - e2);
+          if (!xm && !ym) pl[(NE + yh) * LDP + COLO + xh] = MF::from_f64(o1 - o2);
+        }
+      } else if (e < N * N) {
+        const int ky = e / N, kx = e - ky * N;
+        pl[ky * LDP + (kx < NE ? kx : COLO + kx - NE)] = MF::from_f64(Conv<Tin>::to_f64(pre[i][0]));
+      }
+    }
+  };
+
+  int64_t p = blockIdx.x;
+  gload(p);
+  __syncthreads();  // operators in LDS
+  lstore();
+  __syncthreads();
+  for (; p < planes; p += gridDim.x) {
+    gload(p + gridDim.x);
+    const E *inq = pl + (qa ? NE : 0) * LDP + (qb ? COLO : 0);
+    const E *opyq = oy + (qa ? NE : 0) * LDO, *opxq = ox + (qb ? NE : 0) * LDO;
+    Tout *dst = out + p * (int64_t)(N * N);
+    const int r0 = qa ? NE : 0, c0 = qb ? NE : 0, cl0 = qb ? COLO : 0;
+    auto store = [&](int row, int col, VT v) {
+      if (FWD) dst[(r0 + row) * N + c0 + col] = Conv<Tout>::from_f64((double)v);
+      else zb[(r0 + row) * LDP + cl0 + col] = (AE)v;
+    };
+    switch (w) {  // wave-uniform
+      case 0: quad_transform<TC, Q, ODD ? 1 : 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+      case 1: quad_transform<TC, Q, ODD ? 1 : 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+      case 2: quad_transform<TC, Q, 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+      default: quad_transform<TC, Q, 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+    }
+    __syncthreads();  // every quadrant done
+    if (!FWD) {
+      // X at the four mirror points of each half coordinate
+      for (int e = tid; e < NORB; e += NT) {
+        const int yh = e / NE, xh = e - yh * NE;
+        const bool xm = ODD && xh == M, ym = ODD && yh == M;
+        const double zee = (double)zb[yh * LDP + xh];
+        const double zeo = xm ? 0.0 : (double)zb[yh * LDP + COLO + xh];
+        const double zoe = ym ? 0.0 : (double)zb[(NE + yh) * LDP + xh];
+        const double zoo = (xm || ym) ? 0.0 : (double)zb[(NE + yh) * LDP + COLO + xh];
+        const int y2 = N - 1 - yh, x2 = N - 1 - xh;
+        dst[yh * N + xh] = Conv<Tout>::from_f64((zee + zoe) + (zeo + zoo));
+        if (!xm) dst[yh * N + x2] = Conv<Tout>::from_f64((zee + zoe) - (zeo + zoo));
+        if (!ym) dst[y2 * N + xh] = Conv<Tout>::from_f64((zee - zoe) + (zeo - zoo));
+        if (!xm && !ym) dst[y2 * N + x2] = Conv<Tout>::from_f64((zee - zoe) - (zeo - zoo));
+      }
+      if ((void *)zb == (void *)pl) __syncthreads();  // the results alias the plane
+    }
+    lstore();         // next plane into LDS (waits for its loads)
+    __syncthreads();  // ... visible to every wave
+  }
+}
+
+}  // namespace stig

@@ -17,6 +17,8 @@
 #include "kernels_krylov.h"
 #include "kernels_matvec.h"
 #include "kernels_plane.h"
+#include "kernels_sym.h"
+#include "kernels_plane_sym.h"
 #include "stig_internal.h"
 
 using namespace stig;
@@ -89,6 +91,11 @@ struct stig_plan {
   double gamma = 1.0, nu = 1.0;
   // eigenvectors: [l] -> U_l and U_l^T in FP64, FP32, BF16 (row-major n x n)
   DevBuf U64[3], UT64[3], U32[3], UT32[3], U16[3], UT16[3];
+  // parity-split eigenbasis (persymmetric pencils): half operators per
+  // precision [0 f64, 1 f32, 2 bf16] and direction, forward (rows of U^T) and
+  // backward (rows of U), even (NE x NE) and odd (M x M) halves
+  bool split[3] = {false, false, false};
+  DevBuf hFE[3][3], hFO[3][3], hBE[3][3], hBO[3][3];
   DevBuf lam;            // Ns doubles: lambda_k = sum_l lambda_{l,i_l}
   DevBuf tW64, tWT64, tM64, tW32, tWT32, tM32;  // time bands (unscaled)
   DevBuf tR64[2], tR32[2];  // step records of [W; M] and [W^T; M] (right-looking solve)
@@ -100,6 +107,7 @@ struct stig_plan {
   bool has_dmh = false;
   bool plane_fusion = true;  // fused x/y products in the FD apply
   int time_kernel = 0;        // 0 right-looking, 1 left-looking register form, 2 generic
+  bool parity_split = true;   // half-size mode products where the basis is split
   bool time_recompute = true; // right-looking: redo the forward substitution backward
   const int64_t *csr_rowptr = nullptr;
   const int32_t *csr_col = nullptr;
@@ -342,6 +350,88 @@ stig_status launch_plane(stig_plan *p, const Tin *in, Tout *out,
   return launch_plane_nc<Tin, Tout, TC, 0>(p, in, out, opx, opy, n, planes);
 }
 
+// Half-size mode product along direction l with the parity-split operators.
+template <typename TC> struct PrecIdx;
+template <> struct PrecIdx<double> { static constexpr int v = 0; };
+template <> struct PrecIdx<float> { static constexpr int v = 1; };
+template <> struct PrecIdx<bf16> { static constexpr int v = 2; };
+
+inline bool sym_size_ok(int n) { return n == 32 || n == 33 || n == 64 || n == 65; }
+
+template <typename Tin, typename Tout, typename TC, int M, bool ODD, bool FWD>
+stig_status launch_sym_m(stig_plan *p, const Tin *in, Tout *out, int l, int64_t inner,
+                         int64_t total_cols) {
+  typedef typename Mfma<TC>::elem E;
+  constexpr int NE = M + (ODD ? 1 : 0);
+  const int pi = PrecIdx<TC>::v;
+  const E *oe = (FWD ? p->hFE[pi][l] : p->hBE[pi][l]).template as<E>();
+  const E *oo = (FWD ? p->hFO[pi][l] : p->hBO[pi][l]).template as<E>();
+  const size_t lds = (size_t)(NE + M) * lds_ld<TC>(NE) * sizeof(E);
+  const int64_t nstrips = (total_cols + 15) / 16;
+  const unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID);
+  const int n = 2 * M + (ODD ? 1 : 0);
+  ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
+  hipLaunchKernelGGL((mode_gemm_sym<Tin, Tout, TC, M, ODD, FWD>), dim3(grid), dim3(SYM_THREADS), lds,
+                     p->stream, in, out, oe, oo, inner, total_cols);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tin, typename Tout, typename TC, bool FWD>
+stig_status launch_sym(stig_plan *p, const Tin *in, Tout *out, int l, int64_t inner,
+                       int64_t total_cols) {
+  if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
+  switch (p->n[l]) {
+    case 32: return launch_sym_m<Tin, Tout, TC, 16, false, FWD>(p, in, out, l, inner, total_cols);
+    case 33: return launch_sym_m<Tin, Tout, TC, 16, true, FWD>(p, in, out, l, inner, total_cols);
+    case 64: return launch_sym_m<Tin, Tout, TC, 32, false, FWD>(p, in, out, l, inner, total_cols);
+    case 65: return launch_sym_m<Tin, Tout, TC, 32, true, FWD>(p, in, out, l, inner, total_cols);
+  }
+  return fail(STIG_EINVAL, "no split kernel for this size");
+}
+
+// Fused x/y products with parity-split bases in both directions (n_x = n_y).
+template <typename Tin, typename Tout, typename TC, int M, bool ODD, bool FWD>
+stig_status launch_plane_sym_m(stig_plan *p, const Tin *in, Tout *out, int64_t planes) {
+  typedef typename Mfma<TC>::elem E;
+  const int pi = PrecIdx<TC>::v;
+  auto op = [&](DevBuf (&b)[3][3], int l) { return b[pi][l].template as<E>(); };
+  const E *xE = FWD ? op(p->hFE, 0) : op(p->hBE, 0), *xO = FWD ? op(p->hFO, 0) : op(p->hBO, 0);
+  const E *yE = FWD ? op(p->hFE, 1) : op(p->hBE, 1), *yO = FWD ? op(p->hFO, 1) : op(p->hBO, 1);
+  const size_t lds = plane_sym_lds<TC, M, ODD, FWD>();
+  auto kern = mode_gemm_plane_sym<Tin, Tout, TC, M, ODD, FWD>;
+  static int per_cu = 0;  // per instantiation: resident blocks per CU
+  if (per_cu == 0) {
+    if (lds > 65536)
+      HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, lds));
+    per_cu = std::max(nb, 1);
+  }
+  int64_t grid = std::min<int64_t>(planes, (int64_t)per_cu * p->num_cu);
+  int64_t per = (planes + grid - 1) / grid;
+  grid = (planes + per - 1) / per;
+  const int n = 2 * M + (ODD ? 1 : 0);
+  ProfScope ps(p, STIG_K_PLANE_GEMM, (double)planes * n * n * (sizeof(Tin) + sizeof(Tout)));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, p->stream, in, out, xE, xO, yE, yO,
+                     planes);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tin, typename Tout, typename TC, bool FWD>
+stig_status launch_plane_sym(stig_plan *p, const Tin *in, Tout *out, int64_t planes) {
+  if (planes < 1) return STIG_OK;
+  switch (p->n[0]) {
+    case 32: return launch_plane_sym_m<Tin, Tout, TC, 16, false, FWD>(p, in, out, planes);
+    case 33: return launch_plane_sym_m<Tin, Tout, TC, 16, true, FWD>(p, in, out, planes);
+    case 64: return launch_plane_sym_m<Tin, Tout, TC, 32, false, FWD>(p, in, out, planes);
+    case 65: return launch_plane_sym_m<Tin, Tout, TC, 32, true, FWD>(p, in, out, planes);
+  }
+  return fail(STIG_EINVAL, "no split plane kernel for this size");
+}
+
 template <typename Tio, typename TC, int P>
 stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
   const TC *wb, *mb;
@@ -471,7 +561,9 @@ template <> struct TimeCompute<double> { typedef double type; };
 
 // Steps 2-4 of Algorithm 1 with storage type S for the intermediates and compute
 // type TC for the GEMMs.  Modes 1 and 2 go through the fused plane kernel when
-// they have the same size n <= PLANE_MAX_N and no diagonal scaling is set.
+// they have the same size n <= PLANE_MAX_N and no diagonal scaling is set;
+// the other mode products use the half-size kernels where the basis is
+// parity-split, else the dense ones.
 template <typename S, typename TC>
 stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int transpose) {
   const int64_t tot = p->N * nrhs;
@@ -482,29 +574,40 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
   const double *scale = p->has_dmh ? p->dmh.as<double>() : nullptr;
   const bool fuse = p->d >= 2 && p->n[0] == p->n[1] && p->n[0] <= PLANE_MAX_N && !scale &&
                     p->plane_fusion;
+  auto use_sym = [&](int l) { return p->parity_split && p->split[l] && sym_size_ok(p->n[l]) && !scale; };
+  // one mode product, forward (U_l^T) or backward (U_l)
+  auto mode = [&](auto tin, auto tout, int l, bool fwd, int64_t inner) -> stig_status {
+    typedef typename std::remove_const<typename std::remove_pointer<decltype(tin)>::type>::type Ti;
+    typedef typename std::remove_pointer<decltype(tout)>::type To;
+    const int64_t cols = tot / p->n[l];
+    if (use_sym(l))
+      return fwd ? launch_sym<Ti, To, TC, true>(p, tin, tout, l, inner, cols)
+                 : launch_sym<Ti, To, TC, false>(p, tin, tout, l, inner, cols);
+    const bool first = fwd && l == 0, last = !fwd && l == 0;
+    return launch_mode_gemm<Ti, To, TC>(p, tin, tout, fwd ? OpSet<TC>::UT(p, l) : OpSet<TC>::U(p, l),
+                                        p->n[l], inner, cols, first ? scale : nullptr,
+                                        last ? scale : nullptr);
+  };
   // step 2: forward spatial transform, X x_l U_l^T for l = 1..d
   int64_t inner = 1;
   int l0 = 0;
+  const bool fuse_sym = fuse && use_sym(0) && use_sym(1);
   if (fuse) {
     int n = p->n[0];
-    STIG_TRY((launch_plane<double, S, TC>(p, r, buf[cur], OpSet<TC>::UT(p, 0), OpSet<TC>::UT(p, 1),
-                                           n, tot / ((int64_t)n * n))));
+    if (fuse_sym)
+      STIG_TRY((launch_plane_sym<double, S, TC, true>(p, r, buf[cur], tot / ((int64_t)n * n))));
+    else
+      STIG_TRY((launch_plane<double, S, TC>(p, r, buf[cur], OpSet<TC>::UT(p, 0), OpSet<TC>::UT(p, 1),
+                                             n, tot / ((int64_t)n * n))));
     cur ^= 1;
     inner = (int64_t)n * n;
     l0 = 2;
   }
   for (int l = l0; l < p->d; ++l) {
-    int n = p->n[l];
-    int64_t cols = tot / n;
-    if (l == 0)
-      STIG_TRY((launch_mode_gemm<double, S, TC>(p, r, buf[cur], OpSet<TC>::UT(p, l), n, inner,
-                                                 cols, scale, nullptr)));
-    else {
-      STIG_TRY((launch_mode_gemm<S, S, TC>(p, buf[cur ^ 1], buf[cur], OpSet<TC>::UT(p, l), n,
-                                            inner, cols, nullptr, nullptr)));
-    }
+    if (l == 0) STIG_TRY(mode(r, buf[cur], l, true, inner));
+    else STIG_TRY(mode((const S *)buf[cur ^ 1], buf[cur], l, true, inner));
     cur ^= 1;
-    inner *= n;
+    inner *= p->n[l];
   }
   // step 3: shifted time systems
   STIG_TRY((launch_time<S, typename TimeCompute<TC>::type>(p, buf[cur ^ 1], buf[cur], nrhs,
@@ -512,22 +615,20 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
   cur ^= 1;
   // step 4: back transform, x_l U_l for l = d..1
   for (int l = p->d - 1; l >= l0; --l) {
-    int n = p->n[l];
-    inner /= n;
-    int64_t cols = tot / n;
-    if (l == 0)
-      STIG_TRY((launch_mode_gemm<S, double, TC>(p, buf[cur ^ 1], s, OpSet<TC>::U(p, l), n, inner,
-                                                 cols, nullptr, scale)));
+    inner /= p->n[l];
+    if (l == 0) STIG_TRY(mode((const S *)buf[cur ^ 1], s, l, false, inner));
     else {
-      STIG_TRY((launch_mode_gemm<S, S, TC>(p, buf[cur ^ 1], buf[cur], OpSet<TC>::U(p, l), n,
-                                            inner, cols, nullptr, nullptr)));
+      STIG_TRY(mode((const S *)buf[cur ^ 1], buf[cur], l, false, inner));
       cur ^= 1;
     }
   }
   if (fuse) {
     int n = p->n[0];
-    STIG_TRY((launch_plane<S, double, TC>(p, buf[cur ^ 1], s, OpSet<TC>::U(p, 0), OpSet<TC>::U(p, 1),
-                                           n, tot / ((int64_t)n * n))));
+    if (fuse_sym)
+      STIG_TRY((launch_plane_sym<S, double, TC, false>(p, buf[cur ^ 1], s, tot / ((int64_t)n * n))));
+    else
+      STIG_TRY((launch_plane<S, double, TC>(p, buf[cur ^ 1], s, OpSet<TC>::U(p, 0), OpSet<TC>::U(p, 1),
+                                             n, tot / ((int64_t)n * n))));
   }
   return STIG_OK;
 }
@@ -861,6 +962,10 @@ stig_status stig_set_option(stig_plan *plan, int option, int value) {
       if (value != 0 && value != 1) return fail(STIG_EINVAL, "plane fusion takes 0 or 1");
       plan->plane_fusion = value != 0;
       return STIG_OK;
+    case STIG_OPT_PARITY_SPLIT:
+      if (value != 0 && value != 1) return fail(STIG_EINVAL, "parity split takes 0 or 1");
+      plan->parity_split = value != 0;
+      return STIG_OK;
     case STIG_OPT_TIME_KERNEL:
       if (value < 0 || value > 3) return fail(STIG_EINVAL, "time kernel takes 0 .. 3");
       plan->time_kernel = value == 3 ? 0 : value;
@@ -892,8 +997,40 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     if (!K1d[l] || !M1d[l]) return fail(STIG_EINVAL, "null spatial factor");
     std::vector<double> U((size_t)n * n), UT((size_t)n * n);
     lams[l].resize(n);
-    if (!sym_eig(n, K1d[l], M1d[l], U.data(), lams[l].data()))
+    // persymmetric pencil (uniform knots): even / odd eigenbasis, which the
+    // half-size mode products use; otherwise the plain generalized eigenbasis
+    const bool sp = n >= 2 && persymmetric(n, K1d[l], 1e-13) && persymmetric(n, M1d[l], 1e-13);
+    if (!(sp ? split_eig(n, K1d[l], M1d[l], U.data(), lams[l].data())
+             : sym_eig(n, K1d[l], M1d[l], U.data(), lams[l].data())))
       return fail(STIG_EBREAKDOWN, "spatial mass matrix is not positive definite");
+    p->split[l] = sp;
+    if (sp) {
+      const int m = n / 2, ne = n - m;
+      std::vector<double> fe((size_t)ne * ne), fo((size_t)m * m), be((size_t)ne * ne), bo((size_t)m * m);
+      for (int j = 0; j < ne; ++j)
+        for (int x = 0; x < ne; ++x) {
+          fe[(size_t)j * ne + x] = U[(size_t)x * n + j];
+          be[(size_t)x * ne + j] = U[(size_t)x * n + j];
+        }
+      for (int j = 0; j < m; ++j)
+        for (int x = 0; x < m; ++x) {
+          fo[(size_t)j * m + x] = U[(size_t)x * n + ne + j];
+          bo[(size_t)x * m + j] = U[(size_t)x * n + ne + j];
+        }
+      STIG_TRY(upload(p->hFE[0][l], fe, s));
+      STIG_TRY(upload(p->hFO[0][l], fo, s));
+      STIG_TRY(upload(p->hBE[0][l], be, s));
+      STIG_TRY(upload(p->hBO[0][l], bo, s));
+      STIG_TRY(upload(p->hFE[1][l], convert<float>(fe), s));
+      STIG_TRY(upload(p->hFO[1][l], convert<float>(fo), s));
+      STIG_TRY(upload(p->hBE[1][l], convert<float>(be), s));
+      STIG_TRY(upload(p->hBO[1][l], convert<float>(bo), s));
+      STIG_TRY(upload(p->hFE[2][l], convert<uint16_t>(fe), s));
+      STIG_TRY(upload(p->hFO[2][l], convert<uint16_t>(fo), s));
+      STIG_TRY(upload(p->hBE[2][l], convert<uint16_t>(be), s));
+      STIG_TRY(upload(p->hBO[2][l], convert<uint16_t>(bo), s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) UT[(size_t)i * n + j] = U[(size_t)j * n + i];
     STIG_TRY(upload(p->U64[l], U, s));
@@ -1255,9 +1392,12 @@ size_t stig_plan_device_bytes(const stig_plan *p) {
                         &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->w, &p->tmp, &p->partial,
                         &p->small, &p->flag, &p->lift0, &p->lift1};
   for (auto *b : bs) t += b->bytes;
-  for (int l = 0; l < 3; ++l)
+  for (int l = 0; l < 3; ++l) {
     t += p->U64[l].bytes + p->UT64[l].bytes + p->U32[l].bytes + p->UT32[l].bytes +
          p->U16[l].bytes + p->UT16[l].bytes + p->sK[l].bytes + p->sM[l].bytes;
+    for (int q = 0; q < 3; ++q)
+      t += p->hFE[q][l].bytes + p->hFO[q][l].bytes + p->hBE[q][l].bytes + p->hBO[q][l].bytes;
+  }
   return t;
 }
 
@@ -1289,6 +1429,14 @@ stig_status stig_load_1d(int n_el, int p, double length, const double *fvals, in
 stig_status stig_sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
   if (n < 1 || !K || !M || !U || !lam) return fail(STIG_EINVAL, "bad eigenproblem arguments");
   if (!sym_eig(n, K, M, U, lam)) return fail(STIG_EBREAKDOWN, "M is not positive definite");
+  return STIG_OK;
+}
+
+stig_status stig_split_eig(int n, const double *K, const double *M, double *U, double *lam) {
+  if (n < 2 || !K || !M || !U || !lam) return fail(STIG_EINVAL, "bad eigenproblem arguments");
+  if (!persymmetric(n, K, 1e-13) || !persymmetric(n, M, 1e-13))
+    return fail(STIG_EINVAL, "pencil is not persymmetric");
+  if (!split_eig(n, K, M, U, lam)) return fail(STIG_EBREAKDOWN, "M is not positive definite");
   return STIG_OK;
 }
 

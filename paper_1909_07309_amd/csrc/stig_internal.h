@@ -36,4 +36,12 @@ void separate_2d(int n1, int n2, const double *C11, const double *C22, const dou
 // K U = M U Lambda, U^T M U = I, ascending; false if M is not SPD.
 bool sym_eig(int n, const double *K, const double *M, double *U, double *lam);
 
+// max |A[i][j] - A[n-1-i][n-1-j]| <= tol * max |A|.
+bool persymmetric(int n, const double *A, double tol);
+
+// Eigenbasis of a persymmetric pencil with the even modes first (n/2 + n%2 of
+// them, U[n-1-x][k] = U[x][k]) and the odd modes after (U[n-1-x][k] = -U[x][k]);
+// ascending within each group; same normalisation as sym_eig.
+bool split_eig(int n, const double *K, const double *M, double *U, double *lam);
+
 }  // namespace stig

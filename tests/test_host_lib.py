@@ -76,6 +76,35 @@ def test_host_eigensolver_matches_oracle(n_el, p):
     assert np.abs(U.T @ K @ U - np.diag(lam)).max() < 1e-12 * lam.max()
 
 
+@pytest.mark.parametrize("n_el,p", [(8, 2), (31, 3), (32, 3), (48, 3), (64, 3), (128, 4)])
+def test_split_eigenbasis_is_an_exact_parity_eigenbasis(n_el, p):
+    """Persymmetric pencils (uniform knots): the even/odd split basis is M-orthonormal,
+    diagonalizes K, has exact parity, and its eigenvalues are the oracle's."""
+    from paper_1909_07309_amd import api
+    K, M = bs.space_matrices(n_el, p)
+    n = K.shape[0]
+    J = np.eye(n)[::-1]
+    lam, U = api.split_eig(K, M)
+    ne = n - n // 2
+    assert np.abs(U.T @ M @ U - np.eye(n)).max() < 1e-12
+    assert np.abs(U.T @ K @ U - np.diag(lam)).max() < 1e-12 * lam.max()
+    assert np.array_equal(J @ U[:, :ne], U[:, :ne])          # even, bit for bit
+    assert np.array_equal(J @ U[:, ne:], -U[:, ne:])         # odd
+    assert np.all(np.diff(lam[:ne]) > 0) and np.all(np.diff(lam[ne:]) > 0)
+    lo, _ = fd.space_eig(K, M)
+    assert np.abs(np.sort(lam) - lo).max() <= 1e-12 * lo.max()
+
+
+def test_split_eigenbasis_rejects_a_non_persymmetric_pencil():
+    from paper_1909_07309_amd import api
+    from paper_1909_07309_amd._lib import StigError
+    K, M = bs.space_matrices(16, 3)
+    K = K.copy()
+    K[0, 0] *= 1.001
+    with pytest.raises(StigError):
+        api.split_eig(K, M)
+
+
 def test_argument_validation_without_gpu():
     L = _lib()
     lib = L.lib()
@@ -93,6 +122,8 @@ def test_argument_validation_without_gpu():
     assert lib.stig_set_option(h, 0, 2) == -1
     assert all(lib.stig_set_option(h, 1, v) == 0 for v in (0, 1, 2, 3))
     assert lib.stig_set_option(h, 1, 4) == -1 and lib.stig_set_option(h, 1, -1) == -1
+    assert lib.stig_set_option(h, 2, 0) == 0 and lib.stig_set_option(h, 2, 1) == 0
+    assert lib.stig_set_option(h, 2, 5) == -1
     assert lib.stig_set_option(h, 7, 0) == -1
     lib.stig_plan_destroy(h)
     assert lib.stig_status_string(-4) == b"breakdown (non-positive pivot)"
