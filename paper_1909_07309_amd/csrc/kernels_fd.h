@@ -141,12 +141,22 @@ __host__ __device__ constexpr inline int round_up(int a, int b) { return (a + b 
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 template <typename T> __device__ inline cptr<T> as_const(const T *p) { return (cptr<T>)p; }
 
-// Leading dimension (in elements) of an LDS tile holding k = 0 .. kpad-1 per
-// column, padded so consecutive columns start in different LDS banks.
+// LDS row stride (in elements) of at least mn elements for MFMA operand tiles.
+// A wave reads rows c = lane % 16 at k-slice g = lane / 16, i.e. elements
+// c * ld + g * KPL.  Measured on gfx950 (bank-conflict counter), such reads
+// are conflict-free when the stride is 2 x odd elements for 8-byte (FP64) and
+// 4-byte (FP32) reads, and 8 x odd elements for the 8-byte reads of four BF16
+// values (which also keeps BF16 fragments 8-byte aligned).
+template <typename TC> __host__ __device__ constexpr int lds_pad(int mn) {
+  constexpr int q = sizeof(typename Mfma<TC>::elem) == 2 ? 8 : 2;
+  int k = (mn + q - 1) / q;
+  if (k % 2 == 0) ++k;
+  return k * q;
+}
+
+// Leading dimension of an LDS tile holding k = 0 .. kpad-1 per column.
 template <typename TC> __host__ __device__ inline int lds_ld(int n) {
-  int kpad = round_up(n, Mfma<TC>::KSTEP);
-  if (sizeof(typename Mfma<TC>::elem) >= 4) return kpad | 1;  // odd stride in 4/8-byte words
-  return kpad + 4;                                              // bf16: keep 8-byte alignment
+  return lds_pad<TC>(round_up(n, Mfma<TC>::KSTEP));
 }
 
 constexpr int GEMM_TILE_COLS = 64;
@@ -823,12 +833,17 @@ __device__ inline void pivot_step(int i, Window<TC, P> &S, const StepVals<TC, P>
 // YREC true: nothing is stored; the right-hand-side window is checkpointed with
 // S and the backward sweep redoes the forward substitution of each segment
 // from the input (read a second time, shortly after the first).
-template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC>
+// LROWS (YREC only): the first LROWS right-hand-side rows, which the backward
+// sweep reads again last, are kept in LDS (LROWS * 256 values per block)
+// instead of being read from HBM a second time.
+template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC, int LROWS>
 __global__ void __launch_bounds__(256, sizeof(TC) == 8 ? 2 : (YREC ? 3 : 4))
 time_band_solve_rl(const Tio *__restrict__ in, Tio *__restrict__ out, const double *__restrict__ lam,
                    const TC *__restrict__ rec, const TC *__restrict__ wb, const TC *__restrict__ mb,
                    TC gamma_arg, TC nu, int64_t ns, int nrhs, TC *__restrict__ ysc,
                    int *__restrict__ flag) {
+  static_assert(YREC || LROWS == 0, "the LDS copy serves the recomputed substitution");
+  __shared__ TC rstash[LROWS > 0 ? LROWS * 256 : 1];
   typedef SegPlan<NT, P, NSEG> SP;
   constexpr int LMAX = SP::maxlen();
   constexpr int D = NT - P < 8 ? NT - P : 8;  // right-hand-side prefetch distance (rows)
@@ -846,10 +861,16 @@ time_band_solve_rl(const Tio *__restrict__ in, Tio *__restrict__ out, const doub
   auto rload = [&](const Tio *base, int i) {
     return (TC)Conv<Tio>::to_f64(base[(int64_t)(i < NT ? i : 0) * ns]);
   };
-  // the backward sweep's second read of the input: a relaxed atomic load, which
-  // the compiler does not merge with the first read (merging would keep every
-  // input value live across the whole forward sweep)
+  // the backward sweep's second read of the input: the LDS copy for the first
+  // LROWS rows, else a relaxed atomic load, which the compiler does not merge
+  // with the first read (merging would keep every input value live across the
+  // whole forward sweep)
+  const int tx = threadIdx.x;
+  auto stash = [&](int i, TC v) {
+    if (LROWS > 0 && i < LROWS) rstash[(LROWS > 0 ? i : 0) * 256 + tx] = v;
+  };
   auto rload_again = [&](int i) {
+    if (LROWS > 0 && i < LROWS) return rstash[(LROWS > 0 ? i : 0) * 256 + tx];
     const Tio *p = r + (int64_t)(i < NT ? i : 0) * ns;
     Tio v;
     __atomic_load(p, &v, __ATOMIC_RELAXED);
@@ -863,7 +884,10 @@ time_band_solve_rl(const Tio *__restrict__ in, Tio *__restrict__ out, const doub
   first_window<TC, NT, P>(S, wbc, mbc, gamma, nul);
   TC rw[P], rq[D > 0 ? D : 1];
 #pragma unroll
-  for (int a = 0; a < P; ++a) rw[a] = rload(r, a);
+  for (int a = 0; a < P; ++a) {
+    rw[a] = rload(r, a);
+    if (YREC) stash(a, rw[a]);
+  }
 #pragma unroll
   for (int j = 0; j < D; ++j) rq[j] = rload(r, P + j);
   Window<TC, P> ck[NSEG];
@@ -896,6 +920,7 @@ time_band_solve_rl(const Tio *__restrict__ in, Tio *__restrict__ out, const doub
     if (i + P < NT && D > 0) {
       rin = rq[i % D];
       if (i + P + D < NT) rq[i % D] = rload(r, i + P + D);
+      if (YREC) stash(i + P, rin);
     }
 #pragma unroll
     for (int a = 1; a < P; ++a) rw[a - 1] = rw[a] - l[a] * yi;

@@ -197,13 +197,10 @@ template <int M, bool ODD> struct PlaneSymDims {
   static constexpr int COLO = (NE + 3) / 4 * 4;
 };
 template <typename TC, int M, bool ODD> __host__ __device__ constexpr int plane_sym_ldp() {
-  // odd stride in 4/8-byte words, a multiple of 4 elements for bf16
-  return sizeof(typename Mfma<TC>::elem) >= 4 ? ((PlaneSymDims<M, ODD>::COLO + M) | 1)
-                                              : (PlaneSymDims<M, ODD>::COLO + M + 4);
+  return lds_pad<TC>(PlaneSymDims<M, ODD>::COLO + M);
 }
 template <typename TC, int M, bool ODD> __host__ __device__ constexpr int plane_sym_ldo() {
-  return sizeof(typename Mfma<TC>::elem) >= 4 ? (PlaneSymDims<M, ODD>::NE | 1)
-                                              : ((PlaneSymDims<M, ODD>::NE + 3) / 4 * 4 + 4);
+  return lds_pad<TC>((PlaneSymDims<M, ODD>::NE + 3) / 4 * 4);
 }
 // LDS layout of mode_gemm_plane_sym: plane, OpY halves, OpX halves and, for
 // the backward pass when the accumulator is wider than the element, an

@@ -481,7 +481,7 @@ stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int
   return STIG_OK;
 }
 
-template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC>
+template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC, int LROWS>
 stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
   // forward-substituted values (YREC false): in the output buffer when it has
   // the compute type, else in compute-type scratch
@@ -505,7 +505,7 @@ stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int 
   ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
   const TC *rec = std::is_same<TC, double>::value ? (const TC *)p->tR64[transpose ? 1 : 0].p
                                                   : (const TC *)p->tR32[transpose ? 1 : 0].p;
-  hipLaunchKernelGGL((time_band_solve_rl<Tio, TC, NT, P, NSEG, YREC>), dim3(grid_for(work, 256)),
+  hipLaunchKernelGGL((time_band_solve_rl<Tio, TC, NT, P, NSEG, YREC, LROWS>), dim3(grid_for(work, 256)),
                      dim3(256), 0, p->stream, in, out, p->lam.as<double>(), rec, wb, mb,
                      (TC)p->gamma, (TC)p->nu, p->Ns, nrhs, ysc, p->flag.as<int>());
   HIP_TRY(hipGetLastError());
@@ -514,8 +514,13 @@ stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int 
 
 template <typename Tio, typename TC, int NT, int P, int NSEG>
 stig_status launch_time_rl2(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
-  if (p->time_recompute) return launch_time_rl<Tio, TC, NT, P, NSEG, true>(p, in, out, nrhs, transpose);
-  return launch_time_rl<Tio, TC, NT, P, NSEG, false>(p, in, out, nrhs, transpose);
+  // rows of the input kept in LDS for the second read: 64 KB per block in FP64
+  // (two blocks per CU), 30 KB in FP32 (five blocks per CU)
+  constexpr int LR = std::is_same<TC, double>::value ? 32 : 30;
+  constexpr int LROWS = LR < NT ? LR : NT;
+  if (p->time_recompute)
+    return launch_time_rl<Tio, TC, NT, P, NSEG, true, LROWS>(p, in, out, nrhs, transpose);
+  return launch_time_rl<Tio, TC, NT, P, NSEG, false, 0>(p, in, out, nrhs, transpose);
 }
 
 template <typename Tio, typename TC>
