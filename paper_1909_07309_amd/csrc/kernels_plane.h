@@ -51,7 +51,8 @@ template <> struct PlaneVal<bf16> {
   __device__ static inline uint16_t to_elem(float x) { return float_to_bf16_bits(x); }
 };
 
-// Y_o = Op_y X_o Op_x^T for o = 0 .. planes-1, X_o = in + o*n*n (row y, x fastest).
+// Y_o = Op_y X_o Op_x^T for o = 0 .. planes-1, X_o = in + o*in_stride (row y, x
+// fastest), Y_o = out + o*out_stride (strides >= n*n; padding left untouched).
 // Op_x, Op_y: n x n row-major, compute precision.  NC = n at compile time (65 or
 // 49), or 0 for any n <= PLANE_MAX_N taken from the argument (zero padded to 80).
 // Block = 64 * (NMAX / 16) threads; dynamic LDS = (2 * NR + 1) * ld elements.
@@ -61,7 +62,8 @@ template <typename Tin, typename Tout, typename TC, int NC>
 __global__ void __launch_bounds__(64 * ((NC ? NC : PLANE_MAX_N) / 16), 2)
 mode_gemm_plane(const Tin *__restrict__ in, Tout *__restrict__ out,
                 const typename Mfma<TC>::elem *__restrict__ opx,
-                const typename Mfma<TC>::elem *__restrict__ opy, int n_arg, int64_t planes) {
+                const typename Mfma<TC>::elem *__restrict__ opy, int n_arg, int64_t planes,
+                int64_t in_stride, int64_t out_stride) {
   typedef Mfma<TC> MF;
   typedef typename MF::elem E;
   typedef PlaneVal<TC> PV;
@@ -115,7 +117,7 @@ mode_gemm_plane(const Tin *__restrict__ in, Tout *__restrict__ out,
   Tin pre[PER];
   auto gload = [&](int64_t p) {
     const bool pv = p < planes;
-    const Tin *src = in + (pv ? p : 0) * (int64_t)nn;
+    const Tin *src = in + (pv ? p : 0) * in_stride;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       int e = tid + i * NT;
@@ -230,7 +232,7 @@ mode_gemm_plane(const Tin *__restrict__ in, Tout *__restrict__ out,
         }
       }
     }
-    Tout *dst = out + p * (int64_t)nn;
+    Tout *dst = out + p * out_stride;
 #pragma unroll
     for (int t = 0; t < Q; ++t)
 #pragma unroll

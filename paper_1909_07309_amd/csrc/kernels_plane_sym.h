@@ -219,7 +219,8 @@ template <typename TC, int M, bool ODD, bool FWD> __host__ __device__ constexpr 
 }
 
 // FWD: out = modal planes (even modes first along both axes) of the physical
-// planes in `in`; !FWD: the reverse.  opx*/opy*: half operators of directions
+// planes in `in`; !FWD: the reverse.  Plane o starts at in + o*in_stride and
+// out + o*out_stride (strides >= n*n; padding is neither read nor written).  opx*/opy*: half operators of directions
 // x and y (FWD: rows of U^T; !FWD: rows of U), even (NE x NE) and odd (M x M).
 // Block = 4 waves (one quadrant each); persistent over planes, the next
 // plane's loads in flight while the current one is transformed.
@@ -229,7 +230,8 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
                     const typename Mfma<TC>::elem *__restrict__ opxE,
                     const typename Mfma<TC>::elem *__restrict__ opxO,
                     const typename Mfma<TC>::elem *__restrict__ opyE,
-                    const typename Mfma<TC>::elem *__restrict__ opyO, int64_t planes) {
+                    const typename Mfma<TC>::elem *__restrict__ opyO, int64_t planes,
+                    int64_t in_stride, int64_t out_stride) {
   typedef Mfma<TC> MF;
   typedef typename MF::elem E;
   typedef PlaneVal<TC> PV;
@@ -267,7 +269,7 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
   Tin pre[PER][NLD];
   auto gload = [&](int64_t p) {
     const bool pv = p < planes;
-    const Tin *src = in + (pv ? p : 0) * (int64_t)(N * N);
+    const Tin *src = in + (pv ? p : 0) * in_stride;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + i * NT;
@@ -318,7 +320,7 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
     gload(p + gridDim.x);
     const E *inq = pl + (qa ? NE : 0) * LDP + (qb ? COLO : 0);
     const E *opyq = oy + (qa ? NE : 0) * LDO, *opxq = ox + (qb ? NE : 0) * LDO;
-    Tout *dst = out + p * (int64_t)(N * N);
+    Tout *dst = out + p * out_stride;
     const int r0 = qa ? NE : 0, c0 = qb ? NE : 0, cl0 = qb ? COLO : 0;
     auto store = [&](int row, int col, VT v) {
       if (FWD) dst[(r0 + row) * N + c0 + col] = Conv<Tout>::from_f64((double)v);

@@ -97,6 +97,8 @@ struct stig_plan {
   bool split[3] = {false, false, false};
   DevBuf hFE[3][3], hFO[3][3], hBE[3][3], hBO[3][3];
   DevBuf lam;            // Ns doubles: lambda_k = sum_l lambda_{l,i_l}
+  DevBuf lamp;           // lam in a padded plane layout (stride lamp_ps)
+  int64_t lamp_ps = 0;
   DevBuf tW64, tWT64, tM64, tW32, tWT32, tM32;  // time bands (unscaled)
   DevBuf tR64[2], tR32[2];  // step records of [W; M] and [W^T; M] (right-looking solve)
   DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
@@ -312,7 +314,8 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
 template <typename Tin, typename Tout, typename TC, int NC>
 stig_status launch_plane_nc(stig_plan *p, const Tin *in, Tout *out,
                             const typename Mfma<TC>::elem *opx,
-                            const typename Mfma<TC>::elem *opy, int n, int64_t planes) {
+                            const typename Mfma<TC>::elem *opy, int n, int64_t planes,
+                            int64_t in_stride, int64_t out_stride) {
   typedef typename Mfma<TC>::elem E;
   constexpr int NMAX = NC ? NC : PLANE_MAX_N;
   constexpr int NR = NMAX / 16 * 16 + NMAX % 16;
@@ -334,7 +337,7 @@ stig_status launch_plane_nc(stig_plan *p, const Tin *in, Tout *out,
   grid = (planes + per - 1) / per;
   ProfScope ps(p, STIG_K_PLANE_GEMM, (double)planes * n * n * (sizeof(Tin) + sizeof(Tout)));
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, p->stream, in, out, opx, opy,
-                     n, planes);
+                     n, planes, in_stride, out_stride);
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
@@ -342,12 +345,14 @@ stig_status launch_plane_nc(stig_plan *p, const Tin *in, Tout *out,
 template <typename Tin, typename Tout, typename TC>
 stig_status launch_plane(stig_plan *p, const Tin *in, Tout *out,
                          const typename Mfma<TC>::elem *opx, const typename Mfma<TC>::elem *opy,
-                         int n, int64_t planes) {
+                         int n, int64_t planes, int64_t in_stride, int64_t out_stride) {
   if (n < 1 || n > PLANE_MAX_N) return fail(STIG_EINVAL, "plane size out of range");
   if (planes < 1) return STIG_OK;
-  if (n == 65) return launch_plane_nc<Tin, Tout, TC, 65>(p, in, out, opx, opy, n, planes);
-  if (n == 49) return launch_plane_nc<Tin, Tout, TC, 49>(p, in, out, opx, opy, n, planes);
-  return launch_plane_nc<Tin, Tout, TC, 0>(p, in, out, opx, opy, n, planes);
+  if (n == 65)
+    return launch_plane_nc<Tin, Tout, TC, 65>(p, in, out, opx, opy, n, planes, in_stride, out_stride);
+  if (n == 49)
+    return launch_plane_nc<Tin, Tout, TC, 49>(p, in, out, opx, opy, n, planes, in_stride, out_stride);
+  return launch_plane_nc<Tin, Tout, TC, 0>(p, in, out, opx, opy, n, planes, in_stride, out_stride);
 }
 
 // Half-size mode product along direction l with the parity-split operators.
@@ -392,7 +397,8 @@ stig_status launch_sym(stig_plan *p, const Tin *in, Tout *out, int l, int64_t in
 
 // Fused x/y products with parity-split bases in both directions (n_x = n_y).
 template <typename Tin, typename Tout, typename TC, int M, bool ODD, bool FWD>
-stig_status launch_plane_sym_m(stig_plan *p, const Tin *in, Tout *out, int64_t planes) {
+stig_status launch_plane_sym_m(stig_plan *p, const Tin *in, Tout *out, int64_t planes,
+                               int64_t in_stride, int64_t out_stride) {
   typedef typename Mfma<TC>::elem E;
   const int pi = PrecIdx<TC>::v;
   auto op = [&](DevBuf (&b)[3][3], int l) { return b[pi][l].template as<E>(); };
@@ -415,25 +421,33 @@ stig_status launch_plane_sym_m(stig_plan *p, const Tin *in, Tout *out, int64_t p
   const int n = 2 * M + (ODD ? 1 : 0);
   ProfScope ps(p, STIG_K_PLANE_GEMM, (double)planes * n * n * (sizeof(Tin) + sizeof(Tout)));
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, p->stream, in, out, xE, xO, yE, yO,
-                     planes);
+                     planes, in_stride, out_stride);
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
 
 template <typename Tin, typename Tout, typename TC, bool FWD>
-stig_status launch_plane_sym(stig_plan *p, const Tin *in, Tout *out, int64_t planes) {
+stig_status launch_plane_sym(stig_plan *p, const Tin *in, Tout *out, int64_t planes,
+                             int64_t in_stride, int64_t out_stride) {
   if (planes < 1) return STIG_OK;
   switch (p->n[0]) {
-    case 32: return launch_plane_sym_m<Tin, Tout, TC, 16, false, FWD>(p, in, out, planes);
-    case 33: return launch_plane_sym_m<Tin, Tout, TC, 16, true, FWD>(p, in, out, planes);
-    case 64: return launch_plane_sym_m<Tin, Tout, TC, 32, false, FWD>(p, in, out, planes);
-    case 65: return launch_plane_sym_m<Tin, Tout, TC, 32, true, FWD>(p, in, out, planes);
+    case 32: return launch_plane_sym_m<Tin, Tout, TC, 16, false, FWD>(p, in, out, planes, in_stride, out_stride);
+    case 33: return launch_plane_sym_m<Tin, Tout, TC, 16, true, FWD>(p, in, out, planes, in_stride, out_stride);
+    case 64: return launch_plane_sym_m<Tin, Tout, TC, 32, false, FWD>(p, in, out, planes, in_stride, out_stride);
+    case 65: return launch_plane_sym_m<Tin, Tout, TC, 32, true, FWD>(p, in, out, planes, in_stride, out_stride);
   }
   return fail(STIG_EINVAL, "no split plane kernel for this size");
 }
 
+// Layout of the shifted time systems: ns spatial indices per time row (the
+// row stride), lam[k] the shift of system k.
+struct TimeView {
+  int64_t ns;
+  const double *lam;
+};
+
 template <typename Tio, typename TC, int P>
-stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose, TimeView tv) {
   const TC *wb, *mb;
   if (std::is_same<TC, double>::value) {
     wb = (const TC *)(transpose ? p->tWT64.p : p->tW64.p);
@@ -442,17 +456,18 @@ stig_status launch_time_p(stig_plan *p, const Tio *in, Tio *out, int nrhs, int t
     wb = (const TC *)(transpose ? p->tWT32.p : p->tW32.p);
     mb = (const TC *)p->tM32.p;
   }
-  int64_t work = p->Ns * nrhs;
+  int64_t work = tv.ns * nrhs;
   ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
   hipLaunchKernelGGL((time_band_solve<Tio, TC, P>), dim3(grid_for(work, 256)), dim3(256), 0,
-                     p->stream, in, out, p->lam.as<double>(), wb, mb, (TC)p->gamma, (TC)p->nu,
-                     p->nt, p->Ns, nrhs, p->tscr.as<TC>(), p->flag.as<int>());
+                     p->stream, in, out, tv.lam, wb, mb, (TC)p->gamma, (TC)p->nu,
+                     p->nt, tv.ns, nrhs, p->tscr.as<TC>(), p->flag.as<int>());
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
 
 template <typename Tio, typename TC, int NT, int P, int C>
-stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                            TimeView tv) {
   // FP64 keeps the forward-substituted values in the output buffer (registers
   // would spill); FP32 keeps them in registers.
   constexpr bool YREG = !std::is_same<TC, double>::value;
@@ -460,7 +475,7 @@ stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int
   if (!YREG) {
     if (std::is_same<Tio, TC>::value) ysc = (TC *)out;
     else {
-      STIG_TRY(p->tscr.ensure((size_t)p->N * nrhs * sizeof(TC)));
+      STIG_TRY(p->tscr.ensure((size_t)tv.ns * p->nt * nrhs * sizeof(TC)));
       ysc = p->tscr.as<TC>();
     }
   }
@@ -472,24 +487,25 @@ stig_status launch_time_reg(stig_plan *p, const Tio *in, Tio *out, int nrhs, int
     wb = (const TC *)(transpose ? p->tWT32.p : p->tW32.p);
     mb = (const TC *)p->tM32.p;
   }
-  int64_t work = p->Ns * nrhs;
+  int64_t work = tv.ns * nrhs;
   ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
   hipLaunchKernelGGL((time_band_solve_reg<Tio, TC, NT, P, C, YREG>), dim3(grid_for(work, 256)),
-                     dim3(256), 0, p->stream, in, out, p->lam.as<double>(), wb, mb, (TC)p->gamma,
-                     (TC)p->nu, p->Ns, nrhs, ysc, p->flag.as<int>());
+                     dim3(256), 0, p->stream, in, out, tv.lam, wb, mb, (TC)p->gamma,
+                     (TC)p->nu, tv.ns, nrhs, ysc, p->flag.as<int>());
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
 
 template <typename Tio, typename TC, int NT, int P, int NSEG, bool YREC, int LROWS>
-stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                           TimeView tv) {
   // forward-substituted values (YREC false): in the output buffer when it has
   // the compute type, else in compute-type scratch
   TC *ysc = nullptr;
   if (!YREC) {
     if (std::is_same<Tio, TC>::value) ysc = (TC *)out;
     else {
-      STIG_TRY(p->tscr.ensure((size_t)p->N * nrhs * sizeof(TC)));
+      STIG_TRY(p->tscr.ensure((size_t)tv.ns * p->nt * nrhs * sizeof(TC)));
       ysc = p->tscr.as<TC>();
     }
   }
@@ -501,49 +517,67 @@ stig_status launch_time_rl(stig_plan *p, const Tio *in, Tio *out, int nrhs, int 
     wb = (const TC *)(transpose ? p->tWT32.p : p->tW32.p);
     mb = (const TC *)p->tM32.p;
   }
-  int64_t work = p->Ns * nrhs;
+  int64_t work = tv.ns * nrhs;
   ProfScope ps(p, STIG_K_TIME_SOLVE, (double)work * p->nt * 2 * sizeof(Tio));
   const TC *rec = std::is_same<TC, double>::value ? (const TC *)p->tR64[transpose ? 1 : 0].p
                                                   : (const TC *)p->tR32[transpose ? 1 : 0].p;
   hipLaunchKernelGGL((time_band_solve_rl<Tio, TC, NT, P, NSEG, YREC, LROWS>), dim3(grid_for(work, 256)),
-                     dim3(256), 0, p->stream, in, out, p->lam.as<double>(), rec, wb, mb,
-                     (TC)p->gamma, (TC)p->nu, p->Ns, nrhs, ysc, p->flag.as<int>());
+                     dim3(256), 0, p->stream, in, out, tv.lam, rec, wb, mb,
+                     (TC)p->gamma, (TC)p->nu, tv.ns, nrhs, ysc, p->flag.as<int>());
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
 
 template <typename Tio, typename TC, int NT, int P, int NSEG>
-stig_status launch_time_rl2(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+stig_status launch_time_rl2(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                            TimeView tv) {
   // rows of the input kept in LDS for the second read: 64 KB per block in FP64
   // (two blocks per CU), 30 KB in FP32 (five blocks per CU)
   constexpr int LR = std::is_same<TC, double>::value ? 32 : 30;
   constexpr int LROWS = LR < NT ? LR : NT;
   if (p->time_recompute)
-    return launch_time_rl<Tio, TC, NT, P, NSEG, true, LROWS>(p, in, out, nrhs, transpose);
-  return launch_time_rl<Tio, TC, NT, P, NSEG, false, 0>(p, in, out, nrhs, transpose);
+    return launch_time_rl<Tio, TC, NT, P, NSEG, true, LROWS>(p, in, out, nrhs, transpose, tv);
+  return launch_time_rl<Tio, TC, NT, P, NSEG, false, 0>(p, in, out, nrhs, transpose, tv);
 }
 
 template <typename Tio, typename TC>
-stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                        TimeView tv) {
   // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
   if (p->time_kernel == 1) {
-    if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose);
-    if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose);
-    if (p->nt == 9 && p->pt == 2) return launch_time_reg<Tio, TC, 9, 2, 3>(p, in, out, nrhs, transpose);
+    if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose, tv);
+    if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose, tv);
+    if (p->nt == 9 && p->pt == 2) return launch_time_reg<Tio, TC, 9, 2, 3>(p, in, out, nrhs, transpose, tv);
   } else if (p->time_kernel == 0) {
-    if (p->nt == 66 && p->pt == 3) return launch_time_rl2<Tio, TC, 66, 3, 7>(p, in, out, nrhs, transpose);
-    if (p->nt == 50 && p->pt == 3) return launch_time_rl2<Tio, TC, 50, 3, 6>(p, in, out, nrhs, transpose);
-    if (p->nt == 9 && p->pt == 2) return launch_time_rl2<Tio, TC, 9, 2, 2>(p, in, out, nrhs, transpose);
+    if (p->nt == 66 && p->pt == 3) return launch_time_rl2<Tio, TC, 66, 3, 7>(p, in, out, nrhs, transpose, tv);
+    if (p->nt == 50 && p->pt == 3) return launch_time_rl2<Tio, TC, 50, 3, 6>(p, in, out, nrhs, transpose, tv);
+    if (p->nt == 9 && p->pt == 2) return launch_time_rl2<Tio, TC, 9, 2, 2>(p, in, out, nrhs, transpose, tv);
   }
-  STIG_TRY(p->tscr.ensure((size_t)(p->pt + 1) * p->N * nrhs * sizeof(TC)));
+  STIG_TRY(p->tscr.ensure((size_t)(p->pt + 1) * tv.ns * p->nt * nrhs * sizeof(TC)));
   switch (p->pt) {
-    case 1: return launch_time_p<Tio, TC, 1>(p, in, out, nrhs, transpose);
-    case 2: return launch_time_p<Tio, TC, 2>(p, in, out, nrhs, transpose);
-    case 3: return launch_time_p<Tio, TC, 3>(p, in, out, nrhs, transpose);
-    case 4: return launch_time_p<Tio, TC, 4>(p, in, out, nrhs, transpose);
-    case 5: return launch_time_p<Tio, TC, 5>(p, in, out, nrhs, transpose);
+    case 1: return launch_time_p<Tio, TC, 1>(p, in, out, nrhs, transpose, tv);
+    case 2: return launch_time_p<Tio, TC, 2>(p, in, out, nrhs, transpose, tv);
+    case 3: return launch_time_p<Tio, TC, 3>(p, in, out, nrhs, transpose, tv);
+    case 4: return launch_time_p<Tio, TC, 4>(p, in, out, nrhs, transpose, tv);
+    case 5: return launch_time_p<Tio, TC, 5>(p, in, out, nrhs, transpose, tv);
   }
   return fail(STIG_EINVAL, "unsupported time degree");
+}
+template <typename Tio, typename TC>
+stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose) {
+  return launch_time<Tio, TC>(p, in, out, nrhs, transpose, TimeView{p->Ns, p->lam.as<double>()});
+}
+
+// Shifts for a padded plane layout: lamp[z * ps + i] = lam[z * nn + i] for i < nn;
+// padding entries repeat the first shift of their z index (valid systems whose
+// results are never read).
+__global__ void pad_shifts(const double *__restrict__ lam, double *__restrict__ lamp, int64_t nn,
+                           int64_t ps, int64_t nz) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nz * ps;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = k / ps, i = k - z * ps;
+    lamp[k] = lam[z * nn + (i < nn ? i : 0)];
+  }
 }
 
 // Typed access to the eigenvector copies of one precision.
@@ -571,15 +605,34 @@ template <> struct TimeCompute<double> { typedef double type; };
 // parity-split, else the dense ones.
 template <typename S, typename TC>
 stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int transpose) {
-  const int64_t tot = p->N * nrhs;
-  STIG_TRY(p->s0.ensure(tot * sizeof(S)));
-  STIG_TRY(p->s1.ensure(tot * sizeof(S)));
-  S *buf[2] = {p->s0.as<S>(), p->s1.as<S>()};
-  int cur = 0;
   const double *scale = p->has_dmh ? p->dmh.as<double>() : nullptr;
   const bool fuse = p->d >= 2 && p->n[0] == p->n[1] && p->n[0] <= PLANE_MAX_N && !scale &&
                     p->plane_fusion;
   auto use_sym = [&](int l) { return p->parity_split && p->split[l] && sym_size_ok(p->n[l]) && !scale; };
+  // Intermediates between the fused plane passes: planes padded to a multiple
+  // of 128 bytes, so that the strided passes (mode 3, time) read and write
+  // whole cache lines.
+  const int64_t nn = p->d >= 2 ? (int64_t)p->n[0] * p->n[1] : p->n[0];
+  const int64_t ps = fuse ? (nn + (128 / sizeof(S)) - 1) / (128 / sizeof(S)) * (128 / sizeof(S)) : nn;
+  const int64_t nz = p->d == 3 ? p->n[2] : 1;
+  const int64_t ns = fuse ? nz * ps : p->Ns;       // spatial indices per time row
+  const int64_t tot = ns * p->nt * nrhs;           // entries of one intermediate tensor
+  const int64_t planes = (int64_t)nrhs * p->nt * nz;
+  STIG_TRY(p->s0.ensure(tot * sizeof(S)));
+  STIG_TRY(p->s1.ensure(tot * sizeof(S)));
+  S *buf[2] = {p->s0.as<S>(), p->s1.as<S>()};
+  int cur = 0;
+  TimeView tv{p->Ns, p->lam.as<double>()};
+  if (ps != nn) {
+    if (p->lamp_ps != ps) {
+      STIG_TRY(p->lamp.ensure((size_t)nz * ps * sizeof(double)));
+      hipLaunchKernelGGL(pad_shifts, dim3(grid_for(nz * ps, 256, 4096)), dim3(256), 0, p->stream,
+                         p->lam.as<double>(), p->lamp.as<double>(), nn, ps, nz);
+      HIP_TRY(hipGetLastError());
+      p->lamp_ps = ps;
+    }
+    tv = TimeView{ns, p->lamp.as<double>()};
+  }
   // one mode product, forward (U_l^T) or backward (U_l)
   auto mode = [&](auto tin, auto tout, int l, bool fwd, int64_t inner) -> stig_status {
     typedef typename std::remove_const<typename std::remove_pointer<decltype(tin)>::type>::type Ti;
@@ -594,18 +647,17 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
                                         last ? scale : nullptr);
   };
   // step 2: forward spatial transform, X x_l U_l^T for l = 1..d
+  const bool fuse_sym = fuse && use_sym(0) && use_sym(1);
   int64_t inner = 1;
   int l0 = 0;
-  const bool fuse_sym = fuse && use_sym(0) && use_sym(1);
   if (fuse) {
-    int n = p->n[0];
     if (fuse_sym)
-      STIG_TRY((launch_plane_sym<double, S, TC, true>(p, r, buf[cur], tot / ((int64_t)n * n))));
+      STIG_TRY((launch_plane_sym<double, S, TC, true>(p, r, buf[cur], planes, nn, ps)));
     else
       STIG_TRY((launch_plane<double, S, TC>(p, r, buf[cur], OpSet<TC>::UT(p, 0), OpSet<TC>::UT(p, 1),
-                                             n, tot / ((int64_t)n * n))));
+                                             p->n[0], planes, nn, ps)));
     cur ^= 1;
-    inner = (int64_t)n * n;
+    inner = ps;
     l0 = 2;
   }
   for (int l = l0; l < p->d; ++l) {
@@ -616,7 +668,7 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
   }
   // step 3: shifted time systems
   STIG_TRY((launch_time<S, typename TimeCompute<TC>::type>(p, buf[cur ^ 1], buf[cur], nrhs,
-                                                            transpose)));
+                                                            transpose, tv)));
   cur ^= 1;
   // step 4: back transform, x_l U_l for l = d..1
   for (int l = p->d - 1; l >= l0; --l) {
@@ -628,12 +680,11 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
     }
   }
   if (fuse) {
-    int n = p->n[0];
     if (fuse_sym)
-      STIG_TRY((launch_plane_sym<S, double, TC, false>(p, buf[cur ^ 1], s, tot / ((int64_t)n * n))));
+      STIG_TRY((launch_plane_sym<S, double, TC, false>(p, buf[cur ^ 1], s, planes, ps, nn)));
     else
       STIG_TRY((launch_plane<S, double, TC>(p, buf[cur ^ 1], s, OpSet<TC>::U(p, 0), OpSet<TC>::U(p, 1),
-                                             n, tot / ((int64_t)n * n))));
+                                             p->n[0], planes, ps, nn)));
   }
   return STIG_OK;
 }
@@ -995,6 +1046,7 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
   p->ready = false;
   p->gamma = gamma;
   p->nu = nu;
+  p->lamp_ps = 0;  // padded shifts are rebuilt from the new ones
   hipStream_t s = p->stream;
   std::vector<std::vector<double>> lams(p->d);
   for (int l = 0; l < p->d; ++l) {
@@ -1391,7 +1443,7 @@ stig_status stig_profile_get(stig_plan *p, int kind, double *total_ms, double *b
 size_t stig_plan_device_bytes(const stig_plan *p) {
   if (!p) return 0;
   size_t t = 0;
-  const DevBuf *bs[] = {&p->lam, &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
+  const DevBuf *bs[] = {&p->lam, &p->lamp, &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
                         &p->tR64[0], &p->tR64[1], &p->tR32[0], &p->tR32[1],
                         &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->s0, &p->s1, &p->tscr, &p->m0,
                         &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->w, &p->tmp, &p->partial,
