@@ -5,7 +5,9 @@ The compute lives in libstig.so (HIP kernels behind a C ABI, include/stig.h);
 this package only marshals arguments.  Importing it loads the library and fails
 if it has not been built.
 """
-from ._lib import LIB_PATH, StigError, lib  # noqa: F401
+import torch  # noqa: F401  (torch's HIP runtime first: libstig then binds to the same one)
+
+from ._lib import LIB_PATH, StigError, lib  # noqa: E402,F401
 
 lib()  # fail loudly at import if the HIP library is missing
 

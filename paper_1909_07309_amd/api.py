@@ -50,7 +50,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().stig_plan_destroy(h)
+            try:
+                lib().stig_plan_destroy(h)
+            except Exception:  # interpreter shutdown: module globals already cleared
+                pass
             self._h = None
 
     def _sync_stream(self):

@@ -113,67 +113,69 @@ __device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi
 #pragma unroll
     for (int T = 0; T < Q; ++T) zp[T] = xor_sum(zp[T]) + PV::of(in[(16 * T + c) * ldi + 16 * Q]) * oxff;
   }
-  // ---- product 2, strip by strip: Out = OpY Z
+  // ---- product 2, all strips at once: Out = OpY Z (each OpY fragment read once
+  // per k step serves every strip; Q*Q independent accumulator chains)
   VT yc[Q], ycc = 0;  // RX: output column 16Q (rows 16t + c), corner
 #pragma unroll
   for (int t = 0; t < Q; ++t) yc[t] = 0;
+  typename MF::acc acc2[Q][Q];  // [strip j][row tile t]
+  VT yr[Q];                     // RY: output row 16Q of strip j
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    typename MF::acc acc2[Q];
+    yr[j] = 0;
 #pragma unroll
     for (int t = 0; t < Q; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        acc2[t][v] = 0;
+        acc2[j][t][v] = 0;
         if constexpr (RY != 0)
-          acc2[t][v] = PV::of(opy[(16 * t + MF::out_row(g, v)) * ldo + 16 * Q]) * zr[j];
+          acc2[j][t][v] = PV::of(opy[(16 * t + MF::out_row(g, v)) * ldo + 16 * Q]) * zr[j];
       }
-    VT yr = 0;  // RY: output row 16Q of this strip
+  }
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int T = s / SPT, v0 = (s % SPT) * KPL;
+  for (int s = 0; s < KS; ++s) {
+    const int T = s / SPT, v0 = (s % SPT) * KPL;
+    const int kcol = 16 * T + MF::out_row(g, v0);  // contraction index of slot u: kcol + u
+    typename MF::frag a[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) a[t] = MF::load(opy + (16 * t + c) * ldo + kcol);
+    VT zc[KPL];
+    if constexpr (RX != 0) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) zc[u] = __shfl(zp[T], MF::out_row(g, v0 + u), 64);
+#pragma unroll
+      for (int t = 0; t < Q; ++t)
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) yc[t] += PV::get(a[t], u) * zc[u];
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
       E be[KPL];
 #pragma unroll
       for (int u = 0; u < KPL; ++u) be[u] = PV::to_elem(acc1[j][T][v0 + u]);
       typename MF::frag b = MF::make(be);
-      const int kcol = 16 * T + MF::out_row(g, v0);  // contraction index of slot u: kcol + u
-      VT zc[KPL];
-      if constexpr (RX != 0) {
-        if (j == 0) {
 #pragma unroll
-          for (int u = 0; u < KPL; ++u) zc[u] = __shfl(zp[T], MF::out_row(g, v0 + u), 64);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < Q; ++t) {
-        typename MF::frag a = MF::load(opy + (16 * t + c) * ldo + kcol);
-        acc2[t] = MF::mma(a, b, acc2[t]);
-        if constexpr (RX != 0) {
-          if (j == 0) {
-#pragma unroll
-            for (int u = 0; u < KPL; ++u) yc[t] += PV::get(a, u) * zc[u];
-          }
-        }
-      }
+      for (int t = 0; t < Q; ++t) acc2[j][t] = MF::mma(a[t], b, acc2[j][t]);
       if constexpr (RY != 0) {
 #pragma unroll
-        for (int u = 0; u < KPL; ++u) {
-          const VT oy = PV::of(opy[16 * Q * ldo + kcol + u]);
-          yr += oy * PV::of(be[u]);
-          if constexpr (RX != 0) {
-            if (j == 0) ycc += oy * zc[u];
-          }
-        }
+        for (int u = 0; u < KPL; ++u) yr[j] += PV::of(opy[16 * Q * ldo + kcol + u]) * PV::of(be[u]);
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (RY != 0 && RX != 0) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) ycc += PV::of(opy[16 * Q * ldo + kcol + u]) * zc[u];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
 #pragma unroll
     for (int t = 0; t < Q; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) store(16 * t + MF::out_row(g, v), 16 * j + c, (VT)acc2[t][v]);
+      for (int v = 0; v < 4; ++v) store(16 * t + MF::out_row(g, v), 16 * j + c, (VT)acc2[j][t][v]);
     if constexpr (RY != 0) {
-      yr = xor_sum(yr) + PV::of(opy[16 * Q * ldo + 16 * Q]) * zr[j];
-      if (g == 0) store(16 * Q, 16 * j + c, yr);
+      const VT r = xor_sum(yr[j]) + PV::of(opy[16 * Q * ldo + 16 * Q]) * zr[j];
+      if (g == 0) store(16 * Q, 16 * j + c, r);
     }
   }
   if constexpr (RX != 0) {
