@@ -100,7 +100,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -187,13 +187,20 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         t = json.load(open(TRAFFIC_FILE))
         if t.get("fingerprint") == kernel_fingerprint():
-            # the dominant class's kernel at this workload's FP64 launch shape
-            key = {"mode_gemm": "stig::mode_gemm_small<double, double, double, 65>",
-                   "plane_gemm": "stig::mode_gemm_plane<double, double, double, 65>",
-                   "time_solve": "stig::time_band_solve_rl<double, double, 66, 3, 7, true>"}.get(dom)
-            k = t["kernels"].get(key)
-            if k:
-                traffic = k["fetch_bytes"] + k["write_bytes"]
+            # the dominant class's FP64 kernels at this workload (forward and
+            # backward variants), bytes per launch averaged over their dispatches
+            prefixes = {"mode_gemm": ("stig::mode_gemm_sym<double, double, double",
+                                      "stig::mode_gemm_small<double, double, double"),
+                        "plane_gemm": ("stig::mode_gemm_plane_sym<double, double, double",
+                                       "stig::mode_gemm_plane<double, double, double"),
+                        "time_solve": ("stig::time_band_solve_rl<double, double",)}.get(dom, ())
+            for pre in prefixes:
+                ks = [v for k, v in t["kernels"].items() if k.startswith(pre)]
+                if ks:
+                    nd = sum(v["dispatches"] for v in ks)
+                    traffic = sum((v["fetch_bytes"] + v["write_bytes"]) * v["dispatches"]
+                                  for v in ks) / nd
+                    break
     if kd["bound"] == "mfma":
         roofline = {"kernel": dom, "bound": "mfma", "achieved": kd["TFLOPs"],
                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
