@@ -94,7 +94,11 @@ stig_status stig_set_stream(stig_plan *plan, void *stream);
  *     substitution redone segment by segment in the backward sweep (nothing
  *     stored); 3 = the same with the forward-substituted values stored and read
  *     back; 1 = left-looking, U-row checkpoints; 2 = the generic kernel with
- *     scratch memory (the one every other shape uses).
+ *     scratch memory (the one every other shape uses); 4 = the paper's own
+ *     form (Section 4.2.2, eq. time_eig_2, eq. block_LU): the time pencil
+ *     transformed by the real block form of its arrowhead factorization (dense
+ *     products along t on MFMA) and the arrowhead middle factor solved by block
+ *     LU, for n_t = 34 and 66 (other n_t use 0).
  *   STIG_OPT_PARITY_SPLIT: 1 (default) = where a spatial pencil is
  *     persymmetric (stig_setup_1d_pencils then picks an eigenbasis of even and
  *     odd modes), its mode products run as two half-size products around a
@@ -310,6 +314,18 @@ stig_status stig_sym_eig(int n, const double *K, const double *M, double *U,
  * exposed for testing.  STIG_EINVAL if the pencil is not persymmetric. */
 stig_status stig_split_eig(int n, const double *K, const double *M, double *U,
                            double *lam);
+
+/* Real block form of the paper's arrowhead factorization of a time pencil
+ * (Section 4.2.2, eq. time_eig_2): W, M (host, n x n row-major, the leading
+ * (n-1) block of W skew-symmetric, M SPD) -> U and D = U^T W U (host, n x n
+ * row-major) with U^T M U = I; D is block diagonal in its leading n-1 rows and
+ * columns (a zero 1 x 1 block first when n-1 is odd, then 2 x 2 blocks
+ * [[0, d], [-d, 0]]) plus its last row and column.  *nzero receives 1 or 0.
+ * The factorization stig_setup_1d_pencils uses for STIG_OPT_TIME_KERNEL = 4;
+ * exposed for testing.  STIG_EBREAKDOWN if M is not SPD or the block structure
+ * is not reached to 1e-10 relative. */
+stig_status stig_time_arrowhead(int n, const double *W, const double *M, double *U, double *D,
+                                int *nzero);
 
 const char *stig_status_string(stig_status status);
 const char *stig_last_error(void);

@@ -62,6 +62,7 @@ SIGNATURES = {
     "stig_load_1d": (C.c_int, [C.c_int, C.c_int, C.c_double, _dp, C.c_int, _dp]),
     "stig_sym_eig": (C.c_int, [C.c_int, _dp, _dp, _dp, _dp]),
     "stig_split_eig": (C.c_int, [C.c_int, _dp, _dp, _dp, _dp]),
+    "stig_time_arrowhead": (C.c_int, [C.c_int, _dp, _dp, _dp, _dp, _ip]),
     "stig_status_string": (C.c_char_p, [C.c_int]),
     "stig_last_error": (C.c_char_p, []),
 }

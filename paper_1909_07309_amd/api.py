@@ -176,12 +176,13 @@ class Plan:
     KERNEL_KINDS = ("mode_gemm", "time_solve", "band_pass", "krylov", "csr", "plane_gemm")
 
     OPTIONS = {"plane_fusion": 0, "time_kernel": 1, "parity_split": 2}
-    TIME_KERNELS = {"right_looking": 0, "left_looking": 1, "generic": 2, "right_looking_stored": 3}
+    TIME_KERNELS = {"right_looking": 0, "left_looking": 1, "generic": 2, "right_looking_stored": 3,
+                    "arrowhead": 4}
 
     def set_option(self, name, value):
         """Kernel choices of apply_Pinv (same results up to rounding order):
         plane_fusion (bool, default True), time_kernel ("right_looking" default,
-        "right_looking_stored", "left_looking", "generic"), parity_split (bool,
+        "right_looking_stored", "left_looking", "generic", "arrowhead"), parity_split (bool,
         default True)."""
         if name == "time_kernel" and isinstance(value, str):
             value = self.TIME_KERNELS[value]
@@ -312,3 +313,15 @@ def split_eig(K, M):
     lam = np.empty(n)
     check(lib().stig_split_eig(n, dptr(K), dptr(M), dptr(U), dptr(lam)))
     return lam, U
+
+
+def time_arrowhead(W, M):
+    """(U, D, nzero): real block form of the arrowhead factorization (stig_time_arrowhead)."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = W.shape[0]
+    U = np.empty((n, n))
+    D = np.empty((n, n))
+    nz = C.c_int()
+    check(lib().stig_time_arrowhead(n, dptr(W), dptr(M), dptr(U), dptr(D), C.byref(nz)))
+    return U, D, nz.value

@@ -424,4 +424,153 @@ bool split_eig(int n, const double *K, const double *M, double *U, double *lam) 
   return true;
 }
 
+// Real block form of the arrowhead factorization of a time pencil (W, M)
+// (Section 4.2.2, eq. time_eig_2).  The leading (n-1) blocks W0, M0 have
+// W0 + W0^T = 0 (eq. integral_W), so with M0 = L L^T the matrix
+// S = L^{-1} W0 L^{-T} is real skew-symmetric.  Its real Schur form
+// S = Q B Q^T has 2 x 2 blocks [[0, mu], [-mu, 0]] and, for odd n-1, one zero;
+// it is found from the symmetric eigenproblem of S^T S = -S^2 (eigenvalues
+// mu^2 twice): for each pair, q1 is an eigenvector (orthogonalised against the
+// ones already taken) and q2 = S q1 / |S q1|.  U0 = L^{-T} Q, the last column
+// of U is (-M0^{-1} m, 1) normalised in the M norm (eq. syst_v), so that
+// U^T M U = I and D = U^T W U is block diagonal plus the last row and column.
+// Output (all row-major, modes in the order: zero mode first if n-1 is odd,
+// then the pairs, then the last mode): U (n x n), D (n x n); returns false if
+// M0 is not SPD or the block structure is not reached to tol relative.
+bool time_arrowhead(int n, const double *W, const double *M, double tol, double *U, double *D,
+                    int *nzero) {
+  const int m = n - 1;
+  if (m < 1) return false;
+  std::vector<double> L((size_t)m * m, 0.0);
+  for (int j = 0; j < m; ++j) {  // Cholesky of M0
+    double d = M[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[(size_t)j * m + j] = d;
+    for (int i = j + 1; i < m; ++i) {
+      double v = M[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+      L[(size_t)i * m + j] = v / d;
+    }
+  }
+  auto lsolve = [&](std::vector<double> &x) {  // x <- L^{-1} x
+    for (int i = 0; i < m; ++i) {
+      double v = x[i];
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * m + k] * x[k];
+      x[i] = v / L[(size_t)i * m + i];
+    }
+  };
+  auto ltsolve = [&](std::vector<double> &x) {  // x <- L^{-T} x
+    for (int i = m - 1; i >= 0; --i) {
+      double v = x[i];
+      for (int k = i + 1; k < m; ++k) v -= L[(size_t)k * m + i] * x[k];
+      x[i] = v / L[(size_t)i * m + i];
+    }
+  };
+  // S = L^{-1} W0 L^{-T}, column by column, then skew-symmetrised
+  std::vector<double> S((size_t)m * m), col(m);
+  std::vector<double> T((size_t)m * m);  // T = W0 L^{-T}  (rows of T^T = L^{-1} W0^T)
+  for (int i = 0; i < m; ++i) {  // row i of W0 L^{-T} = (L^{-1} W0[i, :]^T)^T
+    for (int k = 0; k < m; ++k) col[k] = W[(size_t)i * n + k];
+    lsolve(col);
+    for (int k = 0; k < m; ++k) T[(size_t)i * m + k] = col[k];
+  }
+  for (int j = 0; j < m; ++j) {  // column j of L^{-1} T
+    for (int k = 0; k < m; ++k) col[k] = T[(size_t)k * m + j];
+    lsolve(col);
+    for (int k = 0; k < m; ++k) S[(size_t)k * m + j] = col[k];
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double a = 0.5 * (S[(size_t)i * m + j] - S[(size_t)j * m + i]);
+      S[(size_t)i * m + j] = a;
+      S[(size_t)j * m + i] = -a;
+    }
+  for (int i = 0; i < m; ++i) S[(size_t)i * m + i] = 0.0;
+  // eigenvectors of S^T S
+  std::vector<double> StS((size_t)m * m, 0.0), I((size_t)m * m, 0.0), V((size_t)m * m), mu2(m);
+  for (int i = 0; i < m; ++i) {
+    I[(size_t)i * m + i] = 1.0;
+    for (int j = 0; j < m; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < m; ++k) v += S[(size_t)k * m + i] * S[(size_t)k * m + j];
+      StS[(size_t)i * m + j] = v;
+    }
+  }
+  if (!sym_eig(m, StS.data(), I.data(), V.data(), mu2.data())) return false;
+  const int nz = m % 2;
+  std::vector<std::vector<double>> Q;
+  auto ortho = [&](std::vector<double> &x) {
+    for (auto &q : Q) {
+      double d = 0.0;
+      for (int k = 0; k < m; ++k) d += q[k] * x[k];
+      for (int k = 0; k < m; ++k) x[k] -= d * q[k];
+    }
+    double nr = 0.0;
+    for (int k = 0; k < m; ++k) nr += x[k] * x[k];
+    return std::sqrt(nr);
+  };
+  for (int idx = 0; idx < m && (int)Q.size() < m; ++idx) {  // ascending mu^2
+    std::vector<double> q1(m);
+    for (int k = 0; k < m; ++k) q1[k] = V[(size_t)k * m + idx];
+    const double nr = ortho(q1);
+    if (nr < 0.5) continue;  // partner of a pair already taken
+    for (auto &x : q1) x /= nr;
+    Q.push_back(q1);
+    if (nz && Q.size() == 1) continue;  // the zero mode stands alone
+    std::vector<double> q2(m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < m; ++k) q2[i] += S[(size_t)i * m + k] * q1[k];
+    const double n2 = ortho(q2);
+    if (!(n2 > 0.0)) return false;
+    for (auto &x : q2) x /= n2;
+    Q.push_back(q2);
+  }
+  if ((int)Q.size() != m) return false;
+  // U = [[L^{-T} Q, v], [0, c]]
+  std::fill(U, U + (size_t)n * n, 0.0);
+  for (int j = 0; j < m; ++j) {
+    col = Q[j];
+    ltsolve(col);
+    for (int i = 0; i < m; ++i) U[(size_t)i * n + j] = col[i];
+  }
+  std::vector<double> v(m);
+  for (int i = 0; i < m; ++i) v[i] = -M[(size_t)i * n + m];
+  lsolve(v);
+  ltsolve(v);  // v = -M0^{-1} m
+  std::vector<double> c(n);
+  for (int i = 0; i < m; ++i) c[i] = v[i];
+  c[m] = 1.0;
+  double cmc = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) cmc += c[i] * M[(size_t)i * n + k] * c[k];
+  const double cs = 1.0 / std::sqrt(cmc);
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + m] = c[i] * cs;
+  // D = U^T W U
+  std::vector<double> WU((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double w = W[(size_t)i * n + k];
+      if (w == 0.0) continue;
+      for (int j = 0; j < n; ++j) WU[(size_t)i * n + j] += w * U[(size_t)k * n + j];
+    }
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v2 = 0.0;
+      for (int k = 0; k < n; ++k) v2 += U[(size_t)k * n + i] * WU[(size_t)k * n + j];
+      D[(size_t)i * n + j] = v2;
+      dmax = std::max(dmax, std::abs(v2));
+    }
+  // structure check: inside the leading block only the 2 x 2 pair blocks
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const bool inpair = i >= nz && j >= nz && (i - nz) / 2 == (j - nz) / 2 && i != j;
+      if (!inpair && std::abs(D[(size_t)i * n + j]) > tol * dmax) return false;
+    }
+  *nzero = nz;
+  return true;
+}
+
 }  // namespace stig

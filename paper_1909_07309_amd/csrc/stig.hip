@@ -19,6 +19,7 @@
 #include "kernels_plane.h"
 #include "kernels_sym.h"
 #include "kernels_plane_sym.h"
+#include "kernels_arrow.h"
 #include "stig_internal.h"
 
 using namespace stig;
@@ -101,6 +102,10 @@ struct stig_plan {
   int64_t lamp_ps = 0;
   DevBuf tW64, tWT64, tM64, tW32, tWT32, tM32;  // time bands (unscaled)
   DevBuf tR64[2], tR32[2];  // step records of [W; M] and [W^T; M] (right-looking solve)
+  // arrowhead form of the time pencil (n_t = 32 q + 2): U^T and U in mode order
+  // per precision [f64, f32, bf16], tables [d | g | h | sigma] plain / transposed
+  bool arrow_ok = false;
+  DevBuf aTf[3], aTb[3], aTab64[2], aTab32[2];
   DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
   DevBuf sK[3], sM[3];    // spatial bands (matvec, mass apply)
   DevBuf dmh;             // D^{-1/2}, N doubles (optional)
@@ -246,6 +251,61 @@ template <> std::vector<uint16_t> convert(const std::vector<double> &v) {
   std::vector<uint16_t> o(v.size());
   for (size_t i = 0; i < v.size(); ++i) o[i] = float_to_bf16_bits((float)v[i]);
   return o;
+}
+
+// Arrowhead form of the time pencil for the fused time kernel (kernels_arrow.h):
+// for n_t = 32 q + 2 with a zero mode, U^T / U in the kernel's mode order and the
+// block-LU tables, for W_t and (transposed systems) W_t^T, whose form is D^T:
+// d -> -d, arrow column and row exchanged.  Other shapes leave arrow_ok false.
+stig_status setup_arrowhead(stig_plan *p, const double *Wt, const double *Mt) {
+  p->arrow_ok = false;
+  const int n = p->nt;
+  if (n < 34 || (n - 2) % 32 != 0) return STIG_OK;
+  std::vector<double> U((size_t)n * n), D((size_t)n * n);
+  int nz = 0;
+  if (!time_arrowhead(n, Wt, Mt, 1e-10, U.data(), D.data(), &nz) || nz != 1) return STIG_OK;
+  const int NM = n - 2;  // modes in 2 x 2 blocks
+  // mode order: block j -> rows 32 (j/16) + j%16 and that + 16; zero mode NM;
+  // last mode NM + 1.  perm[r] = natural index (zero mode 0, block j: 1 + 2j, 2 + 2j).
+  std::vector<int> perm(n);
+  for (int j = 0; j < NM / 2; ++j) {
+    const int r1 = 32 * (j / 16) + j % 16;
+    perm[r1] = 1 + 2 * j;
+    perm[r1 + 16] = 2 + 2 * j;
+  }
+  perm[NM] = 0;
+  perm[NM + 1] = n - 1;
+  std::vector<double> tf((size_t)n * n), tb((size_t)n * n);
+  for (int r = 0; r < n; ++r)
+    for (int t = 0; t < n; ++t) {
+      tf[(size_t)r * n + t] = U[(size_t)t * n + perm[r]];
+      tb[(size_t)t * n + r] = U[(size_t)t * n + perm[r]];
+    }
+  for (int tr = 0; tr < 2; ++tr) {
+    std::vector<double> tab((size_t)3 * n + 1, 0.0);
+    for (int r = 0; r < NM; ++r) {
+      const int a = perm[r] - ((perm[r] - 1) % 2);  // first member of the block
+      const double d = D[(size_t)a * n + a + 1];
+      tab[r] = tr ? -d : d;
+    }
+    for (int r = 0; r <= NM; ++r) {
+      const double gcol = D[(size_t)perm[r] * n + (n - 1)], hrow = D[(size_t)(n - 1) * n + perm[r]];
+      tab[n + r] = tr ? hrow : gcol;
+      tab[2 * n + r] = tr ? gcol : hrow;
+    }
+    tab[3 * n] = D[(size_t)(n - 1) * n + (n - 1)];
+    STIG_TRY(upload(p->aTab64[tr], tab, p->stream));
+    STIG_TRY(upload(p->aTab32[tr], convert<float>(tab), p->stream));
+  }
+  STIG_TRY(upload(p->aTf[0], tf, p->stream));
+  STIG_TRY(upload(p->aTb[0], tb, p->stream));
+  STIG_TRY(upload(p->aTf[1], convert<float>(tf), p->stream));
+  STIG_TRY(upload(p->aTb[1], convert<float>(tb), p->stream));
+  STIG_TRY(upload(p->aTf[2], convert<uint16_t>(tf), p->stream));
+  STIG_TRY(upload(p->aTb[2], convert<uint16_t>(tb), p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->arrow_ok = true;
+  return STIG_OK;
 }
 
 inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
@@ -540,10 +600,58 @@ stig_status launch_time_rl2(stig_plan *p, const Tio *in, Tio *out, int nrhs, int
   return launch_time_rl<Tio, TC, NT, P, NSEG, false, 0>(p, in, out, nrhs, transpose, tv);
 }
 
+// MFMA type of the arrowhead transforms: that of the apply's GEMMs, i.e. the
+// storage type of the intermediates (FP64, FP32 or BF16).
+template <typename Tio, typename TC> struct TimeArrowType { typedef Tio type; };
+
+// Step 3 in the arrowhead form (time_kernel 4); n_t = 32 Q + 2.
+template <typename Tio, typename TC, int Q>
+stig_status launch_time_arrow_q(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                                TimeView tv) {
+  typedef typename Mfma<TC>::elem E;
+  typedef typename PlaneVal<TC>::vt VT;
+  constexpr int NT = 32 * Q + 2;
+  const int pi = PrecIdx<TC>::v;
+  const VT *tabs = std::is_same<VT, double>::value ? (const VT *)p->aTab64[transpose ? 1 : 0].p
+                                                   : (const VT *)p->aTab32[transpose ? 1 : 0].p;
+  const size_t lds = ((size_t)2 * NT * lds_pad<TC>(NT) * sizeof(E) + 15) / 16 * 16 +
+                     (size_t)(3 * NT + 1) * sizeof(VT);
+  auto kern = time_arrow_solve<Tio, TC, Q>;
+  static int per_cu = 0;  // per instantiation: resident blocks per CU
+  if (per_cu == 0) {
+    if (lds > 65536)
+      HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, ARROW_THREADS, lds));
+    per_cu = std::max(nb, 1);
+  }
+  const int64_t cols = tv.ns * nrhs;
+  if (cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
+  const int64_t nstrips = (cols + 15) / 16;
+  const unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, (int64_t)per_cu * p->num_cu);
+  ProfScope ps(p, STIG_K_TIME_SOLVE, (double)cols * NT * 2 * sizeof(Tio));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(ARROW_THREADS), lds, p->stream, in, out, tv.lam,
+                     p->aTf[pi].as<E>(), p->aTb[pi].as<E>(), tabs, (VT)p->gamma, (VT)p->nu, tv.ns,
+                     cols);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+template <typename Tio, typename TC>
+stig_status launch_time_arrow(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                              TimeView tv) {
+  if (p->nt == 66) return launch_time_arrow_q<Tio, TC, 2>(p, in, out, nrhs, transpose, tv);
+  if (p->nt == 34) return launch_time_arrow_q<Tio, TC, 1>(p, in, out, nrhs, transpose, tv);
+  return fail(STIG_EINVAL, "no arrowhead kernel for this n_t");
+}
+
 template <typename Tio, typename TC>
 stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
                         TimeView tv) {
   // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
+  if (p->time_kernel == 4 && p->arrow_ok && (p->nt == 66 || p->nt == 34))
+    return launch_time_arrow<Tio, typename TimeArrowType<Tio, TC>::type>(p, in, out, nrhs, transpose, tv);
   if (p->time_kernel == 1) {
     if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose, tv);
     if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose, tv);
@@ -1023,7 +1131,7 @@ stig_status stig_set_option(stig_plan *plan, int option, int value) {
       plan->parity_split = value != 0;
       return STIG_OK;
     case STIG_OPT_TIME_KERNEL:
-      if (value < 0 || value > 3) return fail(STIG_EINVAL, "time kernel takes 0 .. 3");
+      if (value < 0 || value > 4) return fail(STIG_EINVAL, "time kernel takes 0 .. 4");
       plan->time_kernel = value == 3 ? 0 : value;
       plan->time_recompute = value != 3;
       return STIG_OK;
@@ -1146,6 +1254,7 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     STIG_TRY(upload(p->tR64[tr], rec, s));
     STIG_TRY(upload(p->tR32[tr], convert<float>(rec), s));
   }
+  STIG_TRY(setup_arrowhead(p, Wt, Mt));
   std::vector<double> gw(wb), gwt(wtb), nm(mb);
   for (auto &v : gw) v *= gamma;
   for (auto &v : gwt) v *= gamma;
@@ -1443,7 +1552,9 @@ stig_status stig_profile_get(stig_plan *p, int kind, double *total_ms, double *b
 size_t stig_plan_device_bytes(const stig_plan *p) {
   if (!p) return 0;
   size_t t = 0;
-  const DevBuf *bs[] = {&p->lam, &p->lamp, &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
+  const DevBuf *bs[] = {&p->lam, &p->lamp, &p->aTf[0], &p->aTf[1], &p->aTf[2], &p->aTb[0],
+                        &p->aTb[1], &p->aTb[2], &p->aTab64[0], &p->aTab64[1], &p->aTab32[0],
+                        &p->aTab32[1], &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
                         &p->tR64[0], &p->tR64[1], &p->tR32[0], &p->tR32[1],
                         &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->s0, &p->s1, &p->tscr, &p->m0,
                         &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->w, &p->tmp, &p->partial,
@@ -1486,6 +1597,14 @@ stig_status stig_load_1d(int n_el, int p, double length, const double *fvals, in
 stig_status stig_sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
   if (n < 1 || !K || !M || !U || !lam) return fail(STIG_EINVAL, "bad eigenproblem arguments");
   if (!sym_eig(n, K, M, U, lam)) return fail(STIG_EBREAKDOWN, "M is not positive definite");
+  return STIG_OK;
+}
+
+stig_status stig_time_arrowhead(int n, const double *W, const double *M, double *U, double *D,
+                                int *nzero) {
+  if (n < 2 || !W || !M || !U || !D || !nzero) return fail(STIG_EINVAL, "bad arrowhead arguments");
+  if (!time_arrowhead(n, W, M, 1e-10, U, D, nzero))
+    return fail(STIG_EBREAKDOWN, "no arrowhead factorization (M not SPD or structure not reached)");
   return STIG_OK;
 }
 

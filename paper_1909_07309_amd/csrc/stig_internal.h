@@ -44,4 +44,10 @@ bool persymmetric(int n, const double *A, double tol);
 // ascending within each group; same normalisation as sym_eig.
 bool split_eig(int n, const double *K, const double *M, double *U, double *lam);
 
+// Real block form of the arrowhead factorization of a time pencil: U (n x n)
+// with U^T M U = I and D = U^T W U block diagonal (a zero mode first when n-1
+// is odd, then 2 x 2 skew blocks) plus the last row and column.
+bool time_arrowhead(int n, const double *W, const double *M, double tol, double *U, double *D,
+                    int *nzero);
+
 }  // namespace stig

@@ -105,6 +105,44 @@ def test_split_eigenbasis_rejects_a_non_persymmetric_pencil():
         api.split_eig(K, M)
 
 
+@pytest.mark.parametrize("n_el,p", [(8, 2), (32, 3), (64, 3)])
+def test_host_arrowhead_matches_the_oracle_factorization(n_el, p):
+    """The real block form of the time pencil's arrowhead factorization: U^T M U = I,
+    block structure of D, its 2 x 2 blocks carry the oracle's purely imaginary
+    eigenvalues, and U (gamma D + nu lam I)^{-1} U^T solves the shifted system."""
+    from paper_1909_07309_amd import api
+    from oracle.arrowhead import time_arrowhead as oracle_arrowhead
+    Wt, Mt = bs.time_matrices(n_el, p)
+    U, D, nz = api.time_arrowhead(Wt, Mt)
+    n = Wt.shape[0]
+    assert np.abs(U.T @ Mt @ U - np.eye(n)).max() < 1e-12
+    assert np.abs(U.T @ Wt @ U - D).max() < 1e-12 * np.abs(D).max()
+    m = n - 1
+    assert nz == m % 2
+    if nz:
+        assert abs(D[0, 0]) < 1e-12 * np.abs(D).max()
+    blocks = []
+    for a in range(nz, m, 2):
+        B = D[a:a + 2, a:a + 2]
+        assert abs(B[0, 0]) + abs(B[1, 1]) < 1e-11 * np.abs(D).max()
+        assert abs(B[0, 1] + B[1, 0]) < 1e-11 * np.abs(D).max()
+        blocks.append(abs(B[0, 1]))
+    inner = D[:m, :m].copy()
+    for a in range(nz, m, 2):
+        inner[a:a + 2, a:a + 2] = 0
+    assert np.abs(inner).max() < 1e-10 * np.abs(D).max()
+    _, _, lam_ring, _, sigma = oracle_arrowhead(Wt, Mt)
+    mu = np.sort(np.abs(lam_ring.imag))
+    ours = np.sort(np.concatenate([[0.0] * nz, blocks, blocks]))
+    assert np.abs(mu - ours).max() < 1e-10 * mu.max()
+    assert abs(D[-1, -1] - sigma.real) < 1e-12 * abs(sigma)
+    for lam in (3.0, 250.0):
+        x = np.random.default_rng(1).standard_normal(n)
+        ref = np.linalg.solve(Wt + lam * Mt, x)
+        got = U @ np.linalg.solve(D + lam * np.eye(n), U.T @ x)
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
 def test_argument_validation_without_gpu():
     L = _lib()
     lib = L.lib()
@@ -120,8 +158,8 @@ def test_argument_validation_without_gpu():
     # kernel options: known values accepted, anything else rejected
     assert lib.stig_set_option(h, 0, 0) == 0 and lib.stig_set_option(h, 0, 1) == 0
     assert lib.stig_set_option(h, 0, 2) == -1
-    assert all(lib.stig_set_option(h, 1, v) == 0 for v in (0, 1, 2, 3))
-    assert lib.stig_set_option(h, 1, 4) == -1 and lib.stig_set_option(h, 1, -1) == -1
+    assert all(lib.stig_set_option(h, 1, v) == 0 for v in (0, 1, 2, 3, 4))
+    assert lib.stig_set_option(h, 1, 5) == -1 and lib.stig_set_option(h, 1, -1) == -1
     assert lib.stig_set_option(h, 2, 0) == 0 and lib.stig_set_option(h, 2, 1) == 0
     assert lib.stig_set_option(h, 2, 5) == -1
     assert lib.stig_set_option(h, 7, 0) == -1
