@@ -170,4 +170,165 @@ __global__ void csr_spmv(const int64_t *__restrict__ rowptr, const int32_t *__re
   }
 }
 
+// Spatial part of the matvec in one pass over each (rhs, t) slice (d = 2, 3):
+//   a = x x_1 M_1 x_2 M_2 x_3 M_3,   b = x x_1 K_1 x_2 M_2 x_3 M_3
+//       + x x_1 M_1 x_2 K_2 x_3 M_3 + x x_1 M_1 x_2 M_2 x_3 K_3
+// (for d = 2 the third factors are the identity and zero).  A block owns R
+// rows y (all x) of one slice and a chunk of planes z, and streams along z.
+// Thread (yy, xx) keeps one column: its rows of the x band and of the y band
+// live in registers.  Per input plane it moves its window rows yy and yy + R
+// (the y halo of P rows on each side needs R >= 2P) to LDS, forms their x
+// products (M_1, K_1), and after one barrier the y products of its own row,
+// which enter a register window of 2P + 1 planes; the z products (scalar
+// band loads, z is uniform) give a and b.  The LDS tiles are double-buffered
+// so one barrier per plane suffices, and input planes are loaded SPF planes
+// ahead of their LDS store into registers.  One read of x (plus halos, mostly L2 hits) and one
+// write of a and b: about 24 bytes per unknown, against 88 for three separate
+// axis passes.  Bands (device, [n][2P+1], entry m of row i at column
+// i + m - P, zero outside): M0, K0 (x), M1, K1 (y), M2, K2 (z).
+constexpr int STENCIL_SPF = 1;  // input planes in flight per thread
+
+template <int P>
+__device__ __forceinline__ int stencil_ldx(int nx) {
+  return nx + 2 * P;  // x rows with P zero columns on each side
+}
+
+constexpr int STENCIL_THREADS = 512;  // at most R * nx threads per block
+
+template <int P>
+__global__ void __launch_bounds__(STENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2)))
+spatial_stencil(const double *__restrict__ x, double *__restrict__ a, double *__restrict__ b,
+                const double *__restrict__ M0, const double *__restrict__ K0,
+                const double *__restrict__ M1, const double *__restrict__ K1,
+                const double *__restrict__ M2, const double *__restrict__ K2, int nx, int ny,
+                int nz, int R, int ZC, int64_t slices) {
+  constexpr int B = 2 * P + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int rows = R + 2 * P, ldx = stencil_ldx<P>(nx);
+  // [2][rows][ldx] input rows, [2][rows][nx] M_1 and K_1 products
+  double *xin = reinterpret_cast<double *>(smem);
+  double *xu = xin + 2 * rows * ldx;
+  double *xv = xu + 2 * rows * nx;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * rows * ldx; e += blockDim.x) xin[e] = 0.0;  // zero x pads
+  const int ntiles = (ny + R - 1) / R, nchunks = (nz + ZC - 1) / ZC;
+  int64_t blk = blockIdx.x;
+  const int chunk = (int)(blk % nchunks);
+  blk /= nchunks;
+  const int64_t slice = blk / ntiles;
+  const int y0 = (int)(blk - slice * ntiles) * R;
+  if (slice >= slices) return;  // whole block: no barrier is skipped by part of it
+  const int z0 = chunk * ZC, z1 = min(nz, z0 + ZC);  // outputs z0 .. z1-1
+  const int64_t plane = (int64_t)nx * ny;
+  const double *xs = x + slice * plane * nz;
+  double *as = a + slice * plane * nz, *bs = b + slice * plane * nz;
+  const bool act = tid < R * nx;
+  const int yy = act ? tid / nx : 0, xx = act ? tid - yy * nx : 0;
+  const int y = y0 + yy;
+  const bool out_ok = act && y < ny;
+  const bool two = act && yy + R < rows;  // second window row yy + R
+  // window rows yy, yy + R are the global rows y0 - P + yy, y0 - P + yy + R
+  const int ya = y0 - P + yy, yb = ya + R;
+  const bool oka = act && ya >= 0 && ya < ny, okb = two && yb >= 0 && yb < ny;
+  double bxm[B], bxk[B], bym[B], byk[B];
+#pragma unroll
+  for (int m = 0; m < B; ++m) {
+    bxm[m] = M0[xx * B + m];
+    bxk[m] = K0[xx * B + m];
+    bym[m] = out_ok ? M1[y * B + m] : 0.0;
+    byk[m] = out_ok ? K1[y * B + m] : 0.0;
+  }
+  cptr<double> mz = as_const(M2), kz = as_const(K2);
+  double Aw[B], Bw[B];
+#pragma unroll
+  for (int m = 0; m < B; ++m) Aw[m] = Bw[m] = 0.0;
+  // input planes z0 - P .. z1 + P - 1
+  const int zfirst = z0 - P, zlast = z1 + P;
+  double ra[STENCIL_SPF], rb[STENCIL_SPF];
+  auto gload = [&](int zin, double &va, double &vb) {
+    const bool zok = zin >= 0 && zin < nz;
+    const int64_t base = (int64_t)(zok ? zin : 0) * plane + xx;
+    const double u = xs[base + (int64_t)(oka ? ya : 0) * nx];
+    const double v = xs[base + (int64_t)(okb ? yb : 0) * nx];
+    va = (zok && oka) ? u : 0.0;
+    vb = (zok && okb) ? v : 0.0;
+  };
+#pragma unroll
+  for (int k = 0; k < STENCIL_SPF; ++k) gload(zfirst + k, ra[k], rb[k]);
+  // pushes the oldest loaded plane into LDS buffer `buf` and loads plane `znext`
+  auto push = [&](int buf, int znext) {
+    double *xi = xin + buf * rows * ldx + P;
+    if (act) xi[yy * ldx + xx] = ra[0];
+    if (two) xi[(yy + R) * ldx + xx] = rb[0];
+#pragma unroll
+    for (int k = 0; k + 1 < STENCIL_SPF; ++k) {
+      ra[k] = ra[k + 1];
+      rb[k] = rb[k + 1];
+    }
+    gload(znext, ra[STENCIL_SPF - 1], rb[STENCIL_SPF - 1]);
+  };
+  __syncthreads();  // x pads are zero before the first row store
+  push(0, zfirst + STENCIL_SPF);
+  __syncthreads();
+  for (int zin = zfirst; zin < zlast; ++zin) {
+    const int buf = (zin - zfirst) & 1;
+    const double *xi = xin + buf * rows * ldx + P;
+    double *u = xu + buf * rows * nx, *v = xv + buf * rows * nx;
+    // x products of window rows yy and yy + R (column xx) of plane zin
+    if (act) {
+      double su = 0.0, sv = 0.0, tu = 0.0, tv = 0.0;
+      const double *r0 = xi + yy * ldx + xx - P, *r1 = r0 + R * ldx;
+#pragma unroll
+      for (int m = 0; m < B; ++m) {
+        const double c0 = r0[m];
+        su += bxm[m] * c0;
+        sv += bxk[m] * c0;
+      }
+      u[yy * nx + xx] = su;
+      v[yy * nx + xx] = sv;
+      if (two) {
+#pragma unroll
+        for (int m = 0; m < B; ++m) {
+          const double c1 = r1[m];
+          tu += bxm[m] * c1;
+          tv += bxk[m] * c1;
+        }
+        u[(yy + R) * nx + xx] = tu;
+        v[(yy + R) * nx + xx] = tv;
+      }
+    }
+    // plane zin + 1 into the other buffer (its previous plane's x products are
+    // done: they preceded the last barrier); one barrier per plane
+    push(buf ^ 1, zin + 1 + STENCIL_SPF);
+    __syncthreads();
+    // y products of this thread's row -> the z window
+    double An = 0.0, Bn = 0.0;
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+      const double uu = u[(yy + m) * nx + xx], vv = v[(yy + m) * nx + xx];
+      An += bym[m] * uu;
+      Bn += bym[m] * vv + byk[m] * uu;
+    }
+#pragma unroll
+    for (int m = 0; m < B - 1; ++m) {
+      Aw[m] = Aw[m + 1];
+      Bw[m] = Bw[m + 1];
+    }
+    Aw[B - 1] = An;
+    Bw[B - 1] = Bn;
+    const int z = zin - P;
+    if (z >= z0 && out_ok) {
+      double sa = 0.0, sb = 0.0;
+#pragma unroll
+      for (int m = 0; m < B; ++m) {
+        const double cm = mz[z * B + m], ck = kz[z * B + m];
+        sa += cm * Aw[m];
+        sb += ck * Aw[m] + cm * Bw[m];
+      }
+      const int64_t o = (int64_t)z * plane + (int64_t)y * nx + xx;
+      as[o] = sa;
+      bs[o] = sb;
+    }
+  }
+}
 }  // namespace stig

@@ -108,6 +108,7 @@ struct stig_plan {
   DevBuf aTf[3], aTb[3], aTab64[2], aTab32[2];
   DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
   DevBuf sK[3], sM[3];    // spatial bands (matvec, mass apply)
+  DevBuf sId, sZero;      // one-row identity / zero band (third direction of a 2D stencil)
   DevBuf dmh;             // D^{-1/2}, N doubles (optional)
   // host copies of the diagonals of the 1D factors (geometry scaling)
   std::vector<double> dK1[3], dM1[3], dWt, dMt;
@@ -853,6 +854,58 @@ stig_status spatial_chain(stig_plan *p, const double *x, int64_t tot, bool with_
   return STIG_OK;
 }
 
+template <int P>
+stig_status launch_stencil_p(stig_plan *p, const double *x, double *a, double *b, int nrhs) {
+  const int nx = p->n[0], ny = p->n[1], nz = p->d == 3 ? p->n[2] : 1;
+  // R rows per block (R >= 2P: each thread holds two of the R + 2P window rows)
+  const int rmax = std::max(2 * P, std::min(8, STENCIL_THREADS / nx));
+  const int R = std::max(2 * P, (ny + (ny + rmax - 1) / rmax - 1) / ((ny + rmax - 1) / rmax));
+  if (R * nx > STENCIL_THREADS) return fail(STIG_EINVAL, "plane too wide for the stencil pass");
+  const int threads = (R * nx + 63) / 64 * 64;
+  // z chunks of at most 16 planes per block (the halo of 2P planes is recomputed)
+  const int nch = (nz + 15) / 16, ZC = (nz + nch - 1) / nch;
+  const size_t lds = (size_t)2 * (R + 2 * P) * (2 * nx + nx + 2 * P) * sizeof(double);
+  if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "plane too wide for the stencil pass");
+  auto kern = spatial_stencil<P>;
+  static size_t configured = 0;
+  if (lds > 65536 && lds > configured) {
+    HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    configured = lds;
+  }
+  const int64_t slices = (int64_t)p->nt * nrhs;
+  const int64_t blocks = slices * ((ny + R - 1) / R) * ((nz + ZC - 1) / ZC);
+  // third direction: the z bands, or identity / zero for d = 2
+  const double *M2 = p->d == 3 ? p->sM[2].as<double>() : p->sId.as<double>();
+  const double *K2 = p->d == 3 ? p->sK[2].as<double>() : p->sZero.as<double>();
+  ProfScope ps(p, STIG_K_BAND_PASS, (double)p->N * nrhs * 24);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, p->stream, x, a, b,
+                     p->sM[0].as<double>(), p->sK[0].as<double>(), p->sM[1].as<double>(),
+                     p->sK[1].as<double>(), M2, K2, nx, ny, nz, R, ZC, slices);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+// The stencil pass holds R >= 2P full rows of x per block of at most
+// STENCIL_THREADS threads; wider planes take the per-axis passes.
+bool stencil_fits(const stig_plan *p) {
+  return p->d >= 2 && p->ps >= 1 && p->ps <= 5 &&
+         std::max(2 * p->ps, std::min(8, STENCIL_THREADS / p->n[0])) * p->n[0] <= STENCIL_THREADS;
+}
+
+stig_status launch_stencil(stig_plan *p, const double *x, double *a, double *b, int nrhs) {
+  if (p->d == 2 && (p->sId.bytes == 0 || p->sZero.bytes == 0))
+    return fail(STIG_ESTATE, "stencil bands missing");
+  switch (p->ps) {
+    case 1: return launch_stencil_p<1>(p, x, a, b, nrhs);
+    case 2: return launch_stencil_p<2>(p, x, a, b, nrhs);
+    case 3: return launch_stencil_p<3>(p, x, a, b, nrhs);
+    case 4: return launch_stencil_p<4>(p, x, a, b, nrhs);
+    case 5: return launch_stencil_p<5>(p, x, a, b, nrhs);
+  }
+  return fail(STIG_EINVAL, "unsupported degree");
+}
+
 stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int transpose) {
   const int64_t tot = p->N * nrhs;
   if (p->csr_rowptr) {
@@ -866,9 +919,18 @@ stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int t
     return STIG_OK;
   }
   DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
-  for (auto *b : bufs) STIG_TRY(b->ensure(tot * sizeof(double)));
   const double *a, *b;
-  STIG_TRY(spatial_chain(p, x, tot, true, &a, &b, bufs));
+  if (stencil_fits(p)) {
+    // spatial part in one stencil pass per (rhs, t) slice
+    STIG_TRY(p->m0.ensure(tot * sizeof(double)));
+    STIG_TRY(p->m1.ensure(tot * sizeof(double)));
+    STIG_TRY(launch_stencil(p, x, p->m0.as<double>(), p->m1.as<double>(), nrhs));
+    a = p->m0.as<double>();
+    b = p->m1.as<double>();
+  } else {
+    for (auto *bb : bufs) STIG_TRY(bb->ensure(tot * sizeof(double)));
+    STIG_TRY(spatial_chain(p, x, tot, true, &a, &b, bufs));
+  }
   // time pass: y = nu (b x_t M_t) + gamma (a x_t W_t)
   const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
   STIG_TRY(band_pass(p, p->pt, a, b, nullptr, y, nullptr, p->tnM.as<double>(), gW, p->nt, p->Ns,
@@ -1229,6 +1291,12 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     lk[k] = v;
   }
   STIG_TRY(upload(p->lam, lk, s));
+  {
+    std::vector<double> id(2 * p->ps + 1, 0.0), zero(2 * p->ps + 1, 0.0);
+    id[p->ps] = 1.0;
+    STIG_TRY(upload(p->sId, id, s));
+    STIG_TRY(upload(p->sZero, zero, s));
+  }
   int nt = p->nt, P = p->pt;
   std::vector<double> WT((size_t)nt * nt);
   for (int i = 0; i < nt; ++i)
