@@ -240,9 +240,12 @@ stig_status stig_lift_adjoint(stig_plan *plan, const double *a_col,
 
 /* Solve A u = f for nrhs right-hand sides by restarted GMRES(restart) with right
  * preconditioning by A-hat^{-1} (or A-hat^{-T} with transpose = 1, which solves
- * A^T u = f).  flexible = 1 selects flexible GMRES (stores the preconditioned
- * vectors; required when prec != STIG_FP64 because the low-precision apply is not
- * a fixed linear operator).  Arnoldi with classical Gram-Schmidt and one
+ * A^T u = f).  flexible = 1 selects flexible GMRES, required when prec !=
+ * STIG_FP64 because the low-precision apply is not a fixed linear operator.  Both
+ * variants keep the m preconditioned basis vectors on the device (m * N doubles)
+ * and form the update as u += Z y, which for a fixed preconditioner equals
+ * P^{-1} (V y) and saves one apply per cycle.  A zero initial guess skips the
+ * first product (r_0 = f).  Arnoldi with classical Gram-Schmidt and one
  * re-orthogonalisation, all in FP64 on the device; Givens rotations on the host.
  * u: device, in = initial guess, out = solution.  Stops when the FP64 true
  * relative residual ||f - A u|| / ||f|| <= rtol, or after maxit inner iterations

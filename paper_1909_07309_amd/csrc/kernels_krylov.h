@@ -13,83 +13,191 @@ constexpr int KRY_BLOCK = 256;
 constexpr int KRY_GRID = 1024;   // partial sums per dot product
 constexpr int KRY_MAXV = 33;     // basis vectors per call (restart <= 32) + w.w
 
+// Streaming loops take KRY_UNROLL elements per thread per trip (grid-stride
+// apart), so each thread has that many independent loads of every vector in
+// flight.  Kernels are instantiated for basis sizes up to NV (4, 8, 16, 32) so
+// that register arrays stay as small as the call needs; large bases have
+// enough loads in flight with one element per trip.
+constexpr int KRY_UNROLL = 4;
+template <int NV>
+constexpr int kry_unroll() {
+  return NV <= 4 ? KRY_UNROLL : (NV <= 8 ? 2 : 1);
+}
+
 // Block-wide sums of the per-thread values vals[i] for the active slots
-// (i < nv, plus slot KRY_MAXV-1 if with_norm); written to
-// partial[i * gridDim.x + blockIdx.x].  Register arrays are only indexed with
-// compile-time constants.
-__device__ inline void block_reduce_store(const double (&vals)[KRY_MAXV], int nv, int with_norm,
+// (i < nv, plus the norm slot vals[NV] if with_norm); slot i goes to
+// partial[i * gridDim.x + blockIdx.x] and the norm to slot KRY_MAXV-1.
+// Register arrays are only indexed with compile-time constants.
+template <int NV>
+__device__ inline void block_reduce_store(const double (&vals)[NV + 1], int nv, int with_norm,
                                           double *red, double *__restrict__ partial) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < KRY_MAXV; ++i) {
-    bool active = (i < nv) || (i == KRY_MAXV - 1 && with_norm);
+  for (int i = 0; i <= NV; ++i) {
+    bool active = (i < nv) || (i == NV && with_norm);
     if (active) {
       double s = vals[i];
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (lane == 0) red[wave * KRY_MAXV + i] = s;
+      if (lane == 0) red[wave * (NV + 1) + i] = s;
     }
   }
   __syncthreads();
   int i = threadIdx.x;
-  if (i < KRY_MAXV && ((i < nv) || (i == KRY_MAXV - 1 && with_norm))) {
+  if (i <= NV && ((i < nv) || (i == NV && with_norm))) {
     double s = 0.0;
-    for (int w = 0; w < KRY_BLOCK / 64; ++w) s += red[w * KRY_MAXV + i];
-    partial[(int64_t)i * gridDim.x + blockIdx.x] = s;
+    for (int w = 0; w < KRY_BLOCK / 64; ++w) s += red[w * (NV + 1) + i];
+    const int slot = i == NV ? KRY_MAXV - 1 : i;
+    partial[(int64_t)slot * gridDim.x + blockIdx.x] = s;
   }
 }
 
 // partial[i * gridDim.x + block] = this block's share of V_i . w (i < nv) and,
 // if with_norm, slot KRY_MAXV-1 = w . w.  V_i = V + i * ldv.
+template <int NV>
 __global__ void __launch_bounds__(KRY_BLOCK)
 krylov_dots(const double *__restrict__ V, int64_t ldv, int nv, const double *__restrict__ w,
             int64_t N, int with_norm, double *__restrict__ partial) {
-  __shared__ double red[(KRY_BLOCK / 64) * KRY_MAXV];
-  double acc[KRY_MAXV];
+  __shared__ double red[(KRY_BLOCK / 64) * (NV + 1)];
+  double acc[NV + 1];
 #pragma unroll
-  for (int i = 0; i < KRY_MAXV; ++i) acc[i] = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double we = w[e];
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  constexpr int U = kry_unroll<NV>();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N;
+       e0 += U * stride) {
+    double we[U];
 #pragma unroll
-    for (int i = 0; i < KRY_MAXV - 1; ++i)
-      if (i < nv) acc[i] += V[i * ldv + e] * we;
-    acc[KRY_MAXV - 1] += we * we;
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * stride;
+      we[u] = e < N ? w[e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) {
+        const double *vi = V + i * ldv;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = e0 + u * stride;
+          acc[i] += (e < N ? vi[e] : 0.0) * we[u];
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[NV] += we[u] * we[u];
   }
-  block_reduce_store(acc, nv, with_norm, red, partial);
+  block_reduce_store<NV>(acc, nv, with_norm, red, partial);
 }
 
 // w += sign * sum_i coef[i] V_i (coef in device memory); then, if with_dots,
 // partial dots V_i . w_new and w_new . w_new as in krylov_dots (with_norm = 1).
+// The dot products re-read V_i[e] right after the update read it (cache hits).
+template <int NV>
 __global__ void __launch_bounds__(KRY_BLOCK)
 krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *__restrict__ coef,
               double sign, double *__restrict__ w, int64_t N, int with_dots,
               double *__restrict__ partial) {
-  __shared__ double red[(KRY_BLOCK / 64) * KRY_MAXV];
-  __shared__ double cs[KRY_MAXV];
-  if (threadIdx.x < KRY_MAXV) cs[threadIdx.x] = (threadIdx.x < nv) ? sign * coef[threadIdx.x] : 0.0;
+  __shared__ double red[(KRY_BLOCK / 64) * (NV + 1)];
+  __shared__ double cs[NV];
+  if (threadIdx.x < NV) cs[threadIdx.x] = ((int)threadIdx.x < nv) ? sign * coef[threadIdx.x] : 0.0;
   __syncthreads();
-  double acc[KRY_MAXV];
+  double acc[NV + 1];
 #pragma unroll
-  for (int i = 0; i < KRY_MAXV; ++i) acc[i] = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double v[KRY_MAXV - 1];
-    double we = w[e];
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  constexpr int U = kry_unroll<NV>();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N;
+       e0 += U * stride) {
+    double we[U];
 #pragma unroll
-    for (int i = 0; i < KRY_MAXV - 1; ++i) {
-      v[i] = (i < nv) ? V[i * ldv + e] : 0.0;
-      we += cs[i] * v[i];
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * stride;
+      we[u] = e < N ? w[e] : 0.0;
     }
-    w[e] = we;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) {
+        const double *vi = V + i * ldv;
+        const double c = cs[i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = e0 + u * stride;
+          we[u] += c * (e < N ? vi[e] : 0.0);
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * stride;
+      if (e < N) w[e] = we[u];
+    }
     if (with_dots) {
 #pragma unroll
-      for (int i = 0; i < KRY_MAXV - 1; ++i) acc[i] += v[i] * we;
-      acc[KRY_MAXV - 1] += we * we;
+      for (int i = 0; i < NV; ++i)
+        if (i < nv) {
+          const double *vi = V + i * ldv;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * stride;
+            acc[i] += (e < N ? vi[e] : 0.0) * we[u];
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[NV] += we[u] * we[u];
     }
   }
   if (!with_dots) return;
-  block_reduce_store(acc, nv, 1, red, partial);
+  block_reduce_store<NV>(acc, nv, 1, red, partial);
+}
+
+// r = f - Ax and this block's share of r . r in slot KRY_MAXV-1 of partial.
+__global__ void __launch_bounds__(KRY_BLOCK)
+residual_norm(const double *__restrict__ f, const double *__restrict__ Ax, double *__restrict__ r,
+              int64_t N, double *__restrict__ partial) {
+  __shared__ double red[(KRY_BLOCK / 64) * 2];
+  double acc[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N;
+       e0 += KRY_UNROLL * stride) {
+    double fv[KRY_UNROLL], av[KRY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < KRY_UNROLL; ++u) {
+      const int64_t e = e0 + u * stride;
+      fv[u] = e < N ? f[e] : 0.0;
+      av[u] = e < N ? Ax[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < KRY_UNROLL; ++u) {
+      const int64_t e = e0 + u * stride;
+      const double rv = fv[u] - av[u];
+      if (e < N) r[e] = rv;
+      acc[1] += rv * rv;
+    }
+  }
+  block_reduce_store<1>(acc, 0, 1, red, partial);
+}
+
+// Shares of x . x (slot 0) and y . y (slot KRY_MAXV-1) in one pass.
+__global__ void __launch_bounds__(KRY_BLOCK)
+two_norms(const double *__restrict__ x, const double *__restrict__ y, int64_t N,
+          double *__restrict__ partial) {
+  __shared__ double red[(KRY_BLOCK / 64) * 2];
+  double acc[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N;
+       e0 += KRY_UNROLL * stride) {
+    double xv[KRY_UNROLL], yv[KRY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < KRY_UNROLL; ++u) {
+      const int64_t e = e0 + u * stride;
+      xv[u] = e < N ? x[e] : 0.0;
+      yv[u] = e < N ? y[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < KRY_UNROLL; ++u) {
+      acc[0] += xv[u] * xv[u];
+      acc[1] += yv[u] * yv[u];
+    }
+  }
+  block_reduce_store<1>(acc, 1, 1, red, partial);
 }
 
 // out[i] = sum_b partial[i * nparts + b], fixed order; one block per i.

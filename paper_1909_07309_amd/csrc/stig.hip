@@ -947,43 +947,82 @@ struct Krylov {
   // out[0..KRY_MAXV) of the small buffer region `slot`
   double *slot(int k) { return small() + k * KRY_MAXV; }
 
-  stig_status dots(const double *V, int nv, const double *w, int with_norm, int out_slot) {
-    ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 1) * p->N * 8);
-    hipLaunchKernelGGL(krylov_dots, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N, nv, w,
-                       p->N, with_norm, partial());
-    HIP_TRY(hipGetLastError());
+  // reduce the per-block partial sums into slot region `out_slot`
+  stig_status reduce(int out_slot) {
     hipLaunchKernelGGL(reduce_partials, dim3(KRY_MAXV), dim3(KRY_BLOCK), 0, p->stream, partial(),
                        KRY_GRID, slot(out_slot));
     HIP_TRY(hipGetLastError());
     return STIG_OK;
   }
+  template <int NV>
+  void launch_dots(const double *V, int nv, const double *w, int with_norm) {
+    hipLaunchKernelGGL(krylov_dots<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N, nv,
+                       w, p->N, with_norm, partial());
+  }
+  template <int NV>
+  void launch_update(const double *V, int nv, const double *coef, double sign, double *w,
+                     int with_dots) {
+    hipLaunchKernelGGL(krylov_update<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N,
+                       nv, coef, sign, w, p->N, with_dots, partial());
+  }
+  stig_status dots(const double *V, int nv, const double *w, int with_norm, int out_slot) {
+    if (nv > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
+    ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 1) * p->N * 8);
+    if (nv <= 4) launch_dots<4>(V, nv, w, with_norm);
+    else if (nv <= 8) launch_dots<8>(V, nv, w, with_norm);
+    else if (nv <= 16) launch_dots<16>(V, nv, w, with_norm);
+    else launch_dots<32>(V, nv, w, with_norm);
+    HIP_TRY(hipGetLastError());
+    return reduce(out_slot);
+  }
   stig_status update(const double *V, int nv, const double *coef, double sign, double *w,
                      int with_dots, int out_slot) {
+    if (nv > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
     ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 2) * p->N * 8);
-    hipLaunchKernelGGL(krylov_update, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N, nv,
-                       coef, sign, w, p->N, with_dots, partial());
+    if (nv <= 4) launch_update<4>(V, nv, coef, sign, w, with_dots);
+    else if (nv <= 8) launch_update<8>(V, nv, coef, sign, w, with_dots);
+    else if (nv <= 16) launch_update<16>(V, nv, coef, sign, w, with_dots);
+    else launch_update<32>(V, nv, coef, sign, w, with_dots);
     HIP_TRY(hipGetLastError());
-    if (with_dots) {
-      hipLaunchKernelGGL(reduce_partials, dim3(KRY_MAXV), dim3(KRY_BLOCK), 0, p->stream,
-                         partial(), KRY_GRID, slot(out_slot));
-      HIP_TRY(hipGetLastError());
-    }
+    return with_dots ? reduce(out_slot) : STIG_OK;
+  }
+  // host value of slot `k`'s entry i (synchronises)
+  stig_status fetch(int k, int i, double *out) {
+    HIP_TRY(hipMemcpyAsync(out, slot(k) + i, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return STIG_OK;
+  }
+  // r = f - Ax; host value of ||r||_2 (synchronises)
+  stig_status residual(const double *f, const double *Ax, double *r, double *norm) {
+    ProfScope ps(p, STIG_K_KRYLOV, 3.0 * p->N * 8);
+    hipLaunchKernelGGL(residual_norm, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, f, Ax, r,
+                       p->N, partial());
+    HIP_TRY(hipGetLastError());
+    STIG_TRY(reduce(3));
+    double v;
+    STIG_TRY(fetch(3, KRY_MAXV - 1, &v));
+    *norm = std::sqrt(v);
+    return STIG_OK;
+  }
+  // host values of ||x||_2 and ||y||_2 from one pass (synchronises)
+  stig_status norms(const double *x, const double *y, double *nx, double *ny) {
+    ProfScope ps(p, STIG_K_KRYLOV, 2.0 * p->N * 8);
+    hipLaunchKernelGGL(two_norms, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, x, y, p->N,
+                       partial());
+    HIP_TRY(hipGetLastError());
+    STIG_TRY(reduce(3));
+    double v[KRY_MAXV];
+    HIP_TRY(hipMemcpyAsync(v, slot(3), KRY_MAXV * sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    *nx = std::sqrt(v[0]);
+    *ny = std::sqrt(v[KRY_MAXV - 1]);
     return STIG_OK;
   }
   stig_status axpby(const double *x, const double *y, double *out, double a, double b) {
     hipLaunchKernelGGL(stig::axpby, dim3(grid_for(p->N, 256, 8192)), dim3(256), 0, p->stream, x,
                        y, out, a, b, p->N);
     HIP_TRY(hipGetLastError());
-    return STIG_OK;
-  }
-  // host value of ||x||_2 (synchronises)
-  stig_status norm(const double *x, double *out) {
-    STIG_TRY(dots(x, 0, x, 1, 3));
-    double v;
-    HIP_TRY(hipMemcpyAsync(&v, slot(3) + KRY_MAXV - 1, sizeof(double), hipMemcpyDeviceToHost,
-                           p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    *out = std::sqrt(v);
     return STIG_OK;
   }
 };
@@ -1010,13 +1049,17 @@ stig_status check_flag(stig_plan *p) {
   return STIG_OK;
 }
 
-// One right-hand side: restarted (F)GMRES with right preconditioning.
+// One right-hand side: restarted (F)GMRES with right preconditioning.  Both
+// variants keep the preconditioned basis Z (m vectors): for a fixed linear
+// preconditioner u += Z y equals u += P^{-1} (V y), and it saves one
+// preconditioner apply per cycle; flexible GMRES needs Z anyway.
 stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rtol, int maxit,
                       int flexible, int transpose, stig_prec prec, stig_info *info) {
+  (void)flexible;
   const int64_t N = p->N;
   Krylov K{p};
   STIG_TRY(p->V.ensure((size_t)(m + 1) * N * sizeof(double)));
-  if (flexible) STIG_TRY(p->Z.ensure((size_t)m * N * sizeof(double)));
+  STIG_TRY(p->Z.ensure((size_t)m * N * sizeof(double)));
   STIG_TRY(p->w.ensure(N * sizeof(double)));
   STIG_TRY(p->tmp.ensure(N * sizeof(double)));
   double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *w = p->w.as<double>(),
@@ -1025,9 +1068,10 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   std::vector<double> &hs = p->host_small;
   hs.assign(4 * KRY_MAXV, 0.0);
 
-  double fnorm;
-  STIG_TRY(K.norm(f, &fnorm));
+  double fnorm, unorm;
+  STIG_TRY(K.norms(f, u, &fnorm, &unorm));
   if (!std::isfinite(fnorm)) return fail(STIG_ENONFINITE, "non-finite right-hand side norm");
+  if (!std::isfinite(unorm)) return fail(STIG_ENONFINITE, "non-finite initial guess");
   info->iters = 0;
   info->restarts = 0;
   info->relres_true = 0.0;
@@ -1037,24 +1081,30 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     HIP_TRY(hipStreamSynchronize(p->stream));
     return STIG_OK;
   }
-  // r0 = f - A u
-  STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
-  STIG_TRY(K.axpby(f, tmp, V, 1.0, -1.0));
+  // r0 = f - A u (= f for a zero initial guess, without a product)
   double beta;
-  STIG_TRY(K.norm(V, &beta));
+  const double *r = V;
+  if (unorm == 0.0) {
+    r = f;
+    beta = fnorm;
+  } else {
+    STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
+    STIG_TRY(K.residual(f, tmp, V, &beta));
+  }
   if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite initial residual");
   info->relres_true = beta / fnorm;
   info->relres_est = info->relres_true;
   int cycle = 0;
   while (beta / fnorm > rtol && info->iters < maxit) {
     if (cycle++ > 0) info->restarts++;
-    STIG_TRY(K.axpby(V, nullptr, V, 1.0 / beta, 0.0));
+    STIG_TRY(K.axpby(r, nullptr, V, 1.0 / beta, 0.0));  // v_0 = r / beta
+    r = V;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
       double *vj = V + (int64_t)j * N;
-      double *zj = flexible ? Z + (int64_t)j * N : tmp;
+      double *zj = Z + (int64_t)j * N;
       STIG_TRY(apply_dispatch(p, vj, zj, 1, transpose, prec));
       STIG_TRY(run_matvec(p, zj, w, 1, transpose));
       // classical Gram-Schmidt with one re-orthogonalisation
@@ -1105,18 +1155,10 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     std::copy(y.begin(), y.begin() + k, hs.begin() + 3 * KRY_MAXV);
     HIP_TRY(hipMemcpyAsync(K.slot(3), hs.data() + 3 * KRY_MAXV, k * sizeof(double),
                            hipMemcpyHostToDevice, p->stream));
-    if (flexible) {
-      STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));   // u += Z y
-    } else {
-      HIP_TRY(hipMemsetAsync(tmp, 0, N * sizeof(double), p->stream));
-      STIG_TRY(K.update(V, k, K.slot(3), 1.0, tmp, 0, 0)); // tmp = V y
-      STIG_TRY(apply_dispatch(p, tmp, w, 1, transpose, prec));
-      STIG_TRY(K.axpby(u, w, u, 1.0, 1.0));                 // u += P^{-1} V y
-    }
+    STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));  // u += Z y
     // true residual
     STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
-    STIG_TRY(K.axpby(f, tmp, V, 1.0, -1.0));
-    STIG_TRY(K.norm(V, &beta));
+    STIG_TRY(K.residual(f, tmp, V, &beta));
     if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite residual");
     info->relres_true = beta / fnorm;
   }

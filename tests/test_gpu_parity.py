@@ -164,6 +164,27 @@ def test_mixed_precision_fgmres_reaches_fp64_accuracy(prec):
     assert e < (1e-5 if prec == "fp32" else 0.5)
 
 
+def test_gmres_nonzero_guess_and_restarts():
+    """A nonzero initial guess (residual formed by a product) and short restart
+    cycles (several restarts, true residual recomputed per cycle), BF16 apply."""
+    from paper_1909_07309_amd.problem import source
+    w, fac, plan, pr = _setup("cube_p3_n64", 12)
+    f = source(w, plan)
+    u0 = _dev(wl.random_tensor(w.shape, 9))
+    u, info = plan.gmres_solve(f, u0.clone(), restart=2, rtol=1e-8, maxit=100, flexible=True,
+                               prec="bf16")
+    f_ref = pr.source()
+    r = f_ref - fd.kron_matvec(u.cpu().numpy(), pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    assert np.linalg.norm(r) / np.linalg.norm(f_ref) <= 1e-8
+    assert info["restarts"] >= 1 and info["converged"]
+    assert abs(info["relres_true"] - np.linalg.norm(r) / np.linalg.norm(f_ref)) <= 1e-9
+    # a zero initial guess takes the same path without the first product
+    u2, info2 = plan.gmres_solve(f, torch.zeros_like(f), restart=30, rtol=1e-8, maxit=100,
+                                 flexible=True, prec="bf16")
+    r2 = f_ref - fd.kron_matvec(u2.cpu().numpy(), pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    assert np.linalg.norm(r2) / np.linalg.norm(f_ref) <= 1e-8
+
+
 def test_full_size_cube_apply_and_solve():
     """The 3D cube at p=3, 64 elements (18,125,250 unknowns), in the bench's launch shape."""
     from paper_1909_07309_amd.problem import source
