@@ -187,6 +187,7 @@ __global__ void csr_spmv(const int64_t *__restrict__ rowptr, const int32_t *__re
 // axis passes.  Bands (device, [n][2P+1], entry m of row i at column
 // i + m - P, zero outside): M0, K0 (x), M1, K1 (y), M2, K2 (z).
 constexpr int STENCIL_SPF = 1;  // input planes in flight per thread
+constexpr int STENCIL_ZC = 24;  // most output planes per block (2P halo planes are recomputed)
 
 template <int P>
 __device__ __forceinline__ int stencil_ldx(int nx) {
@@ -270,19 +271,17 @@ spatial_stencil(const double *__restrict__ x, double *__restrict__ a, double *__
   __syncthreads();  // x pads are zero before the first row store
   push(0, zfirst + STENCIL_SPF);
   __syncthreads();
-  for (int zin = zfirst; zin < zlast; ++zin) {
-    const int buf = (zin - zfirst) & 1;
+  // x products (M_1, K_1) of window rows yy and yy + R of the plane in buffer buf
+  auto xpass_store = [&](int buf, double *u, double *v) {
     const double *xi = xin + buf * rows * ldx + P;
-    double *u = xu + buf * rows * nx, *v = xv + buf * rows * nx;
-    // x products of window rows yy and yy + R (column xx) of plane zin
     if (act) {
       double su = 0.0, sv = 0.0, tu = 0.0, tv = 0.0;
       const double *r0 = xi + yy * ldx + xx - P, *r1 = r0 + R * ldx;
 #pragma unroll
       for (int m = 0; m < B; ++m) {
         const double c0 = r0[m];
-        su += bxm[m] * c0;
-        sv += bxk[m] * c0;
+        su = fma(bxm[m], c0, su);
+        sv = fma(bxk[m], c0, sv);
       }
       u[yy * nx + xx] = su;
       v[yy * nx + xx] = sv;
@@ -290,44 +289,57 @@ spatial_stencil(const double *__restrict__ x, double *__restrict__ a, double *__
 #pragma unroll
         for (int m = 0; m < B; ++m) {
           const double c1 = r1[m];
-          tu += bxm[m] * c1;
-          tv += bxk[m] * c1;
+          tu = fma(bxm[m], c1, tu);
+          tv = fma(bxk[m], c1, tv);
         }
         u[(yy + R) * nx + xx] = tu;
         v[(yy + R) * nx + xx] = tv;
       }
     }
-    // plane zin + 1 into the other buffer (its previous plane's x products are
-    // done: they preceded the last barrier); one barrier per plane
-    push(buf ^ 1, zin + 1 + STENCIL_SPF);
-    __syncthreads();
-    // y products of this thread's row -> the z window
-    double An = 0.0, Bn = 0.0;
+  };
+  // Plane j = zin - zfirst goes to window slot j % B: the plane loop is
+  // unrolled B times, so every slot index is a compile-time constant and the
+  // window needs no register moves.  The output of plane zin - P reads the
+  // planes j - 2P .. j, i.e. slots (ph + 1 + m) % B for m = 0 .. 2P.
+  for (int base = 0; zfirst + base < zlast; base += B) {
 #pragma unroll
-    for (int m = 0; m < B; ++m) {
-      const double uu = u[(yy + m) * nx + xx], vv = v[(yy + m) * nx + xx];
-      An += bym[m] * uu;
-      Bn += bym[m] * vv + byk[m] * uu;
-    }
+    for (int ph = 0; ph < B; ++ph) {
+      const int zin = zfirst + base + ph;
+      if (zin < zlast) {  // block-uniform: every thread takes the same barriers
+        const int buf = (base + ph) & 1;
+        double *u = xu + buf * rows * nx, *v = xv + buf * rows * nx;
+        xpass_store(buf, u, v);
+        // plane zin + 1 into the other buffer (its previous plane's x products
+        // are done: they preceded the last barrier); one barrier per plane
+        push(buf ^ 1, zin + 1 + STENCIL_SPF);
+        __syncthreads();
+        // y products of this thread's row -> window slot ph
+        double An = 0.0, Bn = 0.0;
 #pragma unroll
-    for (int m = 0; m < B - 1; ++m) {
-      Aw[m] = Aw[m + 1];
-      Bw[m] = Bw[m + 1];
-    }
-    Aw[B - 1] = An;
-    Bw[B - 1] = Bn;
-    const int z = zin - P;
-    if (z >= z0 && out_ok) {
-      double sa = 0.0, sb = 0.0;
+        for (int m = 0; m < B; ++m) {
+          const double uu = u[(yy + m) * nx + xx], vv = v[(yy + m) * nx + xx];
+          An = fma(bym[m], uu, An);
+          Bn = fma(bym[m], vv, Bn);
+          Bn = fma(byk[m], uu, Bn);
+        }
+        Aw[ph] = An;
+        Bw[ph] = Bn;
+        const int z = zin - P;
+        if (z >= z0 && out_ok) {
+          double sa = 0.0, sb = 0.0;
 #pragma unroll
-      for (int m = 0; m < B; ++m) {
-        const double cm = mz[z * B + m], ck = kz[z * B + m];
-        sa += cm * Aw[m];
-        sb += ck * Aw[m] + cm * Bw[m];
+          for (int m = 0; m < B; ++m) {
+            const int sl = (ph + 1 + m) % B;
+            const double cm = mz[z * B + m], ck = kz[z * B + m];
+            sa = fma(cm, Aw[sl], sa);
+            sb = fma(ck, Aw[sl], sb);
+            sb = fma(cm, Bw[sl], sb);
+          }
+          const int64_t o = (int64_t)z * plane + (int64_t)y * nx + xx;
+          as[o] = sa;
+          bs[o] = sb;
+        }
       }
-      const int64_t o = (int64_t)z * plane + (int64_t)y * nx + xx;
-      as[o] = sa;
-      bs[o] = sb;
     }
   }
 }

@@ -862,8 +862,8 @@ stig_status launch_stencil_p(stig_plan *p, const double *x, double *a, double *b
   const int R = std::max(2 * P, (ny + (ny + rmax - 1) / rmax - 1) / ((ny + rmax - 1) / rmax));
   if (R * nx > STENCIL_THREADS) return fail(STIG_EINVAL, "plane too wide for the stencil pass");
   const int threads = (R * nx + 63) / 64 * 64;
-  // z chunks of at most 16 planes per block (the halo of 2P planes is recomputed)
-  const int nch = (nz + 15) / 16, ZC = (nz + nch - 1) / nch;
+  // z chunks of at most STENCIL_ZC planes per block, of balanced lengths
+  const int nch = (nz + STENCIL_ZC - 1) / STENCIL_ZC, ZC = (nz + nch - 1) / nch;
   const size_t lds = (size_t)2 * (R + 2 * P) * (2 * nx + nx + 2 * P) * sizeof(double);
   if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "plane too wide for the stencil pass");
   auto kern = spatial_stencil<P>;
