@@ -55,8 +55,9 @@ def cpu_baseline(w, f_host, target_s=12.0):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fd_apply_cube_p3_n64.json")
-KERNEL_SOURCES = ["paper_1909_07309_amd/csrc/kernels_fd.h", "paper_1909_07309_amd/csrc/kernels_plane.h",
-                  "paper_1909_07309_amd/csrc/stig.hip"]
+KERNEL_SOURCES = ["paper_1909_07309_amd/csrc/" + f for f in (
+    "kernels_fd.h", "kernels_plane.h", "kernels_sym.h", "kernels_plane_sym.h", "kernels_arrow.h",
+    "kernels_matvec.h", "kernels_krylov.h", "stig.hip")]
 
 
 def kernel_fingerprint():
@@ -223,6 +224,18 @@ def main():
         mixed[prec] = {"ms_per_apply": dtp / args.steps * 1e3, "DoF_per_s": w.N * args.steps / dtp}
         log(f"[bench] {prec} apply {mixed[prec]['ms_per_apply']:.3f} ms")
 
+    # ---- FP64 matvec y = A x (the per-iteration product of the solves)
+    for _ in range(args.warmup):
+        plan.matvec_A(f, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.matvec_A(f, s)
+    torch.cuda.synchronize()
+    dtm = (time.perf_counter() - t0) / args.steps
+    matvec = {"ms": dtm * 1e3, "DoF_per_s": w.N / dtm}
+    log(f"[bench] fp64 matvec {dtm * 1e3:.3f} ms")
+
     # ---- CPU oracle baseline (also the reference solution: A-hat = A on the cube)
     cpu = None
     u_ref = None
@@ -266,6 +279,7 @@ def main():
         "apply_fp64_tflops": apply_tflops,
         "kernels_fp64_apply": kernels,
         "mixed_apply": mixed,
+        "matvec_fp64": matvec,
         "solve_to_1e-8": solves,
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items()
                                                   if k != "s_per_apply"},

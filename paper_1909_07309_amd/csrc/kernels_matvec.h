@@ -213,11 +213,15 @@ spatial_stencil(const double *__restrict__ x, double *__restrict__ a, double *__
   const int tid = threadIdx.x;
   for (int e = tid; e < 2 * rows * ldx; e += blockDim.x) xin[e] = 0.0;  // zero x pads
   const int ntiles = (ny + R - 1) / R, nchunks = (nz + ZC - 1) / ZC;
-  int64_t blk = blockIdx.x;
+  // Blocks go to the 8 XCDs round-robin (block b to XCD b % 8); each XCD takes a
+  // contiguous run of tiles instead, y tiles fastest, so that tiles next to
+  // each other run on one XCD at the same time and their halo rows hit its L2.
+  const int64_t nb = gridDim.x, q = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8;
+  int64_t blk = xcd * q + min(xcd, rem) + blockIdx.x / 8;
+  const int y0 = (int)(blk % ntiles) * R;
+  blk /= ntiles;
   const int chunk = (int)(blk % nchunks);
-  blk /= nchunks;
-  const int64_t slice = blk / ntiles;
-  const int y0 = (int)(blk - slice * ntiles) * R;
+  const int64_t slice = blk / nchunks;
   if (slice >= slices) return;  // whole block: no barrier is skipped by part of it
   const int z0 = chunk * ZC, z1 = min(nz, z0 + ZC);  // outputs z0 .. z1-1
   const int64_t plane = (int64_t)nx * ny;
