@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-annulus", action="store_true",
+                    help="skip the annulus solves (variable coefficients, CSR matvec)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -267,6 +269,30 @@ def main():
             solves[prec] = rec
             log(f"[bench] solve {prec}: {rec}")
 
+    # ---- annulus (space-time CSR matvec, A-hat^G != A): FGMRES(30) to 1e-8 with
+    # the FP64 and with the FP32 geometry-aware FD preconditioner
+    annulus = {}
+    if not args.no_solve and not args.no_annulus:
+        from paper_1909_07309_amd.annulus import AnnulusSetup
+        wa = wl.WORKLOADS["annulus_p4_n128"]
+        asu = AnnulusSetup(wa)
+        pa = asu.make_plan()
+        fa = asu.source()
+        for prec in ("fp64", "fp32"):
+            pa.gmres_solve(fa, torch.zeros_like(fa), restart=30, rtol=1e-8, maxit=300,
+                           flexible=True, prec=prec)  # warm (allocations)
+            ua = torch.zeros_like(fa)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ua, info = pa.gmres_solve(fa, ua, restart=30, rtol=1e-8, maxit=300, flexible=True,
+                                      prec=prec)
+            torch.cuda.synchronize()
+            annulus[prec] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
+                             "relres_true": info["relres_true"], "method": "FGMRES(30)"}
+            log(f"[bench] annulus solve {prec}: {annulus[prec]}")
+        annulus["N"] = wa.N
+        del pa, asu
+
     line = {
         "metric": "P^-1 applies/s (DoF/s) + solve time to 1e-8 resid, FP64 vs mixed",
         "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
@@ -281,6 +307,7 @@ def main():
         "mixed_apply": mixed,
         "matvec_fp64": matvec,
         "solve_to_1e-8": solves,
+        "annulus_solve_to_1e-8": annulus,
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items()
                                                   if k != "s_per_apply"},
     }
