@@ -129,6 +129,23 @@ def test_matvec_and_mass_match_oracle(name, n_el):
         assert _relmax(m[b], refm) <= 1e-13
 
 
+@pytest.mark.parametrize("name,p,n_el", [("cube_p3_n64", 1, 9), ("cube_p3_n64", 2, 7),
+                                          ("cube_p3_n64", 4, 6), ("cube_p3_n64", 5, 5),
+                                          ("square_p2_n8", 1, 12), ("square_p2_n8", 5, 11)])
+def test_stencil_matvec_every_degree(name, p, n_el):
+    """The fused spatial stencil for every spline degree it is built for (window
+    of 2p + 1 planes, R >= 2p rows per block), with T, gamma and nu != 1."""
+    w, fac, plan, pr = _setup(name, n_el, p=p, T=0.5, gamma=0.7, nu=1.3)
+    x = wl.random_tensor((2,) + w.shape, 13)
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
+    for b in range(2):
+        ref = fd.kron_matvec(x[b], pr.Wt, pr.Mt, pr.K1d, pr.M1d, w.gamma, w.nu)
+        reft = fd.kron_matvec(x[b], pr.Wt, pr.Mt, pr.K1d, pr.M1d, w.gamma, w.nu, transpose=True)
+        assert _relmax(y[b], ref) <= 1e-13
+        assert _relmax(yt[b], reft) <= 1e-13
+
+
 def test_square_solve_matches_dense_direct():
     """The 2D unit-square workload (p=2, 8 elements, 10 random sines), GMRES(30) to 1e-10."""
     from paper_1909_07309_amd.problem import source
