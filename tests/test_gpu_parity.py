@@ -105,6 +105,36 @@ def test_time_kernels_match_oracle(name, n_el, kernel):
         assert e <= 2 * ed + 1e-3, (kernel, transpose, e, ed)
 
 
+@pytest.mark.parametrize("n_el", [31, 32, 64])
+def test_parity_split_products_match_oracle(n_el):
+    """n_s = 32, 33, 65: half-size products around the butterfly (split basis),
+    with and without the fused plane pass, against the dense products and the
+    oracle, every precision, plain and transposed."""
+    w, fac, plan, pr = _setup("cube_p3_n64", n_el)
+    nrhs = 2 if n_el < 64 else 1
+    r = wl.random_tensor((nrhs,) + w.shape, 17)
+    rd = _dev(r)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, w.gamma, w.nu)
+    for transpose in (False, True):
+        ref = np.stack([P.apply(r[b], transpose=transpose) for b in range(nrhs)])
+        for prec in ("fp64", "fp32", "bf16"):
+            errs = {}
+            for split in (True, False):
+                for fusion in (True, False):
+                    plan.set_option("parity_split", split)
+                    plan.set_option("plane_fusion", fusion)
+                    s = plan.apply_Pinv(rd, transpose=transpose, prec=prec).cpu().numpy()
+                    errs[split, fusion] = np.linalg.norm(s - ref) / np.linalg.norm(ref)
+                    if prec == "fp64":
+                        assert _relmax(s, ref) <= 1e-12, (split, fusion, transpose)
+            plan.set_option("parity_split", True)
+            plan.set_option("plane_fusion", True)
+            if prec != "fp64":
+                dense = errs[False, False]
+                for key, e in errs.items():
+                    assert e <= 1.5 * dense + (1e-7 if prec == "fp32" else 1e-4), (prec, key, errs)
+
+
 def test_apply_pinv_matches_dense_solve_tiny():
     w, fac, plan, pr = _setup("cube_p3_n64", 3)
     A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d)
