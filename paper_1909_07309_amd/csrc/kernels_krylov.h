@@ -88,13 +88,14 @@ krylov_dots(const double *__restrict__ V, int64_t ldv, int nv, const double *__r
   block_reduce_store<NV>(acc, nv, with_norm, red, partial);
 }
 
-// w += sign * sum_i coef[i] V_i (coef in device memory); then, if with_dots,
-// partial dots V_i . w_new and w_new . w_new as in krylov_dots (with_norm = 1).
-// The dot products re-read V_i[e] right after the update read it (cache hits).
+// w_new = w + sign * sum_i coef[i] V_i (coef in device memory), written as
+// dst = scale * w_new (dst may be w); then, if with_dots, partial dots
+// V_i . w_new and w_new . w_new as in krylov_dots (with_norm = 1).  The dot
+// products re-read V_i[e] right after the update read it (cache hits).
 template <int NV>
 __global__ void __launch_bounds__(KRY_BLOCK)
 krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *__restrict__ coef,
-              double sign, double *__restrict__ w, int64_t N, int with_dots,
+              double sign, const double *w, double *dst, double scale, int64_t N, int with_dots,
               double *__restrict__ partial) {
   __shared__ double red[(KRY_BLOCK / 64) * (NV + 1)];
   __shared__ double cs[NV];
@@ -127,7 +128,7 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + u * stride;
-      if (e < N) w[e] = we[u];
+      if (e < N) dst[e] = scale * we[u];
     }
     if (with_dots) {
 #pragma unroll

@@ -974,10 +974,10 @@ struct Krylov {
                        w, p->N, with_norm, partial());
   }
   template <int NV>
-  void launch_update(const double *V, int nv, const double *coef, double sign, double *w,
-                     int with_dots) {
+  void launch_update(const double *V, int nv, const double *coef, double sign, const double *w,
+                     double *dst, double scale, int with_dots) {
     hipLaunchKernelGGL(krylov_update<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N,
-                       nv, coef, sign, w, p->N, with_dots, partial());
+                       nv, coef, sign, w, dst, scale, p->N, with_dots, partial());
   }
   stig_status dots(const double *V, int nv, const double *w, int with_norm, int out_slot) {
     if (nv > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
@@ -989,14 +989,17 @@ struct Krylov {
     HIP_TRY(hipGetLastError());
     return reduce(out_slot);
   }
+  // dst (default w) = scale * (w + sign * V coef); with_dots: V^T w_new and
+  // ||w_new||^2 into slot region out_slot
   stig_status update(const double *V, int nv, const double *coef, double sign, double *w,
-                     int with_dots, int out_slot) {
+                     int with_dots, int out_slot, double *dst = nullptr, double scale = 1.0) {
     if (nv > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
+    if (!dst) dst = w;
     ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 2) * p->N * 8);
-    if (nv <= 4) launch_update<4>(V, nv, coef, sign, w, with_dots);
-    else if (nv <= 8) launch_update<8>(V, nv, coef, sign, w, with_dots);
-    else if (nv <= 16) launch_update<16>(V, nv, coef, sign, w, with_dots);
-    else launch_update<32>(V, nv, coef, sign, w, with_dots);
+    if (nv <= 4) launch_update<4>(V, nv, coef, sign, w, dst, scale, with_dots);
+    else if (nv <= 8) launch_update<8>(V, nv, coef, sign, w, dst, scale, with_dots);
+    else if (nv <= 16) launch_update<16>(V, nv, coef, sign, w, dst, scale, with_dots);
+    else launch_update<32>(V, nv, coef, sign, w, dst, scale, with_dots);
     HIP_TRY(hipGetLastError());
     return with_dots ? reduce(out_slot) : STIG_OK;
   }
@@ -1121,16 +1124,32 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
       double *zj = Z + (int64_t)j * N;
       STIG_TRY(apply_dispatch(p, vj, zj, 1, transpose, prec));
       STIG_TRY(run_matvec(p, zj, w, 1, transpose));
-      // classical Gram-Schmidt with one re-orthogonalisation
+      // classical Gram-Schmidt with one re-orthogonalisation.  The second
+      // correction w -= V h2 is deferred: with V orthonormal,
+      // ||w - V h2||^2 = ||w||^2 - ||h2||^2, and the corrected vector is only
+      // needed as the next basis vector, so the correction is fused with the
+      // scaling into v_{j+1} (and skipped when the cycle ends here).
       STIG_TRY(K.dots(V, j + 1, w, 0, 0));                  // h1 = V^T w
-      STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, w, 1, 1));  // w -= V h1; h2 = V^T w
-      STIG_TRY(K.update(V, j + 1, K.slot(1), -1.0, w, 1, 2));  // w -= V h2; ||w||^2
-      HIP_TRY(hipMemcpyAsync(hs.data(), K.slot(0), 3 * KRY_MAXV * sizeof(double),
+      STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, w, 1, 1));  // w -= V h1; h2 = V^T w; ||w||^2
+      HIP_TRY(hipMemcpyAsync(hs.data(), K.slot(0), 2 * KRY_MAXV * sizeof(double),
                              hipMemcpyDeviceToHost, p->stream));
       HIP_TRY(hipStreamSynchronize(p->stream));
       STIG_TRY(check_flag(p));
       info->iters++;
-      double hnext = std::sqrt(hs[2 * KRY_MAXV + KRY_MAXV - 1]);
+      const double wsq = hs[KRY_MAXV + KRY_MAXV - 1];
+      double h2sq = 0.0;
+      for (int i = 0; i <= j; ++i) h2sq += hs[KRY_MAXV + i] * hs[KRY_MAXV + i];
+      bool corrected = false;  // w already holds w - V h2
+      double hnext;
+      if (wsq - h2sq >= 0.25 * wsq) {
+        hnext = std::sqrt(wsq - h2sq);
+      } else {
+        // strong cancellation: apply the correction and take the norm explicitly
+        STIG_TRY(K.update(V, j + 1, K.slot(1), -1.0, w, 1, 2));  // w -= V h2; ||w||^2
+        STIG_TRY(K.fetch(2, KRY_MAXV - 1, &hnext));
+        hnext = std::sqrt(hnext);
+        corrected = true;
+      }
       double colnorm = 0.0;
       for (int i = 0; i <= j; ++i) {
         double h = hs[i] + hs[KRY_MAXV + i];
@@ -1158,7 +1177,11 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
       info->relres_est = std::fabs(g[j + 1]) / fnorm;
       bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
       if (info->relres_est <= rtol || breakdown || info->iters >= maxit) break;
-      if (j + 1 < m) STIG_TRY(K.axpby(w, nullptr, V + (int64_t)(j + 1) * N, 1.0 / hnext, 0.0));
+      if (j + 1 < m) {
+        double *vn = V + (int64_t)(j + 1) * N;
+        if (corrected) STIG_TRY(K.axpby(w, nullptr, vn, 1.0 / hnext, 0.0));
+        else STIG_TRY(K.update(V, j + 1, K.slot(1), -1.0, w, 0, 0, vn, 1.0 / hnext));
+      }
     }
     // y = R^{-1} g
     for (int i = k - 1; i >= 0; --i) {
