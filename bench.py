@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-annulus", action="store_true",
                     help="skip the annulus solves (variable coefficients, CSR matvec)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the batched forward + adjoint solve (32 right-hand sides)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -127,8 +129,11 @@ def main():
 
     w = wl.WORKLOADS["cube_p3_n64"]
     log(f"[bench] workload {w.name}: N = {w.N}")
+    t0 = time.perf_counter()
     fac = CubeFactors(w)
     plan = fac.make_plan()
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3   # host assembly, 1D eigenproblems, uploads
     f = source(w, plan)
     torch.cuda.synchronize()
     s = torch.empty_like(f)
@@ -238,13 +243,21 @@ def main():
     matvec = {"ms": dtm * 1e3, "DoF_per_s": w.N / dtm}
     log(f"[bench] fp64 matvec {dtm * 1e3:.3f} ms")
 
-    # ---- CPU oracle baseline (also the reference solution: A-hat = A on the cube)
+    # ---- CPU oracle baseline (also the reference solution: A-hat = A on the cube),
+    # on all host threads, then one apply on one thread (beside the paper's serial timings)
     cpu = None
+    cpu1 = None
     u_ref = None
     if not args.no_cpu_baseline:
         f_host = f.cpu().numpy()
         u_ref, cpu = cpu_baseline(w, f_host)
         log(f"[bench] cpu oracle {cpu['s_per_apply']:.2f} s/apply ({cpu['cores']} threads)")
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            _, cpu1 = cpu_baseline(w, f_host, target_s=0.0)
+        cpu1["cores"] = 1
+        cpu1["sample"] = f"one full FP64 apply of A-hat^-1 on the {w.N}-unknown tensor, one thread"
+        log(f"[bench] cpu oracle, one thread: {cpu1['s_per_apply']:.2f} s/apply")
 
     # ---- solves to 1e-8
     solves = {}
@@ -293,6 +306,41 @@ def main():
         annulus["N"] = wa.N
         del pa, asu
 
+    # ---- batched forward + adjoint solve (p=3, 48 elements, 32 right-hand sides):
+    # u = A^{-1}(f - A_I0 c0), loss 0.5 ||u - u*||^2, gradients w.r.t. f and c0
+    adjoint = {}
+    if not args.no_solve and not args.no_adjoint:
+        from paper_1909_07309_amd.autograd import solve as stig_solve
+        from paper_1909_07309_amd.problem import smoothed_source
+
+        wb = wl.WORKLOADS["cube_p3_n48_b32"]
+        facb = CubeFactors(wb)
+        planb = facb.make_plan()
+        fb = smoothed_source(planb, torch.from_numpy(wl.source_coefficients(wb)).cuda()).detach()
+        c0 = torch.zeros((wb.nrhs,) + (wb.n_s,) * wb.d, dtype=torch.float64, device="cuda")
+        tgt = torch.from_numpy(wl.adjoint_target(wb)).cuda()
+        opts = dict(rtol=wb.rtol, restart=wb.restart, maxit=wb.maxit)
+        cols = (facb.W_col0, facb.M_col0)
+        times = []
+        for rep_ in range(2):   # the first pass allocates the Krylov buffers
+            ft = fb.clone().requires_grad_(True)
+            ct = c0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u = stig_solve(planb, ft, ct, cols, **opts)
+            loss = 0.5 * ((u - tgt) ** 2).sum()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3))
+        adjoint = {"forward_ms": times[-1][0], "backward_ms": times[-1][1], "nrhs": wb.nrhs,
+                   "N_per_rhs": wb.N, "rtol": wb.rtol,
+                   "DoF_per_s": wb.N * wb.nrhs * 2 / ((times[-1][0] + times[-1][1]) * 1e-3)}
+        log(f"[bench] adjoint batch: {adjoint}")
+        del planb, fb, u, ft, ct
+
     line = {
         "metric": "P^-1 applies/s (DoF/s) + solve time to 1e-8 resid, FP64 vs mixed",
         "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
@@ -308,8 +356,12 @@ def main():
         "matvec_fp64": matvec,
         "solve_to_1e-8": solves,
         "annulus_solve_to_1e-8": annulus,
+        "adjoint_batch": adjoint,
+        "setup_ms": setup_ms,
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items()
                                                   if k != "s_per_apply"},
+        "cpu_baseline_1thread": None if cpu1 is None else {k: v for k, v in cpu1.items()
+                                                           if k != "s_per_apply"},
     }
     print(json.dumps(line), flush=True)
 
