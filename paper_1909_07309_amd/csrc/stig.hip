@@ -123,7 +123,9 @@ struct stig_plan {
   int64_t csr_nnz = 0;
   // scratch
   DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, w, tmp, partial, small, flag, lift0, lift1;
-  std::vector<double> host_small;
+  // pinned host staging of the small Krylov transfers: 4 coefficient slots of
+  // KRY_MAXV doubles, then the breakdown flag
+  double *pin = nullptr;
   // optional per-kernel timing with HIP events on the plan's stream
   bool prof = false;
   struct Pending {
@@ -142,6 +144,7 @@ struct stig_plan {
       (void)hipEventDestroy(q.b);
     }
     for (auto e : free_events) (void)hipEventDestroy(e);
+    if (pin) (void)hipHostFree(pin);
   }
 };
 
@@ -1005,8 +1008,10 @@ struct Krylov {
   }
   // host value of slot `k`'s entry i (synchronises)
   stig_status fetch(int k, int i, double *out) {
-    HIP_TRY(hipMemcpyAsync(out, slot(k) + i, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->pin + 3 * KRY_MAXV, slot(k) + i, sizeof(double),
+                           hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
+    *out = p->pin[3 * KRY_MAXV];
     return STIG_OK;
   }
   // r = f - Ax; host value of ||r||_2 (synchronises)
@@ -1028,7 +1033,7 @@ struct Krylov {
                        partial());
     HIP_TRY(hipGetLastError());
     STIG_TRY(reduce(3));
-    double v[KRY_MAXV];
+    double *v = p->pin + 3 * KRY_MAXV;
     HIP_TRY(hipMemcpyAsync(v, slot(3), KRY_MAXV * sizeof(double), hipMemcpyDeviceToHost,
                            p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -1052,6 +1057,28 @@ stig_status apply_dispatch(stig_plan *p, const double *r, double *s, int nrhs, i
     case STIG_BF16: return run_apply<bf16, bf16>(p, r, s, nrhs, transpose);
   }
   return fail(STIG_EINVAL, "unknown precision");
+}
+
+// pinned staging area of the plan (allocated on first use)
+stig_status ensure_pinned(stig_plan *p) {
+  if (p->pin) return STIG_OK;
+  if (hipHostMalloc((void **)&p->pin, (4 * KRY_MAXV + 1) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    p->pin = nullptr;
+    return fail(STIG_ENOMEM, "pinned host staging buffer");
+  }
+  return STIG_OK;
+}
+int *pinned_flag(stig_plan *p) { return reinterpret_cast<int *>(p->pin + 4 * KRY_MAXV); }
+
+// reports (and clears) the breakdown flag whose copy is in the pinned area
+stig_status flag_result(stig_plan *p, int f) {
+  if (f) {
+    int z = 0;
+    HIP_TRY(hipMemcpy(p->flag.p, &z, sizeof(int), hipMemcpyHostToDevice));
+    return fail(STIG_EBREAKDOWN, "non-positive pivot in a shifted time system");
+  }
+  return STIG_OK;
 }
 
 stig_status check_flag(stig_plan *p) {
@@ -1082,8 +1109,8 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *w = p->w.as<double>(),
          *tmp = p->tmp.as<double>();
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  std::vector<double> &hs = p->host_small;
-  hs.assign(4 * KRY_MAXV, 0.0);
+  STIG_TRY(ensure_pinned(p));
+  double *hs = p->pin;
 
   double fnorm, unorm;
   STIG_TRY(K.norms(f, u, &fnorm, &unorm));
@@ -1131,10 +1158,13 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
       // scaling into v_{j+1} (and skipped when the cycle ends here).
       STIG_TRY(K.dots(V, j + 1, w, 0, 0));                  // h1 = V^T w
       STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, w, 1, 1));  // w -= V h1; h2 = V^T w; ||w||^2
-      HIP_TRY(hipMemcpyAsync(hs.data(), K.slot(0), 2 * KRY_MAXV * sizeof(double),
+      // the two coefficient slots and the breakdown flag in one round trip
+      HIP_TRY(hipMemcpyAsync(hs, K.slot(0), 2 * KRY_MAXV * sizeof(double),
                              hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipMemcpyAsync(pinned_flag(p), p->flag.p, sizeof(int), hipMemcpyDeviceToHost,
+                             p->stream));
       HIP_TRY(hipStreamSynchronize(p->stream));
-      STIG_TRY(check_flag(p));
+      STIG_TRY(flag_result(p, *pinned_flag(p)));
       info->iters++;
       const double wsq = hs[KRY_MAXV + KRY_MAXV - 1];
       double h2sq = 0.0;
@@ -1189,8 +1219,9 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
       for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
       y[i] = s / H[(size_t)i * m + i];
     }
-    std::copy(y.begin(), y.begin() + k, hs.begin() + 3 * KRY_MAXV);
-    HIP_TRY(hipMemcpyAsync(K.slot(3), hs.data() + 3 * KRY_MAXV, k * sizeof(double),
+    // (the pinned area is not touched again before the next synchronisation)
+    std::copy(y.begin(), y.begin() + k, hs + 2 * KRY_MAXV);
+    HIP_TRY(hipMemcpyAsync(K.slot(3), hs + 2 * KRY_MAXV, k * sizeof(double),
                            hipMemcpyHostToDevice, p->stream));
     STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));  // u += Z y
     // true residual
