@@ -167,6 +167,30 @@ stig_status stig_assemble_2d(int n_el, int p, int nq, const double *c11, const d
                              const double *c33, int64_t *rowptr, int32_t *col, double *valK,
                              double *valM, int64_t *nnz);
 
+/* The same in 3D on the unit cube in parametric coordinates (n = n_el + p - 2
+ * unknowns per direction, unknown s = i_1 + n (i_2 + n i_3), n^3 < 2^31):
+ *   K_ij = int c11 d1B_i d1B_j + c22 d2B_i d2B_j + c33 d3B_i d3B_j,
+ *   M_ij = int c00 B_i B_j,
+ * from coefficient values at the tensor Gauss grid (host, [q3][q2][q1] with
+ * n_el * nq points per direction).  Output CSR (host): rowptr (n^3 + 1), col
+ * (int32, sorted), valK, valM over the overlap pattern (|i_l - j_l| <= p).
+ * With rowptr == NULL only *nnz is returned (size query). */
+stig_status stig_assemble_3d(int n_el, int p, int nq, const double *c11, const double *c22,
+                             const double *c33, const double *c00, int64_t *rowptr, int32_t *col,
+                             double *valK, double *valM, int64_t *nnz);
+
+/* 3D form of eq. separation from element-midpoint samples (host, [e3][e2][e1],
+ * all positive): the mass coefficient C00 ~ phi1(e1) phi2(e2) phi3(e3) by a
+ * rank-one fit in log space (log phi1 = mean over (e2, e3) of log C00, log
+ * phi_l = mean over the other two of log C00 minus the global mean for l = 2, 3),
+ * then C_ll ~ Phi_l(e_l) prod_{m != l} phi_m with log Phi_l the mean over the
+ * other two directions of log(C_ll / prod_{m != l} phi_m).  Exact for products of
+ * univariate factors.  Outputs (host): phi_l, Phi_l of length n_l.  STIG_EINVAL
+ * for a non-positive sample. */
+stig_status stig_separate_3d(int n1, int n2, int n3, const double *C11, const double *C22,
+                             const double *C33, const double *C00, double *phi1, double *phi2,
+                             double *phi3, double *Phi1, double *Phi2, double *Phi3);
+
 /* Separable approximation of eq. separation from element-midpoint samples
  * (host, [e2][e1], n1 x n2 elements) of the diagonal coefficients C11, C22 and
  * C33: C33 ~ phi1(e1) phi2(e2), C11 ~ Phi1(e1) phi2(e2), C22 ~ phi1(e1) Phi2(e2),

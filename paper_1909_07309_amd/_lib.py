@@ -55,6 +55,10 @@ SIGNATURES = {
     "stig_assemble_2d": (C.c_int, [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _vp, _vp, _dp, _dp,
                                    C.POINTER(C.c_int64)]),
     "stig_separate_2d": (C.c_int, [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+    "stig_assemble_3d": (C.c_int, [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _vp, _vp, _dp,
+                                   _dp, C.POINTER(C.c_int64)]),
+    "stig_separate_3d": (C.c_int, [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                   _dp, _dp, _dp]),
     "stig_kron_csr_rowptr": (C.c_int, [C.c_int, C.c_int, C.c_int64, _vp, _vp]),
     "stig_kron_csr_fill": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, _dp]),
     "stig_quadrature": (C.c_int, [C.c_int, C.c_int, C.c_double, _dp, _dp]),

@@ -294,6 +294,32 @@ def separate_2d(C11, C22, C33):
     return tuple(out)
 
 
+def assemble_3d(n_el, p, nq, c11, c22, c33, c00):
+    """Host CSR (rowptr int64, col int32, valK, valM) of the 3D parametric stiffness / mass."""
+    cs = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (c11, c22, c33, c00)]
+    nnz = C.c_int64()
+    check(lib().stig_assemble_3d(n_el, p, nq, None, None, None, None, None, None, None, None,
+                                 C.byref(nnz)))
+    n = n_el + p - 2
+    rowptr = np.empty(n ** 3 + 1, dtype=np.int64)
+    col = np.empty(nnz.value, dtype=np.int32)
+    valK = np.empty(nnz.value)
+    valM = np.empty(nnz.value)
+    check(lib().stig_assemble_3d(n_el, p, nq, *[dptr(c) for c in cs],
+                                 rowptr.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p),
+                                 dptr(valK), dptr(valM), C.byref(nnz)))
+    return rowptr, col, valK, valM
+
+
+def separate_3d(C11, C22, C33, C00):
+    """(phi1, phi2, phi3, Phi1, Phi2, Phi3) from element-midpoint samples shaped [e3][e2][e1]."""
+    Cs = [np.ascontiguousarray(a, dtype=np.float64) for a in (C11, C22, C33, C00)]
+    n3, n2, n1 = Cs[3].shape
+    out = [np.empty(n1), np.empty(n2), np.empty(n3), np.empty(n1), np.empty(n2), np.empty(n3)]
+    check(lib().stig_separate_3d(n1, n2, n3, *[dptr(c) for c in Cs], *[dptr(o) for o in out]))
+    return tuple(out)
+
+
 def sym_eig(K, M):
     K = np.ascontiguousarray(K, dtype=np.float64)
     M = np.ascontiguousarray(M, dtype=np.float64)

@@ -267,6 +267,164 @@ void separate_2d(int n1, int n2, const double *C11, const double *C22, const dou
   }
 }
 
+int64_t assemble_3d(int n_el, int p, int nq, const double *c11, const double *c22,
+                    const double *c33, const double *c00, int64_t *rowptr, int32_t *col,
+                    double *valK, double *valM) {
+  // Restricted tensor-product space on (0,1)^3, n = n_el + p - 2 per direction,
+  // unknown s = i1 + n (i2 + n i3); pattern: |i_l - j_l| <= p in every direction.
+  const int n = n_el + p - 2;
+  const int64_t Ns = (int64_t)n * n * n;
+  auto width = [&](int i) { return std::min(n - 1, i + p) - std::max(0, i - p) + 1; };
+  if (!rowptr) {  // size query
+    int64_t w = 0;
+    for (int i = 0; i < n; ++i) w += width(i);
+    return w * w * w;
+  }
+  rowptr[0] = 0;
+  for (int64_t s = 0; s < Ns; ++s) {
+    const int i1 = (int)(s % n), i2 = (int)((s / n) % n), i3 = (int)(s / ((int64_t)n * n));
+    int64_t k = rowptr[s];
+    for (int j3 = std::max(0, i3 - p); j3 <= std::min(n - 1, i3 + p); ++j3)
+      for (int j2 = std::max(0, i2 - p); j2 <= std::min(n - 1, i2 + p); ++j2)
+        for (int j1 = std::max(0, i1 - p); j1 <= std::min(n - 1, i1 + p); ++j1) {
+          col[k] = j1 + n * (j2 + n * j3);
+          valK[k] = 0.0;
+          valM[k] = 0.0;
+          ++k;
+        }
+    rowptr[s + 1] = k;
+  }
+  std::vector<double> x, w;
+  element_quadrature(n_el, nq, 1.0, x, w);
+  const int P1 = p + 1, nqt = n_el * nq;
+  // basis values / derivatives at the points of every element: [e][k][a]
+  std::vector<double> Nv((size_t)n_el * nq * P1), Dv((size_t)n_el * nq * P1);
+  for (int e = 0; e < n_el; ++e)
+    for (int k = 0; k < nq; ++k)
+      span_basis(e, n_el, p, 1.0, x[(size_t)e * nq + k], &Nv[((size_t)e * nq + k) * P1],
+                 &Dv[((size_t)e * nq + k) * P1]);
+  const size_t L6 = (size_t)P1 * P1 * P1 * P1 * P1 * P1;
+  std::vector<double> T1((size_t)nq * nq * P1 * P1), T2((size_t)nq * P1 * P1 * P1 * P1);
+  std::vector<double> locK(L6), locM(L6);
+  // one term: loc += sum_q c(q) w(q) F3 G3 F2 G2 F1 G1 (F, G = values or derivatives),
+  // contracted one direction at a time
+  auto term = [&](const double *c, bool d1, bool d2, bool d3, int e1, int e2, int e3,
+                  std::vector<double> &loc) {
+    const double *B1 = &(d1 ? Dv : Nv)[(size_t)e1 * nq * P1];
+    const double *B2 = &(d2 ? Dv : Nv)[(size_t)e2 * nq * P1];
+    const double *B3 = &(d3 ? Dv : Nv)[(size_t)e3 * nq * P1];
+    const double *w1 = &w[(size_t)e1 * nq], *w2 = &w[(size_t)e2 * nq], *w3 = &w[(size_t)e3 * nq];
+    // T1[k3][k2][a1][b1]
+    for (int k3 = 0; k3 < nq; ++k3)
+      for (int k2 = 0; k2 < nq; ++k2) {
+        double *t = &T1[((size_t)k3 * nq + k2) * P1 * P1];
+        std::fill(t, t + P1 * P1, 0.0);
+        for (int k1 = 0; k1 < nq; ++k1) {
+          const size_t g = ((size_t)(e3 * nq + k3) * nqt + (e2 * nq + k2)) * nqt + (e1 * nq + k1);
+          const double cw = c[g] * w1[k1];
+          for (int a1 = 0; a1 < P1; ++a1)
+            for (int b1 = 0; b1 < P1; ++b1) t[a1 * P1 + b1] += cw * B1[k1 * P1 + a1] * B1[k1 * P1 + b1];
+        }
+      }
+    // T2[k3][a2][b2][a1][b1]
+    for (int k3 = 0; k3 < nq; ++k3) {
+      double *t2 = &T2[(size_t)k3 * P1 * P1 * P1 * P1];
+      std::fill(t2, t2 + P1 * P1 * P1 * P1, 0.0);
+      for (int k2 = 0; k2 < nq; ++k2) {
+        const double *t = &T1[((size_t)k3 * nq + k2) * P1 * P1];
+        for (int a2 = 0; a2 < P1; ++a2)
+          for (int b2 = 0; b2 < P1; ++b2) {
+            const double f = w2[k2] * B2[k2 * P1 + a2] * B2[k2 * P1 + b2];
+            double *o = t2 + (a2 * P1 + b2) * P1 * P1;
+            for (int ab = 0; ab < P1 * P1; ++ab) o[ab] += f * t[ab];
+          }
+      }
+    }
+    // loc[a3][b3][a2][b2][a1][b1]
+    for (int k3 = 0; k3 < nq; ++k3) {
+      const double *t2 = &T2[(size_t)k3 * P1 * P1 * P1 * P1];
+      for (int a3 = 0; a3 < P1; ++a3)
+        for (int b3 = 0; b3 < P1; ++b3) {
+          const double f = w3[k3] * B3[k3 * P1 + a3] * B3[k3 * P1 + b3];
+          double *o = &loc[(size_t)(a3 * P1 + b3) * P1 * P1 * P1 * P1];
+          for (int r = 0; r < P1 * P1 * P1 * P1; ++r) o[r] += f * t2[r];
+        }
+    }
+  };
+  for (int e3 = 0; e3 < n_el; ++e3)
+    for (int e2 = 0; e2 < n_el; ++e2)
+      for (int e1 = 0; e1 < n_el; ++e1) {
+        std::fill(locK.begin(), locK.end(), 0.0);
+        std::fill(locM.begin(), locM.end(), 0.0);
+        term(c11, true, false, false, e1, e2, e3, locK);
+        term(c22, false, true, false, e1, e2, e3, locK);
+        term(c33, false, false, true, e1, e2, e3, locK);
+        term(c00, false, false, false, e1, e2, e3, locM);
+        for (int a3 = 0; a3 < P1; ++a3)
+          for (int a2 = 0; a2 < P1; ++a2)
+            for (int a1 = 0; a1 < P1; ++a1) {
+              const int i1 = e1 + a1 - 1, i2 = e2 + a2 - 1, i3 = e3 + a3 - 1;
+              if (i1 < 0 || i1 >= n || i2 < 0 || i2 >= n || i3 < 0 || i3 >= n) continue;
+              const int64_t row = i1 + (int64_t)n * (i2 + (int64_t)n * i3);
+              const int lo1 = std::max(0, i1 - p), lo2 = std::max(0, i2 - p), lo3 = std::max(0, i3 - p);
+              const int wd1 = width(i1), wd2 = width(i2);
+              for (int b3 = 0; b3 < P1; ++b3)
+                for (int b2 = 0; b2 < P1; ++b2)
+                  for (int b1 = 0; b1 < P1; ++b1) {
+                    const int j1 = e1 + b1 - 1, j2 = e2 + b2 - 1, j3 = e3 + b3 - 1;
+                    if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n || j3 < 0 || j3 >= n) continue;
+                    const size_t li = ((((size_t)(a3 * P1 + b3) * P1 + a2) * P1 + b2) * P1 + a1) * P1 + b1;
+                    const int64_t k =
+                        rowptr[row] + ((int64_t)(j3 - lo3) * wd2 + (j2 - lo2)) * wd1 + (j1 - lo1);
+                    valK[k] += locK[li];
+                    valM[k] += locM[li];
+                  }
+            }
+      }
+  return rowptr[Ns];
+}
+
+void separate_3d(int n1, int n2, int n3, const double *C11, const double *C22, const double *C33,
+                 const double *C00, double *phi1, double *phi2, double *phi3, double *Phi1,
+                 double *Phi2, double *Phi3) {
+  // Rank-one fits in log space of element-midpoint samples [e3][e2][e1]: the
+  // mass coefficient C00 ~ phi1(e1) phi2(e2) phi3(e3) with
+  //   log phi1 = mean over (e2, e3) of log C00,
+  //   log phi_l = mean over the other two of log C00 - mean log C00  (l = 2, 3),
+  // and C_ll ~ Phi_l(e_l) prod_{m != l} phi_m with log Phi_l the mean over the
+  // other two directions of log(C_ll / prod_{m != l} phi_m).  Exact whenever
+  // the samples are products of univariate factors.
+  const size_t tot_n = (size_t)n1 * n2 * n3;
+  std::vector<double> r1(n1, 0.0), r2(n2, 0.0), r3(n3, 0.0);
+  double tot = 0.0;
+  auto at = [&](int e1, int e2, int e3) { return ((size_t)e3 * n2 + e2) * n1 + e1; };
+  for (int e3 = 0; e3 < n3; ++e3)
+    for (int e2 = 0; e2 < n2; ++e2)
+      for (int e1 = 0; e1 < n1; ++e1) {
+        const double l = std::log(C00[at(e1, e2, e3)]);
+        r1[e1] += l;
+        r2[e2] += l;
+        r3[e3] += l;
+        tot += l;
+      }
+  tot /= (double)tot_n;
+  for (int e1 = 0; e1 < n1; ++e1) phi1[e1] = std::exp(r1[e1] / ((double)n2 * n3));
+  for (int e2 = 0; e2 < n2; ++e2) phi2[e2] = std::exp(r2[e2] / ((double)n1 * n3) - tot);
+  for (int e3 = 0; e3 < n3; ++e3) phi3[e3] = std::exp(r3[e3] / ((double)n1 * n2) - tot);
+  std::vector<double> s1(n1, 0.0), s2(n2, 0.0), s3(n3, 0.0);
+  for (int e3 = 0; e3 < n3; ++e3)
+    for (int e2 = 0; e2 < n2; ++e2)
+      for (int e1 = 0; e1 < n1; ++e1) {
+        const size_t g = at(e1, e2, e3);
+        s1[e1] += std::log(C11[g] / (phi2[e2] * phi3[e3]));
+        s2[e2] += std::log(C22[g] / (phi1[e1] * phi3[e3]));
+        s3[e3] += std::log(C33[g] / (phi1[e1] * phi2[e2]));
+      }
+  for (int e1 = 0; e1 < n1; ++e1) Phi1[e1] = std::exp(s1[e1] / ((double)n2 * n3));
+  for (int e2 = 0; e2 < n2; ++e2) Phi2[e2] = std::exp(s2[e2] / ((double)n1 * n3));
+  for (int e3 = 0; e3 < n3; ++e3) Phi3[e3] = std::exp(s3[e3] / ((double)n1 * n2));
+}
+
 // Returns false if M is not positive definite.
 bool sym_eig(int n, const double *K, const double *M, double *U, double *lam) {
   std::vector<double> L((size_t)n * n, 0.0);

@@ -1530,6 +1530,32 @@ stig_status stig_separate_2d(int n1, int n2, const double *C11, const double *C2
   return STIG_OK;
 }
 
+stig_status stig_assemble_3d(int n_el, int p, int nq, const double *c11, const double *c22,
+                             const double *c33, const double *c00, int64_t *rowptr, int32_t *col,
+                             double *valK, double *valM, int64_t *nnz) {
+  if (n_el < 1 || p < 1 || p > 16 || nq < 1 || !nnz || n_el + p - 2 < 1)
+    return fail(STIG_EINVAL, "bad 3D assembly");
+  const int64_t n = n_el + p - 2;
+  if (n * n * n >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "3D space too large for int32 columns");
+  if (rowptr && (!col || !valK || !valM || !c11 || !c22 || !c33 || !c00))
+    return fail(STIG_EINVAL, "null 3D assembly array");
+  *nnz = assemble_3d(n_el, p, nq, c11, c22, c33, c00, rowptr, col, valK, valM);
+  return STIG_OK;
+}
+
+stig_status stig_separate_3d(int n1, int n2, int n3, const double *C11, const double *C22,
+                             const double *C33, const double *C00, double *phi1, double *phi2,
+                             double *phi3, double *Phi1, double *Phi2, double *Phi3) {
+  if (n1 < 1 || n2 < 1 || n3 < 1 || !C11 || !C22 || !C33 || !C00 || !phi1 || !phi2 || !phi3 ||
+      !Phi1 || !Phi2 || !Phi3)
+    return fail(STIG_EINVAL, "bad separation arguments");
+  for (int64_t i = 0; i < (int64_t)n1 * n2 * n3; ++i)
+    if (!(C11[i] > 0) || !(C22[i] > 0) || !(C33[i] > 0) || !(C00[i] > 0))
+      return fail(STIG_EINVAL, "coefficients must be positive");
+  separate_3d(n1, n2, n3, C11, C22, C33, C00, phi1, phi2, phi3, Phi1, Phi2, Phi3);
+  return STIG_OK;
+}
+
 stig_status stig_kron_csr_rowptr(int n_t, int p_t, int64_t ns, const int64_t *rowptr2d,
                                  int64_t *rowptr) {
   if (n_t < 1 || p_t < 0 || ns < 1 || !rowptr2d || !rowptr) return fail(STIG_EINVAL, "bad rowptr");

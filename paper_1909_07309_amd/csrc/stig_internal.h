@@ -29,6 +29,20 @@ void load_1d(int n_el, int p, double length, const double *fvals, int nq, double
 int64_t assemble_2d(int n_el, int p, int nq, const double *c11, const double *c22,
                     const double *c33, int64_t *rowptr, int32_t *col, double *valK, double *valM);
 
+// 3D stiffness / mass on the restricted tensor space (unknown s = i1 + n (i2 +
+// n i3)) from coefficient samples at the tensor Gauss grid [q3][q2][q1]:
+// K = int c11 d1B d1B + c22 d2B d2B + c33 d3B d3B, M = int c00 B B;
+// rowptr == nullptr: size query.
+int64_t assemble_3d(int n_el, int p, int nq, const double *c11, const double *c22,
+                    const double *c33, const double *c00, int64_t *rowptr, int32_t *col,
+                    double *valK, double *valM);
+
+// Separable (rank-one, log-space) approximation of 3D samples [e3][e2][e1]:
+// C00 ~ phi1 phi2 phi3 and C_ll ~ Phi_l prod_{m != l} phi_m.
+void separate_3d(int n1, int n2, int n3, const double *C11, const double *C22, const double *C33,
+                 const double *C00, double *phi1, double *phi2, double *phi3, double *Phi1,
+                 double *Phi2, double *Phi3);
+
 // Separable (rank-one, log-space) approximation of sampled coefficients.
 void separate_2d(int n1, int n2, const double *C11, const double *C22, const double *C33,
                  double *phi1, double *phi2, double *Phi1, double *Phi2);

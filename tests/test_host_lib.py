@@ -12,6 +12,8 @@ import pytest
 from oracle import bsplines as bs
 from oracle import fd
 
+import workloads as wl
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -165,3 +167,27 @@ def test_argument_validation_without_gpu():
     assert lib.stig_set_option(h, 7, 0) == -1
     lib.stig_plan_destroy(h)
     assert lib.stig_status_string(-4) == b"breakdown (non-positive pivot)"
+
+
+@pytest.mark.parametrize("n_el,p", [(4, 2), (5, 3)])
+def test_3d_assembly_separation_and_factors_match_oracle(n_el, p):
+    """The extruded-annulus setup on the host: 3D CSR stiffness / mass, the 3D
+    separation and the weighted 1D factors against the oracle's own code."""
+    from oracle.annulus3d import Annulus3DProblem
+    from paper_1909_07309_amd.annulus3d import Annulus3DSetup
+    w = wl.scaled(wl.WORKLOADS["annulus3d_p2_n32"], n_el, p=p)
+    a = Annulus3DSetup(w)
+    o = Annulus3DProblem(w)
+    rp, col, vK, vM = a.space
+    n3 = (n_el + p - 2) ** 3
+    assert rp.size == n3 + 1 and np.all(np.diff(rp) > 0)
+    import scipy.sparse as sp
+    K = sp.csr_matrix((vK, col, rp), shape=(n3, n3)).toarray()
+    M = sp.csr_matrix((vM, col, rp), shape=(n3, n3)).toarray()
+    assert np.abs(K - o.Ks.toarray()).max() <= 1e-13 * np.abs(K).max()
+    assert np.abs(M - o.Ms.toarray()).max() <= 1e-13 * np.abs(M).max()
+    assert np.abs(a.dKs - np.diag(K)).max() == 0 and np.abs(a.dMs - np.diag(M)).max() == 0
+    for l in range(3):
+        assert np.abs(a.Kt[l] - o.Kt[l]).max() <= 1e-13 * np.abs(o.Kt[l]).max()
+        assert np.abs(a.Mtl[l] - o.Mtl[l]).max() <= 1e-13 * np.abs(o.Mtl[l]).max()
+    assert np.abs(a.Wt - o.Wt).max() < 1e-14 and np.abs(a.Mt - o.Mt).max() < 1e-14

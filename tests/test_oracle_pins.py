@@ -357,3 +357,92 @@ def test_annulus_geometry_preconditioner_matches_dense():
     s = o.preconditioner().apply(r)
     ref = np.linalg.solve(AG, r.ravel())
     assert np.abs(s.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------- extruded annulus (3D)
+
+def _annulus3d(n_el, p=2):
+    from oracle.annulus3d import Annulus3DProblem
+    return Annulus3DProblem(wl.scaled(wl.WORKLOADS["annulus3d_p2_n32"], n_el, p=p))
+
+
+def test_annulus3d_mass_is_radially_weighted_kronecker_product():
+    """M_s = int B_i B_j |det J| with |det J| = pi r / 2 depending on eta_1 only:
+    M-hat_3 (x) M-hat_2 (x) M_r[pi r / 2]."""
+    o = _annulus3d(4, p=3)
+    xi = bs.open_uniform_knots(4, 3)
+    Mr = bs.restrict_space(bs.mass(xi, 3, weight=lambda x: np.pi * (1 + x) / 2, nq=6))
+    Mh = bs.restrict_space(bs.mass(xi, 3, nq=6))
+    assert np.abs(o.Ms.toarray() - np.kron(Mh, np.kron(Mh, Mr))).max() < 1e-15
+
+
+def test_annulus3d_stiffness_separates_for_constant_conductivity(monkeypatch):
+    """With kappa = 1 the extruded polar-map stiffness is
+    M3 (x) M2 (x) K_r[pi r/2] + M3 (x) K2 (x) M_r[2/(pi r)] + K3 (x) M2 (x) M_r[pi r/2]
+    (direction 1 radial, 2 angular, 3 along the extrusion)."""
+    monkeypatch.setattr(wl, "annulus3d_conductivity", lambda x, y, z: np.ones_like(x))
+    o = _annulus3d(4, p=2)
+    xi = bs.open_uniform_knots(4, 2)
+    Kr = bs.restrict_space(bs.stiffness(xi, 2, weight=lambda x: np.pi * (1 + x) / 2, nq=5))
+    Mr1 = bs.restrict_space(bs.mass(xi, 2, weight=lambda x: 2 / (np.pi * (1 + x)), nq=5))
+    Mr2 = bs.restrict_space(bs.mass(xi, 2, weight=lambda x: np.pi * (1 + x) / 2, nq=5))
+    Kh = bs.restrict_space(bs.stiffness(xi, 2, nq=5))
+    Mh = bs.restrict_space(bs.mass(xi, 2, nq=5))
+    ref = (np.kron(Mh, np.kron(Mh, Kr)) + np.kron(Mh, np.kron(Kh, Mr1))
+           + np.kron(Kh, np.kron(Mh, Mr2)))
+    assert np.abs(o.Ks.toarray() - ref).max() < 1e-12 * np.abs(ref).max()
+    # C00, C11 and C33 depend on eta_1 only: their separated fits are exact
+    mids = (np.arange(4) + 0.5) / 4
+    E3, E2, E1 = np.meshgrid(mids, mids, mids, indexing="ij")
+    c = np.pi * (1 + E1) / 2
+    phi1, phi2, phi3 = o.phi
+    Phi1, Phi2, Phi3 = o.Phi
+    prod = phi3[:, None, None] * phi2[None, :, None] * phi1[None, None, :]
+    assert np.allclose(prod, c, rtol=1e-13)
+    assert np.allclose(phi3[:, None, None] * phi2[None, :, None] * Phi1[None, None, :], c, rtol=1e-13)
+    assert np.allclose(Phi3[:, None, None] * phi2[None, :, None] * phi1[None, None, :], c, rtol=1e-13)
+
+
+def test_annulus3d_separation_is_exact_for_separable_samples(monkeypatch):
+    """The 3D fit of eq. separation reproduces samples that have the model's form:
+    C00 = b1(e1) b2(e2) b3(e3) and C_ll = a_l(e_l) prod_{m != l} b_m(e_m)."""
+    from oracle import annulus3d as a3
+    b1 = lambda x: 1 + x
+    b2 = lambda y: 1 + y ** 2
+    b3 = lambda z: 3 - z
+    coeffs = lambda e1, e2, e3: ((0.5 + e1) * b2(e2) * b3(e3), b1(e1) * (2 + e2) * b3(e3),
+                                 b1(e1) * b2(e2) * (1 + e3), b1(e1) * b2(e2) * b3(e3))
+    monkeypatch.setattr(a3, "extruded_polar_coefficients", coeffs)
+    monkeypatch.setattr(wl, "annulus3d_conductivity", lambda x, y, z: np.ones_like(x))
+    o = _annulus3d(5, p=2)
+    mids = (np.arange(5) + 0.5) / 5
+    E3, E2, E1 = np.meshgrid(mids, mids, mids, indexing="ij")
+    C11, C22, C33, C00 = coeffs(E1, E2, E3)
+    phi1, phi2, phi3 = o.phi
+    Phi1, Phi2, Phi3 = o.Phi
+    g = lambda f3, f2, f1: f3[:, None, None] * f2[None, :, None] * f1[None, None, :]
+    assert np.allclose(g(phi3, phi2, phi1), C00, rtol=1e-13)
+    assert np.allclose(g(phi3, phi2, Phi1), C11, rtol=1e-13)
+    assert np.allclose(g(phi3, Phi2, phi1), C22, rtol=1e-13)
+    assert np.allclose(g(Phi3, phi2, phi1), C33, rtol=1e-13)
+    # and a dropped direction is caught: a fit without phi3 misses C00
+    assert not np.allclose(g(np.ones(5), phi2, phi1), C00, rtol=1e-3)
+
+
+def test_annulus3d_geometry_preconditioner_matches_dense():
+    """A-hat^G = D^{1/2} A-tilde D^{1/2} in 3D: FD apply against a dense solve, and
+    diag(A-hat^G) = diag(A)."""
+    o = _annulus3d(3, p=2)
+    Kt, Mtl = o.Kt, o.Mtl
+    k3 = lambda a, b, c: np.kron(a, np.kron(b, c))
+    Ms = k3(Mtl[2], Mtl[1], Mtl[0])
+    Ks = k3(Mtl[2], Mtl[1], Kt[0]) + k3(Mtl[2], Kt[1], Mtl[0]) + k3(Kt[2], Mtl[1], Mtl[0])
+    At = np.kron(o.Wt, Ms) + np.kron(o.Mt, Ks)
+    D = o.D().ravel()
+    AG = np.sqrt(D)[:, None] * At * np.sqrt(D)[None, :]
+    A = o.dense_A()
+    assert np.abs(np.diag(AG) - np.diag(A)).max() < 1e-13 * np.abs(np.diag(A)).max()
+    r = wl.random_tensor(o.w.shape, 2)
+    s = o.preconditioner().apply(r)
+    ref = np.linalg.solve(AG, r.ravel())
+    assert np.abs(s.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -72,6 +72,11 @@ WORKLOADS = {
     "annulus_p4_n128": Workload("annulus_p4_n128", d=2, p=4, n_el=128,
                                 rtol=1e-8, geometry="annulus",
                                 precisions=("fp32",)),
+    # 3D quarter annulus (radii 1, 2) extruded along z over [0, 1], p=2, 32
+    # elements: variable 3D conductivity and heat capacity, full space-time CSR
+    # system matrix, 3D geometry-aware preconditioner.  32^3 x 33 = 1,081,344 unknowns.
+    "annulus3d_p2_n32": Workload("annulus3d_p2_n32", d=3, p=2, n_el=32, rtol=1e-8,
+                                 geometry="annulus3d", precisions=("fp32",)),
     # 3D unit cube, p=3, 48 elements, a batch of 32 right-hand sides.
     "cube_p3_n48_b32": Workload("cube_p3_n48_b32", d=3, p=3, n_el=48,
                                 rtol=1e-13, nrhs=32),
@@ -142,6 +147,11 @@ def random_tensor(shape, seed: int) -> np.ndarray:
 def annulus_conductivity(x, y):
     """kappa(x) = 1 + 0.5 sin(2 pi x) sin(2 pi y)."""
     return 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+
+
+def annulus3d_conductivity(x, y, z):
+    """kappa(x) = 1 + 0.5 sin(2 pi x) sin(2 pi y) cos(pi z)."""
+    return 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.cos(np.pi * z)
 
 
 def annulus_heat_capacity(t):
