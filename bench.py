@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-annulus", action="store_true",
-                    help="skip the annulus solves (variable coefficients, CSR matvec)")
+                    help="skip the 2D and 3D annulus solves (variable coefficients, CSR matvec)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the batched forward + adjoint solve (32 right-hand sides)")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -306,6 +306,43 @@ def main():
         annulus["N"] = wa.N
         del pa, asu
 
+    # ---- extruded annulus in 3D (A-hat^G with the 3D separation, CSR matvec):
+    # FGMRES(30) to 1e-8 with the FP64 and with the FP32 preconditioner
+    annulus3d = {}
+    if not args.no_solve and not args.no_annulus:
+        from paper_1909_07309_amd.annulus3d import Annulus3DSetup
+        w3 = wl.WORKLOADS["annulus3d_p2_n32"]
+        t0 = time.perf_counter()
+        a3 = Annulus3DSetup(w3)
+        p3 = a3.make_plan()
+        torch.cuda.synchronize()
+        annulus3d["setup_ms"] = (time.perf_counter() - t0) * 1e3
+        f3 = a3.source()
+        s3 = torch.empty_like(f3)
+        for prec in ("fp64", "fp32"):
+            for _ in range(3):
+                p3.apply_Pinv(f3, s3, prec=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                p3.apply_Pinv(f3, s3, prec=prec)
+            torch.cuda.synchronize()
+            apply_ms = (time.perf_counter() - t0) / 10 * 1e3
+            p3.gmres_solve(f3, torch.zeros_like(f3), restart=30, rtol=1e-8, maxit=300,
+                           flexible=True, prec=prec)  # warm (allocations)
+            u3 = torch.zeros_like(f3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u3, info = p3.gmres_solve(f3, u3, restart=30, rtol=1e-8, maxit=300, flexible=True,
+                                      prec=prec)
+            torch.cuda.synchronize()
+            annulus3d[prec] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
+                               "relres_true": info["relres_true"], "apply_ms": apply_ms,
+                               "method": "FGMRES(30)"}
+            log(f"[bench] annulus3d solve {prec}: {annulus3d[prec]}")
+        annulus3d["N"] = w3.N
+        del p3, a3
+
     # ---- batched forward + adjoint solve (p=3, 48 elements, 32 right-hand sides):
     # u = A^{-1}(f - A_I0 c0), loss 0.5 ||u - u*||^2, gradients w.r.t. f and c0
     adjoint = {}
@@ -356,6 +393,7 @@ def main():
         "matvec_fp64": matvec,
         "solve_to_1e-8": solves,
         "annulus_solve_to_1e-8": annulus,
+        "annulus3d_solve_to_1e-8": annulus3d,
         "adjoint_batch": adjoint,
         "setup_ms": setup_ms,
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items()
