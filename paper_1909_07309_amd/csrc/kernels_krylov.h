@@ -88,8 +88,8 @@ krylov_dots(const double *__restrict__ V, int64_t ldv, int nv, const double *__r
   block_reduce_store<NV>(acc, nv, with_norm, red, partial);
 }
 
-// w_new = w + sign * sum_i coef[i] V_i (coef in device memory), written as
-// dst = scale * w_new (dst may be w); then, if with_dots, partial dots
+// w_new = w + sign * sum_i coef[i] V_i (coef in device memory; w == nullptr
+// reads as zero), written as dst = scale * w_new (dst may be w); then, if with_dots, partial dots
 // V_i . w_new and w_new . w_new as in krylov_dots (with_norm = 1).  The dot
 // products re-read V_i[e] right after the update read it (cache hits).
 template <int NV>
@@ -112,7 +112,7 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + u * stride;
-      we[u] = e < N ? w[e] : 0.0;
+      we[u] = (w && e < N) ? w[e] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i)

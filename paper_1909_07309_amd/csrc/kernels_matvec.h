@@ -73,6 +73,58 @@ __global__ void band_pass_strided(const double *__restrict__ in1, const double *
   }
 }
 
+// The last pass of the matvec fused with the residual: for each spatial
+// column (stride inner along t), r = f - (sum_m Bb[j][m] b[j+m-P] + Bc[j][m]
+// a[j+m-P]) and this block's share of r . r in partial[blockIdx.x] (fixed-order
+// block reduction).
+template <int P>
+__global__ void __launch_bounds__(256)
+time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
+                   const double *__restrict__ f, double *__restrict__ r,
+                   const double *__restrict__ Bb, const double *__restrict__ Bc, int n,
+                   int64_t inner, int64_t total_cols, double *__restrict__ partial) {
+  constexpr int B = 2 * P + 1;
+  __shared__ double red[4];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (c < total_cols) {
+    const int64_t o = c / inner, i = c - o * inner;
+    const int64_t base = o * (int64_t)n * inner + i;
+    double wa[B], wb[B];
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+      const int j = m - P;
+      wa[m] = (j >= 0 && j < n) ? a[base + (int64_t)j * inner] : 0.0;
+      wb[m] = (j >= 0 && j < n) ? b[base + (int64_t)j * inner] : 0.0;
+    }
+    cptr<double> cBb = as_const(Bb), cBc = as_const(Bc);
+    for (int j = 0; j < n; ++j) {
+      cptr<double> rb = cBb + (size_t)j * B;
+      cptr<double> rc = cBc + (size_t)j * B;
+      const int64_t e = base + (int64_t)j * inner;
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < B; ++m) s += rb[m] * wb[m] + rc[m] * wa[m];
+      const double rv = f[e] - s;
+      r[e] = rv;
+      acc += rv * rv;
+#pragma unroll
+      for (int m = 0; m < B - 1; ++m) {
+        wa[m] = wa[m + 1];
+        wb[m] = wb[m + 1];
+      }
+      const int jn = j + P + 1;
+      wa[B - 1] = (jn < n) ? a[base + (int64_t)jn * inner] : 0.0;
+      wb[B - 1] = (jn < n) ? b[base + (int64_t)jn * inner] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 // Contiguous axis (inner == 1): one thread per output entry; the 2P+1 reads
 // of neighbouring entries hit the same cache lines as the neighbouring threads.
 template <int P>

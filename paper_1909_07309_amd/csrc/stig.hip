@@ -923,6 +923,57 @@ stig_status launch_stencil(stig_plan *p, const double *x, double *a, double *b, 
   return fail(STIG_EINVAL, "unsupported degree");
 }
 
+// spatial part of the banded matvec: a = x (x) M_s, b = x (x) K_s (all d axes)
+stig_status matvec_spatial(stig_plan *p, const double *x, int nrhs, const double **a,
+                           const double **b) {
+  const int64_t tot = p->N * nrhs;
+  if (stencil_fits(p)) {
+    // spatial part in one stencil pass per (rhs, t) slice
+    STIG_TRY(p->m0.ensure(tot * sizeof(double)));
+    STIG_TRY(p->m1.ensure(tot * sizeof(double)));
+    STIG_TRY(launch_stencil(p, x, p->m0.as<double>(), p->m1.as<double>(), nrhs));
+    *a = p->m0.as<double>();
+    *b = p->m1.as<double>();
+    return STIG_OK;
+  }
+  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+  for (auto *bb : bufs) STIG_TRY(bb->ensure(tot * sizeof(double)));
+  return spatial_chain(p, x, tot, true, a, b, bufs);
+}
+
+template <int P>
+stig_status launch_time_residual(stig_plan *p, const double *a, const double *b, const double *f,
+                                 double *r, int transpose, double *partial, int64_t blocks) {
+  const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
+  ProfScope ps(p, STIG_K_BAND_PASS, (double)p->N * 8 * 4);
+  hipLaunchKernelGGL(time_pass_residual<P>, dim3((unsigned)blocks), dim3(256), 0, p->stream, a, b,
+                     f, r, p->tnM.as<double>(), gW, p->nt, p->Ns, p->Ns, partial);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+// r = f - A x for one right-hand side on the banded (Kronecker) form, with the
+// last pass fused with the residual and this grid's partial sums of r . r in
+// partial[0 .. *nparts).  Returns STIG_EINVAL (nothing launched) on the CSR form.
+stig_status run_residual_banded(stig_plan *p, const double *f, const double *x, double *r,
+                                int transpose, double *partial, int64_t partial_cap,
+                                int64_t *nparts) {
+  if (p->csr_rowptr) return fail(STIG_EINVAL, "no banded form");
+  const int64_t blocks = (p->Ns + 255) / 256;
+  if (blocks > partial_cap) return fail(STIG_EINVAL, "residual partials do not fit");
+  const double *a, *b;
+  STIG_TRY(matvec_spatial(p, x, 1, &a, &b));
+  *nparts = blocks;
+  switch (p->pt) {
+    case 1: return launch_time_residual<1>(p, a, b, f, r, transpose, partial, blocks);
+    case 2: return launch_time_residual<2>(p, a, b, f, r, transpose, partial, blocks);
+    case 3: return launch_time_residual<3>(p, a, b, f, r, transpose, partial, blocks);
+    case 4: return launch_time_residual<4>(p, a, b, f, r, transpose, partial, blocks);
+    case 5: return launch_time_residual<5>(p, a, b, f, r, transpose, partial, blocks);
+  }
+  return fail(STIG_EINVAL, "unsupported degree");
+}
+
 stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int transpose) {
   const int64_t tot = p->N * nrhs;
   if (p->csr_rowptr) {
@@ -935,19 +986,8 @@ stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int t
     }
     return STIG_OK;
   }
-  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
   const double *a, *b;
-  if (stencil_fits(p)) {
-    // spatial part in one stencil pass per (rhs, t) slice
-    STIG_TRY(p->m0.ensure(tot * sizeof(double)));
-    STIG_TRY(p->m1.ensure(tot * sizeof(double)));
-    STIG_TRY(launch_stencil(p, x, p->m0.as<double>(), p->m1.as<double>(), nrhs));
-    a = p->m0.as<double>();
-    b = p->m1.as<double>();
-  } else {
-    for (auto *bb : bufs) STIG_TRY(bb->ensure(tot * sizeof(double)));
-    STIG_TRY(spatial_chain(p, x, tot, true, &a, &b, bufs));
-  }
+  STIG_TRY(matvec_spatial(p, x, nrhs, &a, &b));
   // time pass: y = nu (b x_t M_t) + gamma (a x_t W_t)
   const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
   STIG_TRY(band_pass(p, p->pt, a, b, nullptr, y, nullptr, p->tnM.as<double>(), gW, p->nt, p->Ns,
@@ -994,10 +1034,12 @@ struct Krylov {
   }
   // dst (default w) = scale * (w + sign * V coef); with_dots: V^T w_new and
   // ||w_new||^2 into slot region out_slot
+  // (w == nullptr with dst given: w reads as zero)
   stig_status update(const double *V, int nv, const double *coef, double sign, double *w,
                      int with_dots, int out_slot, double *dst = nullptr, double scale = 1.0) {
     if (nv > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
     if (!dst) dst = w;
+    if (!dst) return fail(STIG_EINVAL, "update without a destination");
     ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 2) * p->N * 8);
     if (nv <= 4) launch_update<4>(V, nv, coef, sign, w, dst, scale, with_dots);
     else if (nv <= 8) launch_update<8>(V, nv, coef, sign, w, dst, scale, with_dots);
@@ -1013,6 +1055,25 @@ struct Krylov {
     HIP_TRY(hipStreamSynchronize(p->stream));
     *out = p->pin[3 * KRY_MAXV];
     return STIG_OK;
+  }
+  // r = f - A u; host value of ||r||_2 (synchronises).  On the banded form the
+  // last pass of the product writes r and its partial norms directly.
+  stig_status residual_of(const double *f, const double *u, double *r, double *tmp,
+                          int transpose, double *norm) {
+    const int64_t cap = (int64_t)(p->partial.bytes / sizeof(double));
+    if (!p->csr_rowptr && (p->Ns + 255) / 256 <= cap) {
+      int64_t nparts = 0;
+      STIG_TRY(run_residual_banded(p, f, u, r, transpose, partial(), cap, &nparts));
+      hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(KRY_BLOCK), 0, p->stream, partial(),
+                         (int)nparts, slot(3));
+      HIP_TRY(hipGetLastError());
+      double v;
+      STIG_TRY(fetch(3, 0, &v));
+      *norm = std::sqrt(v);
+      return STIG_OK;
+    }
+    STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
+    return residual(f, tmp, r, norm);
   }
   // r = f - Ax; host value of ||r||_2 (synchronises)
   stig_status residual(const double *f, const double *Ax, double *r, double *norm) {
@@ -1132,8 +1193,7 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     r = f;
     beta = fnorm;
   } else {
-    STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
-    STIG_TRY(K.residual(f, tmp, V, &beta));
+    STIG_TRY(K.residual_of(f, u, V, tmp, transpose, &beta));
   }
   if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite initial residual");
   info->relres_true = beta / fnorm;
@@ -1223,10 +1283,11 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     std::copy(y.begin(), y.begin() + k, hs + 2 * KRY_MAXV);
     HIP_TRY(hipMemcpyAsync(K.slot(3), hs + 2 * KRY_MAXV, k * sizeof(double),
                            hipMemcpyHostToDevice, p->stream));
-    STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));  // u += Z y
+    // u += Z y (u = Z y while u is the zero initial guess)
+    if (cycle == 1 && unorm == 0.0) STIG_TRY(K.update(Z, k, K.slot(3), 1.0, nullptr, 0, 0, u));
+    else STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));
     // true residual
-    STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
-    STIG_TRY(K.residual(f, tmp, V, &beta));
+    STIG_TRY(K.residual_of(f, u, V, tmp, transpose, &beta));
     if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite residual");
     info->relres_true = beta / fnorm;
   }
