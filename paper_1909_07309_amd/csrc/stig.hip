@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <type_traits>
 #include <chrono>
 #include <cmath>
@@ -126,6 +127,7 @@ struct stig_plan {
   // pinned host staging of the small Krylov transfers: 4 coefficient slots of
   // KRY_MAXV doubles, then the breakdown flag
   double *pin = nullptr;
+  size_t pin_n = 0;  // doubles in the pinned area
   // optional per-kernel timing with HIP events on the plan's stream
   bool prof = false;
   struct Pending {
@@ -999,10 +1001,13 @@ stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int t
 
 struct Krylov {
   stig_plan *p;
+  int64_t ld = 0;   // distance between consecutive basis vectors (0: N)
+  int64_t off = 0;  // offset of this right-hand side's slot regions in the small buffer
   double *partial() { return p->partial.as<double>(); }
   double *small() { return p->small.as<double>(); }
+  int64_t ldv() const { return ld ? ld : p->N; }
   // out[0..KRY_MAXV) of the small buffer region `slot`
-  double *slot(int k) { return small() + k * KRY_MAXV; }
+  double *slot(int k) { return small() + off + k * KRY_MAXV; }
 
   // reduce the per-block partial sums into slot region `out_slot`
   stig_status reduce(int out_slot) {
@@ -1013,13 +1018,13 @@ struct Krylov {
   }
   template <int NV>
   void launch_dots(const double *V, int nv, const double *w, int with_norm) {
-    hipLaunchKernelGGL(krylov_dots<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N, nv,
-                       w, p->N, with_norm, partial());
+    hipLaunchKernelGGL(krylov_dots<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, ldv(),
+                       nv, w, p->N, with_norm, partial());
   }
   template <int NV>
   void launch_update(const double *V, int nv, const double *coef, double sign, const double *w,
                      double *dst, double scale, int with_dots) {
-    hipLaunchKernelGGL(krylov_update<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, p->N,
+    hipLaunchKernelGGL(krylov_update<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, V, ldv(),
                        nv, coef, sign, w, dst, scale, p->N, with_dots, partial());
   }
   stig_status dots(const double *V, int nv, const double *w, int with_norm, int out_slot) {
@@ -1075,6 +1080,22 @@ struct Krylov {
     STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
     return residual(f, tmp, r, norm);
   }
+  // r = f - Ax, ||r||^2 into slot 3 entry KRY_MAXV-1 (no synchronisation)
+  stig_status residual_async(const double *f, const double *Ax, double *r) {
+    ProfScope ps(p, STIG_K_KRYLOV, 3.0 * p->N * 8);
+    hipLaunchKernelGGL(residual_norm, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, f, Ax, r,
+                       p->N, partial());
+    HIP_TRY(hipGetLastError());
+    return reduce(3);
+  }
+  // ||x||^2, ||y||^2 into slot 3 entries 0 and KRY_MAXV-1 (no synchronisation)
+  stig_status norms_async(const double *x, const double *y) {
+    ProfScope ps(p, STIG_K_KRYLOV, 2.0 * p->N * 8);
+    hipLaunchKernelGGL(two_norms, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, x, y, p->N,
+                       partial());
+    HIP_TRY(hipGetLastError());
+    return reduce(3);
+  }
   // r = f - Ax; host value of ||r||_2 (synchronises)
   stig_status residual(const double *f, const double *Ax, double *r, double *norm) {
     ProfScope ps(p, STIG_K_KRYLOV, 3.0 * p->N * 8);
@@ -1121,16 +1142,21 @@ stig_status apply_dispatch(stig_plan *p, const double *r, double *s, int nrhs, i
 }
 
 // pinned staging area of the plan (allocated on first use)
-stig_status ensure_pinned(stig_plan *p) {
-  if (p->pin) return STIG_OK;
-  if (hipHostMalloc((void **)&p->pin, (4 * KRY_MAXV + 1) * sizeof(double)) != hipSuccess) {
+stig_status ensure_pinned(stig_plan *p, size_t n = 4 * KRY_MAXV + 1) {
+  if (p->pin && p->pin_n >= n) return STIG_OK;
+  if (p->pin) (void)hipHostFree(p->pin);
+  p->pin = nullptr;
+  p->pin_n = 0;
+  if (hipHostMalloc((void **)&p->pin, n * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     p->pin = nullptr;
     return fail(STIG_ENOMEM, "pinned host staging buffer");
   }
+  p->pin_n = n;
   return STIG_OK;
 }
-int *pinned_flag(stig_plan *p) { return reinterpret_cast<int *>(p->pin + 4 * KRY_MAXV); }
+// the breakdown flag's copy: the last double of the pinned area
+int *pinned_flag(stig_plan *p) { return reinterpret_cast<int *>(p->pin + p->pin_n - 1); }
 
 // reports (and clears) the breakdown flag whose copy is in the pinned area
 stig_status flag_result(stig_plan *p, int f) {
@@ -1293,6 +1319,182 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   }
   STIG_TRY(check_flag(p));
   return info->relres_true <= rtol ? STIG_OK : STIG_NOT_CONVERGED;
+}
+
+// First restart cycle of (F)GMRES for nb right-hand sides in lockstep: step j
+// applies the preconditioner and A to the j-th basis vectors of all of them in
+// one batched call (basis vectors stored [j][rhs][N]), runs each one's Gram-
+// Schmidt kernels, and synchronises once for all.  A right-hand side whose
+// estimate reaches rtol (or that breaks down) freezes; its later basis slots
+// are zeroed so the batched calls stay finite.  At the end every solution is
+// updated and its true residual computed; done[r] tells which reached rtol.
+// The iteration is the same as gmres_one's first cycle for each right-hand side.
+stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m, double rtol,
+                        int maxit, int transpose, stig_prec prec, stig_info *infos, bool *done) {
+  const int64_t N = p->N, ld = (int64_t)nb * N;
+  constexpr int S4 = 4 * KRY_MAXV;  // small-buffer doubles per right-hand side
+  STIG_TRY(p->V.ensure((size_t)(m + 1) * ld * sizeof(double)));
+  STIG_TRY(p->Z.ensure((size_t)m * ld * sizeof(double)));
+  STIG_TRY(p->w.ensure((size_t)ld * sizeof(double)));
+  STIG_TRY(p->tmp.ensure((size_t)ld * sizeof(double)));
+  STIG_TRY(p->small.ensure((size_t)nb * S4 * sizeof(double)));
+  STIG_TRY(ensure_pinned(p, (size_t)nb * S4 + 1));
+  double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *w = p->w.as<double>(),
+         *tmp = p->tmp.as<double>(), *hs = p->pin;
+  std::vector<Krylov> K;
+  for (int r = 0; r < nb; ++r) K.push_back(Krylov{p, ld, (int64_t)r * S4});
+  auto fetch_all = [&](bool with_flag) -> stig_status {
+    HIP_TRY(hipMemcpyAsync(hs, p->small.p, (size_t)nb * S4 * sizeof(double),
+                           hipMemcpyDeviceToHost, p->stream));
+    if (with_flag)
+      HIP_TRY(hipMemcpyAsync(pinned_flag(p), p->flag.p, sizeof(int), hipMemcpyDeviceToHost,
+                             p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return with_flag ? flag_result(p, *pinned_flag(p)) : STIG_OK;
+  };
+  // ||f||, ||u|| of every right-hand side in one round trip
+  for (int r = 0; r < nb; ++r) STIG_TRY(K[r].norms_async(f + r * N, u + r * N));
+  STIG_TRY(fetch_all(false));
+  std::vector<double> fnorm(nb), unorm(nb), beta(nb, 0.0);
+  for (int r = 0; r < nb; ++r) {
+    fnorm[r] = std::sqrt(hs[r * S4 + 3 * KRY_MAXV]);
+    unorm[r] = std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
+    if (!std::isfinite(fnorm[r])) return fail(STIG_ENONFINITE, "non-finite right-hand side norm");
+    if (!std::isfinite(unorm[r])) return fail(STIG_ENONFINITE, "non-finite initial guess");
+  }
+  std::vector<char> active(nb, 0);
+  std::vector<int> kk(nb, 0);
+  std::vector<std::vector<double>> H(nb), cs(nb), sn(nb), g(nb);
+  for (int r = 0; r < nb; ++r) {
+    infos[r] = stig_info{0, 0, 0.0, 0.0, 0.0};
+    done[r] = false;
+    double *v0 = V + r * N;
+    if (fnorm[r] == 0.0) {
+      HIP_TRY(hipMemsetAsync(u + r * N, 0, N * sizeof(double), p->stream));
+      HIP_TRY(hipMemsetAsync(v0, 0, N * sizeof(double), p->stream));
+      done[r] = true;
+      continue;
+    }
+    if (unorm[r] == 0.0) {
+      beta[r] = fnorm[r];
+      STIG_TRY(K[r].axpby(f + r * N, nullptr, v0, 1.0 / beta[r], 0.0));
+    } else {
+      STIG_TRY(K[r].residual_of(f + r * N, u + r * N, v0, tmp, transpose, &beta[r]));
+      if (!std::isfinite(beta[r])) return fail(STIG_ENONFINITE, "non-finite initial residual");
+      if (beta[r] / fnorm[r] <= rtol) {  // already converged: keep u
+        infos[r].relres_true = infos[r].relres_est = beta[r] / fnorm[r];
+        HIP_TRY(hipMemsetAsync(v0, 0, N * sizeof(double), p->stream));
+        done[r] = true;
+        continue;
+      }
+      STIG_TRY(K[r].axpby(v0, nullptr, v0, 1.0 / beta[r], 0.0));
+    }
+    infos[r].relres_true = infos[r].relres_est = beta[r] / fnorm[r];
+    active[r] = 1;
+    H[r].assign((size_t)(m + 1) * m, 0.0);
+    cs[r].assign(m, 0.0);
+    sn[r].assign(m, 0.0);
+    g[r].assign(m + 1, 0.0);
+    g[r][0] = beta[r];
+  }
+  auto any_active = [&]() {
+    for (int r = 0; r < nb; ++r)
+      if (active[r]) return true;
+    return false;
+  };
+  for (int j = 0; j < m && any_active(); ++j) {
+    STIG_TRY(apply_dispatch(p, V + j * ld, Z + j * ld, nb, transpose, prec));
+    STIG_TRY(run_matvec(p, Z + j * ld, w, nb, transpose));
+    for (int r = 0; r < nb; ++r) {
+      if (!active[r]) continue;
+      STIG_TRY(K[r].dots(V + r * N, j + 1, w + r * N, 0, 0));
+      STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(0), -1.0, w + r * N, 1, 1));
+    }
+    STIG_TRY(fetch_all(true));
+    for (int r = 0; r < nb; ++r) {
+      if (!active[r]) continue;
+      const double *h = hs + r * S4;
+      std::vector<double> &Hr = H[r];
+      infos[r].iters++;
+      const double wsq = h[KRY_MAXV + KRY_MAXV - 1];
+      double h2sq = 0.0;
+      for (int i = 0; i <= j; ++i) h2sq += h[KRY_MAXV + i] * h[KRY_MAXV + i];
+      bool corrected = false;
+      double hnext;
+      if (wsq - h2sq >= 0.25 * wsq) {
+        hnext = std::sqrt(wsq - h2sq);
+      } else {
+        STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(1), -1.0, w + r * N, 1, 2));
+        STIG_TRY(K[r].fetch(2, KRY_MAXV - 1, &hnext));
+        hnext = std::sqrt(hnext);
+        corrected = true;
+      }
+      double colnorm = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        const double hv = h[i] + h[KRY_MAXV + i];
+        Hr[(size_t)i * m + j] = hv;
+        colnorm += hv * hv;
+      }
+      if (!std::isfinite(hnext) || !std::isfinite(colnorm))
+        return fail(STIG_ENONFINITE, "non-finite value in the Arnoldi process");
+      for (int i = 0; i < j; ++i) {
+        const double a = Hr[(size_t)i * m + j], b = Hr[(size_t)(i + 1) * m + j];
+        Hr[(size_t)i * m + j] = cs[r][i] * a + sn[r][i] * b;
+        Hr[(size_t)(i + 1) * m + j] = -sn[r][i] * a + cs[r][i] * b;
+      }
+      const double a = Hr[(size_t)j * m + j], b = hnext;
+      const double rr = std::hypot(a, b);
+      cs[r][j] = rr == 0.0 ? 1.0 : a / rr;
+      sn[r][j] = rr == 0.0 ? 0.0 : b / rr;
+      Hr[(size_t)j * m + j] = rr;
+      g[r][j + 1] = -sn[r][j] * g[r][j];
+      g[r][j] = cs[r][j] * g[r][j];
+      kk[r] = j + 1;
+      infos[r].relres_est = std::fabs(g[r][j + 1]) / fnorm[r];
+      const bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
+      if (infos[r].relres_est <= rtol || breakdown || infos[r].iters >= maxit || j + 1 == m) {
+        active[r] = 0;
+        continue;
+      }
+      double *vn = V + (j + 1) * ld + r * N;
+      if (corrected) STIG_TRY(K[r].axpby(w + r * N, nullptr, vn, 1.0 / hnext, 0.0));
+      else STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(1), -1.0, w + r * N, 0, 0, vn,
+                                1.0 / hnext));
+    }
+    // frozen right-hand sides: zero basis vector for the next batched step
+    if (j + 1 < m)
+      for (int r = 0; r < nb; ++r)
+        if (!active[r])
+          HIP_TRY(hipMemsetAsync(V + (j + 1) * ld + r * N, 0, N * sizeof(double), p->stream));
+  }
+  // solutions and their true residuals (one batched product, one round trip)
+  for (int r = 0; r < nb; ++r) {
+    if (kk[r] == 0) continue;
+    std::vector<double> y(kk[r]);
+    for (int i = kk[r] - 1; i >= 0; --i) {
+      double sacc = g[r][i];
+      for (int c = i + 1; c < kk[r]; ++c) sacc -= H[r][(size_t)i * m + c] * y[c];
+      y[i] = sacc / H[r][(size_t)i * m + i];
+    }
+    double *stage = hs + r * S4 + 2 * KRY_MAXV;  // not touched again before the next round trip
+    std::copy(y.begin(), y.end(), stage);
+    HIP_TRY(hipMemcpyAsync(K[r].slot(3), stage, kk[r] * sizeof(double), hipMemcpyHostToDevice,
+                           p->stream));
+    if (unorm[r] == 0.0) STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, nullptr, 0, 0, u + r * N));
+    else STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, u + r * N, 0, 0));
+  }
+  STIG_TRY(run_matvec(p, u, tmp, nb, transpose));
+  for (int r = 0; r < nb; ++r)
+    if (kk[r] > 0) STIG_TRY(K[r].residual_async(f + r * N, tmp + r * N, V + r * N));
+  STIG_TRY(fetch_all(true));
+  for (int r = 0; r < nb; ++r) {
+    if (kk[r] == 0) continue;
+    const double bt = std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
+    if (!std::isfinite(bt)) return fail(STIG_ENONFINITE, "non-finite residual");
+    infos[r].relres_true = bt / fnorm[r];
+    done[r] = infos[r].relres_true <= rtol;
+  }
+  return STIG_OK;
 }
 
 }  // namespace
@@ -1767,16 +1969,56 @@ stig_status stig_gmres_solve(stig_plan *p, const double *f, double *u, int nrhs,
   auto t0 = std::chrono::steady_clock::now();
   stig_info worst{0, 0, 0.0, 0.0, 0.0};
   stig_status result = STIG_OK;
-  for (int r = 0; r < nrhs; ++r) {
-    stig_info one{0, 0, 0.0, 0.0, 0.0};
-    stig_status st = gmres_one(p, f + r * p->N, u + r * p->N, restart, rtol, maxit, flexible,
-                               transpose ? 1 : 0, prec, &one);
-    if (st < 0) return st;
-    if (st == STIG_NOT_CONVERGED) result = st;
+  auto merge = [&](const stig_info &one) {
     worst.iters = std::max(worst.iters, one.iters);
     worst.restarts = std::max(worst.restarts, one.restarts);
     worst.relres_true = std::max(worst.relres_true, one.relres_true);
     worst.relres_est = std::max(worst.relres_est, one.relres_est);
+  };
+  // Batches: the first restart cycle of up to nb right-hand sides in lockstep,
+  // nb chosen so that its bases, products and intermediates take at most half
+  // of the free device memory; right-hand sides it leaves above rtol continue
+  // one by one from their current iterate.
+  int nb = 1;
+  if (nrhs > 1) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const double per = (2.0 * restart + 8.0) * (double)p->N * sizeof(double);
+      nb = (int)std::max(1.0, std::min((double)nrhs, 0.5 * (double)free_b / per));
+    }
+    (void)hipGetLastError();
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += nb) {
+    const int cnt = std::min(nb, nrhs - r0);
+    std::vector<stig_info> first(cnt, stig_info{0, 0, 0.0, 0.0, 0.0});
+    std::vector<char> dn(cnt, 0);
+    if (cnt > 1) {
+      std::unique_ptr<bool[]> d(new bool[cnt]);
+      STIG_TRY(gmres_batch(p, f + r0 * p->N, u + r0 * p->N, cnt, restart, rtol, maxit,
+                           transpose ? 1 : 0, prec, first.data(), d.get()));
+      for (int i = 0; i < cnt; ++i) dn[i] = d[i];
+    }
+    for (int i = 0; i < cnt; ++i) {
+      const int r = r0 + i;
+      if (dn[i]) {
+        merge(first[i]);
+        continue;
+      }
+      const int used = first[i].iters;
+      if (cnt > 1 && used >= maxit) {  // budget spent in the batched cycle
+        result = STIG_NOT_CONVERGED;
+        merge(first[i]);
+        continue;
+      }
+      stig_info one{0, 0, 0.0, 0.0, 0.0};
+      stig_status st = gmres_one(p, f + r * p->N, u + r * p->N, restart, rtol, maxit - used,
+                                 flexible, transpose ? 1 : 0, prec, &one);
+      if (st < 0) return st;
+      if (st == STIG_NOT_CONVERGED) result = st;
+      one.iters += used;
+      if (cnt > 1 && used > 0) one.restarts += 1;
+      merge(one);
+    }
   }
   HIP_TRY(hipStreamSynchronize(p->stream));
   worst.t_solve_ms =
