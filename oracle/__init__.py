@@ -24,6 +24,9 @@ isogeometric Galerkin methods for parabolic problems", arXiv:1909.07309):
                   (Sections 4.2-4.4), as an independent cross-check of ``fd``.
 * ``annulus``   - quarter-annulus geometry, variable separable coefficients,
                   the geometry-aware preconditioner A-hat^G (Section 4.3).
+* ``annulus3d`` - the same on the quarter annulus extruded to 3D, with the
+                  3D separation of the coefficients (Section 4.3 in 3D).
+* ``convergence`` - errors of a manufactured solution (Section 5.1 rates).
 * ``adjoint``   - dense adjoint gradients of a quadratic loss.
 * ``problems``  - load vectors of the synthetic workloads.
 
