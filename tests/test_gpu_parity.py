@@ -148,6 +148,24 @@ def test_parity_split_products_match_oracle(n_el):
                     assert e <= 1.5 * dense + (1e-7 if prec == "fp32" else 1e-4), (prec, key, errs)
 
 
+@pytest.mark.parametrize("d,p,n_el", [(1, 1, 6), (1, 4, 9), (1, 5, 3), (2, 1, 5), (2, 3, 4),
+                                      (2, 5, 6), (3, 1, 4), (3, 2, 3), (3, 4, 5), (3, 5, 4)])
+def test_apply_and_matvec_every_dimension_and_degree(d, p, n_el):
+    """Every spatial dimension with low and high degrees (generic time kernel,
+    runtime-size mode kernels, every band width), gamma, nu and T != 1: the FP64
+    apply (plain and transposed) and the matvec against the oracle."""
+    base = {1: "square_p2_n8", 2: "square_p2_n8", 3: "cube_p3_n64"}[d]
+    w, fac, plan, pr = _setup(base, n_el, d=d, p=p, T=2.0, gamma=0.8, nu=1.7, source="smoothed_normal")
+    r = wl.random_tensor(w.shape, 41)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt, w.gamma, w.nu)
+    for transpose in (False, True):
+        s = plan.apply_Pinv(_dev(r), transpose=transpose).cpu().numpy()
+        assert _relmax(s, P.apply(r, transpose=transpose)) <= 1e-12, transpose
+        y = plan.matvec_A(_dev(r), transpose=transpose).cpu().numpy()
+        ref = fd.kron_matvec(r, pr.Wt, pr.Mt, pr.K1d, pr.M1d, w.gamma, w.nu, transpose=transpose)
+        assert _relmax(y, ref) <= 1e-13, transpose
+
+
 def test_apply_pinv_matches_dense_solve_tiny():
     w, fac, plan, pr = _setup("cube_p3_n64", 3)
     A = dense.kron_system(pr.Wt, pr.Mt, pr.K1d, pr.M1d)
