@@ -62,7 +62,8 @@ typedef enum { STIG_FP64 = 0, STIG_FP32 = 1, STIG_BF16 = 2 } stig_prec;
 typedef struct {
   int iters;            /* total inner (Arnoldi) iterations over all restarts */
   int restarts;         /* number of restart cycles started after the first */
-  double relres_true;   /* ||f - A u||_2 / ||f||_2 recomputed in FP64 at exit */
+  double relres_true;   /* ||f - A u||_2 / ||f||_2 at exit, in FP64 from products of A
+                           (see stig_gmres_solve), not from the GMRES estimate */
   double relres_est;    /* GMRES residual estimate at exit (relative) */
   double t_solve_ms;    /* wall time of the call (host clock, stream synchronised) */
 } stig_info;
@@ -271,7 +272,12 @@ stig_status stig_lift_adjoint(stig_plan *plan, const double *a_col,
  * P^{-1} (V y) and saves one apply per cycle.  A zero initial guess skips the
  * first product (r_0 = f).  Arnoldi with classical Gram-Schmidt and one
  * re-orthogonalisation, all in FP64 on the device; Givens rotations on the host.
- * u: device, in = initial guess, out = solution.  Stops when the FP64 true
+ * The true residual at the end of each restart cycle is r = r_0 - sum_i y_i (A z_i)
+ * with the products A z_i of that cycle kept as computed (one stored vector per
+ * iteration, m * N doubles) and r_0 the cycle's starting residual (f, or f - A u
+ * by a direct product for a nonzero initial guess): FP64 products of A, so the
+ * drift of the Hessenberg estimate does not enter it.
+ * u: device, in = initial guess, out = solution.  Stops when that FP64 true
  * relative residual ||f - A u|| / ||f|| <= rtol, or after maxit inner iterations
  * per right-hand side (then STIG_NOT_CONVERGED).  Right-hand sides are solved one
  * after another.  info (host, may be NULL) receives the worst case over the batch. */

@@ -123,7 +123,7 @@ struct stig_plan {
   const double *csr_val = nullptr;
   int64_t csr_nnz = 0;
   // scratch
-  DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, w, tmp, partial, small, flag, lift0, lift1;
+  DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, AZ, w, tmp, partial, small, flag, lift0, lift1;
   // pinned host staging of the small Krylov transfers: 4 coefficient slots of
   // KRY_MAXV doubles, then the breakdown flag
   double *pin = nullptr;
@@ -1080,14 +1080,6 @@ struct Krylov {
     STIG_TRY(run_matvec(p, u, tmp, 1, transpose));
     return residual(f, tmp, r, norm);
   }
-  // r = f - Ax, ||r||^2 into slot 3 entry KRY_MAXV-1 (no synchronisation)
-  stig_status residual_async(const double *f, const double *Ax, double *r) {
-    ProfScope ps(p, STIG_K_KRYLOV, 3.0 * p->N * 8);
-    hipLaunchKernelGGL(residual_norm, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, f, Ax, r,
-                       p->N, partial());
-    HIP_TRY(hipGetLastError());
-    return reduce(3);
-  }
   // ||x||^2, ||y||^2 into slot 3 entries 0 and KRY_MAXV-1 (no synchronisation)
   stig_status norms_async(const double *x, const double *y) {
     ProfScope ps(p, STIG_K_KRYLOV, 2.0 * p->N * 8);
@@ -1191,10 +1183,11 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   Krylov K{p};
   STIG_TRY(p->V.ensure((size_t)(m + 1) * N * sizeof(double)));
   STIG_TRY(p->Z.ensure((size_t)m * N * sizeof(double)));
+  STIG_TRY(p->AZ.ensure((size_t)m * N * sizeof(double)));
   STIG_TRY(p->w.ensure(N * sizeof(double)));
   STIG_TRY(p->tmp.ensure(N * sizeof(double)));
-  double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *w = p->w.as<double>(),
-         *tmp = p->tmp.as<double>();
+  double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *AZ = p->AZ.as<double>(),
+         *w = p->w.as<double>(), *tmp = p->tmp.as<double>();
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   STIG_TRY(ensure_pinned(p));
   double *hs = p->pin;
@@ -1234,16 +1227,16 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     int k = 0;
     for (int j = 0; j < m; ++j) {
       double *vj = V + (int64_t)j * N;
-      double *zj = Z + (int64_t)j * N;
+      double *zj = Z + (int64_t)j * N, *azj = AZ + (int64_t)j * N;
       STIG_TRY(apply_dispatch(p, vj, zj, 1, transpose, prec));
-      STIG_TRY(run_matvec(p, zj, w, 1, transpose));
+      STIG_TRY(run_matvec(p, zj, azj, 1, transpose));  // A z_j, kept for the cycle's residual
       // classical Gram-Schmidt with one re-orthogonalisation.  The second
       // correction w -= V h2 is deferred: with V orthonormal,
       // ||w - V h2||^2 = ||w||^2 - ||h2||^2, and the corrected vector is only
       // needed as the next basis vector, so the correction is fused with the
       // scaling into v_{j+1} (and skipped when the cycle ends here).
-      STIG_TRY(K.dots(V, j + 1, w, 0, 0));                  // h1 = V^T w
-      STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, w, 1, 1));  // w -= V h1; h2 = V^T w; ||w||^2
+      STIG_TRY(K.dots(V, j + 1, azj, 0, 0));  // h1 = V^T A z_j
+      STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, azj, 1, 1, w));  // w = A z_j - V h1; h2 = V^T w; ||w||^2
       // the two coefficient slots and the breakdown flag in one round trip
       HIP_TRY(hipMemcpyAsync(hs, K.slot(0), 2 * KRY_MAXV * sizeof(double),
                              hipMemcpyDeviceToHost, p->stream));
@@ -1305,15 +1298,25 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
       for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
       y[i] = s / H[(size_t)i * m + i];
     }
-    // (the pinned area is not touched again before the next synchronisation)
-    std::copy(y.begin(), y.begin() + k, hs + 2 * KRY_MAXV);
+    // y and y / beta to the device (the pinned area is not written again
+    // before the next synchronisation)
+    for (int i = 0; i < k; ++i) {
+      hs[2 * KRY_MAXV + i] = y[i];
+      hs[3 * KRY_MAXV + i] = y[i] / beta;
+    }
     HIP_TRY(hipMemcpyAsync(K.slot(3), hs + 2 * KRY_MAXV, k * sizeof(double),
+                           hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(K.slot(2), hs + 3 * KRY_MAXV, k * sizeof(double),
                            hipMemcpyHostToDevice, p->stream));
     // u += Z y (u = Z y while u is the zero initial guess)
     if (cycle == 1 && unorm == 0.0) STIG_TRY(K.update(Z, k, K.slot(3), 1.0, nullptr, 0, 0, u));
     else STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));
-    // true residual
-    STIG_TRY(K.residual_of(f, u, V, tmp, transpose, &beta));
+    // true residual from this cycle's products of A: r = r_0 - sum_i y_i A z_i
+    // = beta (v_0 - AZ y / beta), written over v_0, with its norm
+    STIG_TRY(K.update(AZ, k, K.slot(2), -1.0, V, 1, 3, V, beta));
+    double nsq;
+    STIG_TRY(K.fetch(3, KRY_MAXV - 1, &nsq));
+    beta *= std::sqrt(nsq);
     if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite residual");
     info->relres_true = beta / fnorm;
   }
@@ -1335,12 +1338,13 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   constexpr int S4 = 4 * KRY_MAXV;  // small-buffer doubles per right-hand side
   STIG_TRY(p->V.ensure((size_t)(m + 1) * ld * sizeof(double)));
   STIG_TRY(p->Z.ensure((size_t)m * ld * sizeof(double)));
+  STIG_TRY(p->AZ.ensure((size_t)m * ld * sizeof(double)));
   STIG_TRY(p->w.ensure((size_t)ld * sizeof(double)));
   STIG_TRY(p->tmp.ensure((size_t)ld * sizeof(double)));
   STIG_TRY(p->small.ensure((size_t)nb * S4 * sizeof(double)));
   STIG_TRY(ensure_pinned(p, (size_t)nb * S4 + 1));
-  double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *w = p->w.as<double>(),
-         *tmp = p->tmp.as<double>(), *hs = p->pin;
+  double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *AZ = p->AZ.as<double>(),
+         *w = p->w.as<double>(), *tmp = p->tmp.as<double>(), *hs = p->pin;
   std::vector<Krylov> K;
   for (int r = 0; r < nb; ++r) K.push_back(Krylov{p, ld, (int64_t)r * S4});
   auto fetch_all = [&](bool with_flag) -> stig_status {
@@ -1404,11 +1408,12 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   };
   for (int j = 0; j < m && any_active(); ++j) {
     STIG_TRY(apply_dispatch(p, V + j * ld, Z + j * ld, nb, transpose, prec));
-    STIG_TRY(run_matvec(p, Z + j * ld, w, nb, transpose));
+    STIG_TRY(run_matvec(p, Z + j * ld, AZ + j * ld, nb, transpose));
     for (int r = 0; r < nb; ++r) {
       if (!active[r]) continue;
-      STIG_TRY(K[r].dots(V + r * N, j + 1, w + r * N, 0, 0));
-      STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(0), -1.0, w + r * N, 1, 1));
+      double *az = AZ + j * ld + r * N;
+      STIG_TRY(K[r].dots(V + r * N, j + 1, az, 0, 0));
+      STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(0), -1.0, az, 1, 1, w + r * N));
     }
     STIG_TRY(fetch_all(true));
     for (int r = 0; r < nb; ++r) {
@@ -1476,20 +1481,26 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
       for (int c = i + 1; c < kk[r]; ++c) sacc -= H[r][(size_t)i * m + c] * y[c];
       y[i] = sacc / H[r][(size_t)i * m + i];
     }
-    double *stage = hs + r * S4 + 2 * KRY_MAXV;  // not touched again before the next round trip
-    std::copy(y.begin(), y.end(), stage);
+    // y and y / beta (staging not written again before the next round trip)
+    double *stage = hs + r * S4 + 2 * KRY_MAXV;
+    for (int i = 0; i < kk[r]; ++i) {
+      stage[i] = y[i];
+      stage[KRY_MAXV + i] = y[i] / beta[r];
+    }
     HIP_TRY(hipMemcpyAsync(K[r].slot(3), stage, kk[r] * sizeof(double), hipMemcpyHostToDevice,
                            p->stream));
+    HIP_TRY(hipMemcpyAsync(K[r].slot(2), stage + KRY_MAXV, kk[r] * sizeof(double),
+                           hipMemcpyHostToDevice, p->stream));
     if (unorm[r] == 0.0) STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, nullptr, 0, 0, u + r * N));
     else STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, u + r * N, 0, 0));
+    // r = r_0 - sum_i y_i A z_i = beta (v_0 - AZ y / beta) over v_0, with its norm
+    STIG_TRY(K[r].update(AZ + r * N, kk[r], K[r].slot(2), -1.0, V + r * N, 1, 3, V + r * N,
+                         beta[r]));
   }
-  STIG_TRY(run_matvec(p, u, tmp, nb, transpose));
-  for (int r = 0; r < nb; ++r)
-    if (kk[r] > 0) STIG_TRY(K[r].residual_async(f + r * N, tmp + r * N, V + r * N));
   STIG_TRY(fetch_all(true));
   for (int r = 0; r < nb; ++r) {
     if (kk[r] == 0) continue;
-    const double bt = std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
+    const double bt = beta[r] * std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
     if (!std::isfinite(bt)) return fail(STIG_ENONFINITE, "non-finite residual");
     infos[r].relres_true = bt / fnorm[r];
     done[r] = infos[r].relres_true <= rtol;
@@ -1976,15 +1987,15 @@ stig_status stig_gmres_solve(stig_plan *p, const double *f, double *u, int nrhs,
     worst.relres_est = std::max(worst.relres_est, one.relres_est);
   };
   // Batches: the first restart cycle of up to nb right-hand sides in lockstep,
-  // nb chosen so that its bases, products and intermediates take at most half
+  // nb chosen so that its bases, products and intermediates take at most 60 %
   // of the free device memory; right-hand sides it leaves above rtol continue
   // one by one from their current iterate.
   int nb = 1;
   if (nrhs > 1) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-      const double per = (2.0 * restart + 8.0) * (double)p->N * sizeof(double);
-      nb = (int)std::max(1.0, std::min((double)nrhs, 0.5 * (double)free_b / per));
+      const double per = (3.0 * restart + 8.0) * (double)p->N * sizeof(double);
+      nb = (int)std::max(1.0, std::min((double)nrhs, 0.6 * (double)free_b / per));
     }
     (void)hipGetLastError();
   }
