@@ -179,27 +179,31 @@ __global__ void time_outer2(const double *__restrict__ a, const double *__restri
   for (int t = 0; t < nt; ++t) o[(int64_t)t * ns] = wa[t] * av + wb[t] * bv;
 }
 
-// Entries of A = W (x) M_s + Mt (x) K_s as CSR, one thread per row (t, s):
-// for each time neighbour t' in the band and each entry (s, s') of the spatial
-// pattern, column t' * ns + s' and value W[t][t'] M_s[s][s'] + Mt[t][t'] K_s[s][s'].
-// Time bands as rows of 2P+1 coefficients (zero outside the matrix).
+// Space-time CSR of W (x) M_s + M_t (x) K_s from the spatial CSR (rp2, col2,
+// m2, k2) and the time bands (wb, mb: rows of 2P+1, entry P + d at column
+// t + d).  Row r = t ns + s holds, for each time neighbour tp = t-P .. t+P in
+// range (ascending), the spatial row s shifted by tp ns.  One wavefront per
+// row: its lanes write consecutive entries.
 __global__ void kron_csr_fill(const int64_t *__restrict__ rowptr, int32_t *__restrict__ col,
                               double *__restrict__ val, const int64_t *__restrict__ rp2,
                               const int32_t *__restrict__ col2, const double *__restrict__ m2,
                               const double *__restrict__ k2, const double *__restrict__ wb,
                               const double *__restrict__ mb, int P, int nt, int64_t ns) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= ns * nt) return;
-  int64_t t = r / ns, s = r - t * ns;
-  int64_t k = rowptr[r];
+  const int lane = threadIdx.x & 63;
+  const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int B = 2 * P + 1;
-  for (int64_t tp = t - P; tp <= t + P; ++tp) {
-    if (tp < 0 || tp >= nt) continue;
-    double wv = wb[t * B + (tp - t) + P], mv = mb[t * B + (tp - t) + P];
-    for (int64_t e = rp2[s]; e < rp2[s + 1]; ++e) {
-      col[k] = (int32_t)(tp * ns + col2[e]);
-      val[k] = wv * m2[e] + mv * k2[e];
-      ++k;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < ns * nt;
+       r += wstride) {
+    const int64_t t = r / ns, s = r - t * ns;
+    const int64_t e0 = rp2[s], L = rp2[s + 1] - e0;
+    const int64_t tlo = t - P < 0 ? 0 : t - P, thi = t + P < nt ? t + P : nt - 1;
+    int64_t k = rowptr[r];
+    for (int64_t tp = tlo; tp <= thi; ++tp, k += L) {
+      const double wv = wb[t * B + (tp - t) + P], mv = mb[t * B + (tp - t) + P];
+      for (int64_t e = lane; e < L; e += 64) {
+        col[k + e] = (int32_t)(tp * ns + col2[e0 + e]);
+        val[k + e] = wv * m2[e0 + e] + mv * k2[e0 + e];
+      }
     }
   }
 }

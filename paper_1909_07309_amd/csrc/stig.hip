@@ -1858,7 +1858,7 @@ stig_status stig_kron_csr_fill(stig_plan *p, const int64_t *rowptr, int32_t *col
   DevBuf dw, dm;
   STIG_TRY(upload(dw, wb, p->stream));
   STIG_TRY(upload(dm, mb, p->stream));
-  hipLaunchKernelGGL(kron_csr_fill, dim3(grid_for(p->N, 256)), dim3(256), 0, p->stream, rowptr,
+  hipLaunchKernelGGL(kron_csr_fill, dim3(grid_for(p->N * 64, 256)), dim3(256), 0, p->stream, rowptr,
                      col, val, rowptr2d, col2d, valM2d, valK2d, dw.as<double>(), dm.as<double>(),
                      p->pt, p->nt, p->Ns);
   HIP_TRY(hipGetLastError());
