@@ -105,7 +105,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-annulus", action="store_true",
-                    help="skip the 2D and 3D annulus solves (variable coefficients, CSR matvec)")
+                    help="skip the 2D and 3D annulus solves (variable coefficients; CSR and "
+                         "factored matvec)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the batched forward + adjoint solve (32 right-hand sides)")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -282,66 +283,78 @@ def main():
             solves[prec] = rec
             log(f"[bench] solve {prec}: {rec}")
 
-    # ---- annulus (space-time CSR matvec, A-hat^G != A): FGMRES(30) to 1e-8 with
-    # the FP64 and with the FP32 geometry-aware FD preconditioner
-    annulus = {}
-    if not args.no_solve and not args.no_annulus:
-        from paper_1909_07309_amd.annulus import AnnulusSetup
-        wa = wl.WORKLOADS["annulus_p4_n128"]
-        asu = AnnulusSetup(wa)
-        pa = asu.make_plan()
-        fa = asu.source()
-        for prec in ("fp64", "fp32"):
-            pa.gmres_solve(fa, torch.zeros_like(fa), restart=30, rtol=1e-8, maxit=300,
-                           flexible=True, prec=prec)  # warm (allocations)
-            ua = torch.zeros_like(fa)
-            torch.cuda.synchronize()
+    # ---- annulus (2D) and extruded annulus (3D): A-hat^G != A, FGMRES(30) to 1e-8
+    # with the FP64 and with the FP32 geometry-aware FD preconditioner, for both
+    # forms of A x: the whole space-time matrix as a CSR ("csr") and only the
+    # sparse spatial factors and the time bands ("factored", Section 4.5)
+    def annulus_runs(setup, w, timed_apply):
+        out = {"N": w.N}
+        for form in ("csr", "factored"):
             t0 = time.perf_counter()
-            ua, info = pa.gmres_solve(fa, ua, restart=30, rtol=1e-8, maxit=300, flexible=True,
-                                      prec=prec)
+            pl = setup.make_plan(matvec=form)
             torch.cuda.synchronize()
-            annulus[prec] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
-                             "relres_true": info["relres_true"], "method": "FGMRES(30)"}
-            log(f"[bench] annulus solve {prec}: {annulus[prec]}")
-        annulus["N"] = wa.N
-        del pa, asu
-
-    # ---- extruded annulus in 3D (A-hat^G with the 3D separation, CSR matvec):
-    # FGMRES(30) to 1e-8 with the FP64 and with the FP32 preconditioner
-    annulus3d = {}
-    if not args.no_solve and not args.no_annulus:
-        from paper_1909_07309_amd.annulus3d import Annulus3DSetup
-        w3 = wl.WORKLOADS["annulus3d_p2_n32"]
-        t0 = time.perf_counter()
-        a3 = Annulus3DSetup(w3)
-        p3 = a3.make_plan()
-        torch.cuda.synchronize()
-        annulus3d["setup_ms"] = (time.perf_counter() - t0) * 1e3
-        f3 = a3.source()
-        s3 = torch.empty_like(f3)
-        for prec in ("fp64", "fp32"):
-            for _ in range(3):
-                p3.apply_Pinv(f3, s3, prec=prec)
+            rec = {"setup_ms": (time.perf_counter() - t0) * 1e3,
+                   "plan_device_GB": pl.device_bytes() / 1e9}
+            if form == "csr":
+                rec["plan_device_GB"] += sum(t.numel() * t.element_size()
+                                             for t in pl._keep["csr"]) / 1e9
+            f = setup.source()
+            y = torch.empty_like(f)
+            for _ in range(2):
+                pl.matvec_A(f, y)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(10):
-                p3.apply_Pinv(f3, s3, prec=prec)
+                pl.matvec_A(f, y)
             torch.cuda.synchronize()
-            apply_ms = (time.perf_counter() - t0) / 10 * 1e3
-            p3.gmres_solve(f3, torch.zeros_like(f3), restart=30, rtol=1e-8, maxit=300,
-                           flexible=True, prec=prec)  # warm (allocations)
-            u3 = torch.zeros_like(f3)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            u3, info = p3.gmres_solve(f3, u3, restart=30, rtol=1e-8, maxit=300, flexible=True,
-                                      prec=prec)
-            torch.cuda.synchronize()
-            annulus3d[prec] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
-                               "relres_true": info["relres_true"], "apply_ms": apply_ms,
-                               "method": "FGMRES(30)"}
-            log(f"[bench] annulus3d solve {prec}: {annulus3d[prec]}")
-        annulus3d["N"] = w3.N
-        del p3, a3
+            rec["matvec_ms"] = (time.perf_counter() - t0) / 10 * 1e3
+            for prec in ("fp64", "fp32"):
+                r = {}
+                if timed_apply:
+                    s_ = torch.empty_like(f)
+                    for _ in range(3):
+                        pl.apply_Pinv(f, s_, prec=prec)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(10):
+                        pl.apply_Pinv(f, s_, prec=prec)
+                    torch.cuda.synchronize()
+                    r["apply_ms"] = (time.perf_counter() - t0) / 10 * 1e3
+                pl.gmres_solve(f, torch.zeros_like(f), restart=30, rtol=1e-8, maxit=300,
+                               flexible=True, prec=prec)  # warm (allocations)
+                u = torch.zeros_like(f)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u, info = pl.gmres_solve(f, u, restart=30, rtol=1e-8, maxit=300, flexible=True,
+                                         prec=prec)
+                torch.cuda.synchronize()
+                r.update({"ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
+                          "relres_true": info["relres_true"], "method": "FGMRES(30)"})
+                rec[prec] = r
+            out[form] = rec
+            log(f"[bench] {w.name} {form}: {rec}")
+            del pl, f, y
+            torch.cuda.empty_cache()
+        return out
+
+    annulus, annulus3d = {}, {}
+    if not args.no_solve and not args.no_annulus:
+        from paper_1909_07309_amd.annulus import AnnulusSetup
+        from paper_1909_07309_amd.annulus3d import Annulus3DSetup
+        wa = wl.WORKLOADS["annulus_p4_n128"]
+        t0 = time.perf_counter()
+        a2 = AnnulusSetup(wa)
+        host_ms = (time.perf_counter() - t0) * 1e3
+        annulus = annulus_runs(a2, wa, False)
+        annulus["host_setup_ms"] = host_ms
+        del a2
+        w3 = wl.WORKLOADS["annulus3d_p2_n32"]
+        t0 = time.perf_counter()
+        a3 = Annulus3DSetup(w3)
+        host_ms = (time.perf_counter() - t0) * 1e3
+        annulus3d = annulus_runs(a3, w3, True)
+        annulus3d["host_setup_ms"] = host_ms
+        del a3
 
     # ---- batched forward + adjoint solve (p=3, 48 elements, 32 right-hand sides):
     # u = A^{-1}(f - A_I0 c0), loss 0.5 ||u - u*||^2, gradients w.r.t. f and c0

@@ -119,8 +119,9 @@ stig_status stig_set_option(stig_plan *plan, int option, int value);
  * The library solves K_l U_l = M_l U_l Lambda_l with U_l^T M_l U_l = I
  * (eq. space_eig) by Cholesky + cyclic Jacobi on the host, uploads U_l, U_l^T,
  * Lambda_l (and FP32/BF16 copies), and the band coefficients of W_t, W_t^T, M_t.
- * The same factors define the matrix-free matvec of stig_matvec_A unless
- * stig_set_A_csr is called.  Entries outside the bandwidth p_s / p_t must be 0
+ * The same factors define the matrix-free matvec of stig_matvec_A (the time
+ * factors always; the spatial ones unless stig_set_spatial_factors or
+ * stig_set_A_csr is called).  Entries outside the bandwidth p_s / p_t must be 0
  * (else STIG_EINVAL).  May be called again to replace the factors. */
 stig_status stig_setup_1d_pencils(stig_plan *plan, const double *const *K1d,
                                   const double *const *M1d, const double *Wt,
@@ -142,6 +143,25 @@ stig_status stig_set_diag_scaling(stig_plan *plan, const double *D);
  * the CSR form (STIG_EINVAL). */
 stig_status stig_set_A_csr(stig_plan *plan, const int64_t *rowptr,
                            const int32_t *col, const double *val, int64_t nnz);
+
+/* Optional: the matvec of Section 4.5 with sparse spatial factors.  Only the
+ * factors of A are stored, not A itself:
+ *   A = gamma W_t (x) M_s + nu M_t (x) K_s,
+ * with the plan's time factors and general sparse N_s x N_s spatial matrices
+ * M_s, K_s (the variable-coefficient and geometry case of Section 4.3.1, whose
+ * spatial matrices are not Kronecker products).  Host CSR with one pattern for
+ * both: rowptr (N_s + 1 int64, rowptr[0] = 0, non-decreasing), col (int32 in
+ * [0, N_s), any order within a row), valM, valK (FP64), spatial unknown order
+ * [x_d]..[x_1].  The library keeps its own device copies of M_s, K_s and of
+ * their transposes in a padded column-major layout: 2 x width x N_s x 20 bytes,
+ * width = the longest row (or column).  stig_matvec_A then runs one sparse
+ * spatial pass per time level and one banded pass along t; transposed products
+ * are supported.  Synchronises.  rowptr = NULL removes the factors.  Setting
+ * the factors clears a matrix given to stig_set_A_csr, and setting that matrix
+ * clears the factors.  STIG_EINVAL if rowptr or col are out of range (nothing
+ * changed). */
+stig_status stig_set_spatial_factors(stig_plan *plan, const int64_t *rowptr, const int32_t *col,
+                                     const double *valM, const double *valK);
 
 /* Optional: the geometry-aware scaling of eq. prec_geo computed by the library
  * when the true system has the same time factors as the plan and spatial
@@ -229,7 +249,8 @@ stig_status stig_apply_Pinv(stig_plan *plan, const double *r, double *s,
 
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1), FP64, eq. syst_mat:
  * A = gamma W_t (x) M_s + nu M_t (x) K_s, computed matrix-free by banded mode
- * products (Section 4.5), or with the CSR matrix of stig_set_A_csr.
+ * products (Section 4.5), with the sparse spatial factors of
+ * stig_set_spatial_factors, or with the CSR matrix of stig_set_A_csr.
  * x, y: device, nrhs * N doubles, not overlapping. */
 stig_status stig_matvec_A(stig_plan *plan, const double *x, double *y, int nrhs,
                           int transpose);
@@ -293,7 +314,7 @@ enum {
   STIG_K_TIME_SOLVE = 1,  /* banded shifted time solves */
   STIG_K_BAND_PASS = 2,   /* banded mode products of the matvec / mass apply */
   STIG_K_KRYLOV = 3,      /* Arnoldi dot products and updates */
-  STIG_K_CSR = 4,         /* CSR matvec */
+  STIG_K_CSR = 4,         /* CSR matvec, sparse spatial factor pass */
   STIG_K_PLANE_GEMM = 5,  /* fused mode-1/mode-2 MFMA products of the FD apply */
   STIG_NUM_KERNEL_KINDS = 6
 };

@@ -40,6 +40,7 @@ SIGNATURES = {
                                         C.c_double, C.c_double]),
     "stig_set_diag_scaling": (C.c_int, [_vp, _vp]),
     "stig_set_A_csr": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64]),
+    "stig_set_spatial_factors": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "stig_apply_Pinv": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int]),
     "stig_matvec_A": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int]),
     "stig_apply_mass": (C.c_int, [_vp, _vp, _vp, C.c_int]),

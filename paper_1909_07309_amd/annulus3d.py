@@ -73,14 +73,20 @@ class Annulus3DSetup:
         self.Mtl = [assemble_1d(n_el, p, "mass", weight=ph[elem], nq=nq)[1:-1, 1:-1].copy()
                     for ph in (phi1, phi2, phi3)]
 
-    def make_plan(self, with_csr=True, device="cuda"):
+    def make_plan(self, matvec="csr", device="cuda"):
+        """matvec: "csr" (the whole space-time matrix on the device), "factored" (only the
+        sparse spatial factors, Section 4.5) or None (the plan's Kronecker factors)."""
         w = self.w
         plan = Plan([w.n_s] * 3, w.n_t, w.p, w.p)
         plan.setup_1d_pencils(self.Kt, self.Mtl, self.Wt, self.Mt, 1.0, 1.0)
         plan.set_diag_scaling_kron(self.dMs, self.dKs)
-        if with_csr:
+        if matvec == "csr":
             rowptr, col, val = plan.kron_csr(self.space, self.Wt, self.Mt, device)
             plan.set_A_csr(rowptr, col, val)
+        elif matvec == "factored":
+            plan.set_spatial_factors(self.space)
+        else:
+            assert matvec is None, matvec
         return plan
 
     def source(self, device="cuda", seed=0):

@@ -102,6 +102,24 @@ class Plan:
                                    C.c_void_p(col.data_ptr()), C.c_void_p(val.data_ptr()),
                                    int(val.numel())))
 
+    def set_spatial_factors(self, space_csr):
+        """Matvec with sparse spatial factors: A = gamma W_t (x) M_s + nu M_t (x) K_s from a
+        host spatial CSR (rowptr, col, valK, valM), as `assemble_2d` / `assemble_3d` return
+        it; None removes them."""
+        self._sync_stream()
+        if space_csr is None:
+            check(lib().stig_set_spatial_factors(self._h, None, None, None, None))
+            return
+        rp, col, vK, vM = space_csr
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        vK = np.ascontiguousarray(vK, dtype=np.float64)
+        vM = np.ascontiguousarray(vM, dtype=np.float64)
+        assert rp.size == self.N_s + 1 and col.size == vK.size == vM.size == int(rp[-1])
+        check(lib().stig_set_spatial_factors(self._h, rp.ctypes.data_as(C.c_void_p),
+                                             col.ctypes.data_as(C.c_void_p), dptr(vM), dptr(vK)))
+        self._keep.pop("csr", None)
+
     def apply_Pinv(self, r, s=None, transpose=False, prec="fp64"):
         nrhs = self._nrhs(r)
         if s is None:

@@ -384,6 +384,45 @@ int64_t assemble_3d(int n_el, int p, int nq, const double *c11, const double *c2
   return rowptr[Ns];
 }
 
+int spatial_ell(int64_t n, const int64_t *rowptr, const int32_t *col, const double *valM,
+                const double *valK, bool transpose, int align, std::vector<int32_t> *ce,
+                std::vector<double> *me, std::vector<double> *ke) {
+  if (rowptr[0] != 0) return -1;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return -1;
+  const int64_t nnz = rowptr[n];
+  for (int64_t e = 0; e < nnz; ++e)
+    if (col[e] < 0 || col[e] >= n) return -1;
+  // row lengths of the stored matrix (of the transpose: column counts)
+  std::vector<int64_t> len(n, 0);
+  if (transpose) {
+    for (int64_t e = 0; e < nnz; ++e) ++len[col[e]];
+  } else {
+    for (int64_t i = 0; i < n; ++i) len[i] = rowptr[i + 1] - rowptr[i];
+  }
+  int64_t width = 0;
+  for (int64_t i = 0; i < n; ++i) width = std::max(width, len[i]);
+  align = std::max(align, 1);
+  width = (std::max<int64_t>(width, 1) + align - 1) / align * align;
+  if (!ce) return (int)width;
+  ce->assign((size_t)(width * n), 0);
+  me->assign((size_t)(width * n), 0.0);
+  ke->assign((size_t)(width * n), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = 0; k < width; ++k) (*ce)[(size_t)(k * n + i)] = (int32_t)i;
+  std::vector<int64_t> fill(n, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      // stored entry (i, j): (r, col) or, for the transpose, (col, r)
+      const int64_t i = transpose ? col[e] : r, j = transpose ? r : col[e];
+      const size_t slot = (size_t)(fill[i]++ * n + i);
+      (*ce)[slot] = (int32_t)j;
+      (*me)[slot] = valM[e];
+      (*ke)[slot] = valK[e];
+    }
+  return (int)width;
+}
+
 void separate_3d(int n1, int n2, int n3, const double *C11, const double *C22, const double *C33,
                  const double *C00, double *phi1, double *phi2, double *phi3, double *Phi1,
                  double *Phi2, double *Phi3) {

@@ -289,11 +289,15 @@ constexpr int GEMM2_THREADS = 256;
 // NC = n as a compile-time constant (0: n taken from the argument).  With NC
 // fixed, the MFMA chain has no runtime guards, so the accumulators stay in
 // place instead of being copied at every branch.
+// in_scale / out_scale (optional, length nscale, index taken modulo nscale):
+// per-entry factors multiplied in on load / on store; a column's entries lie in
+// one period of nscale, so the modulo is taken once per column.
 template <typename Tin, typename Tout, typename TC, int NC>
 __global__ void __launch_bounds__(GEMM2_THREADS)
 mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
                 const typename Mfma<TC>::elem *__restrict__ Op, int n_arg, int64_t inner,
-                int64_t total_cols) {
+                int64_t total_cols, const double *__restrict__ in_scale,
+                const double *__restrict__ out_scale, int64_t nscale) {
   typedef Mfma<TC> MF;
   typedef typename MF::elem E;
   constexpr int NMAX = NC ? NC : GEMM2_MAX_N;
@@ -308,11 +312,25 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   const int ld = lds_ld<TC>(NMAX);
   E *opl = reinterpret_cast<E *>(smem);  // [NROWS][ld]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < NROWS * KPADM; e += GEMM2_THREADS) {
-    int j = e / KPADM, k = e - j * KPADM;
-    bool ok = j < n && k < n;
-    E v = Op[ok ? (size_t)j * n + k : 0];
-    opl[(size_t)j * ld + k] = ok ? v : MF::zero();
+  // FU loads in flight per thread: when a block multiplies only a few strips,
+  // this copy would otherwise be a chain of dependent L2 round trips
+  constexpr int FILL = NROWS * KPADM, FU = 8;
+  for (int e0 = tid; e0 < FILL; e0 += GEMM2_THREADS * FU) {
+    E v[FU];
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int e = e0 + u * GEMM2_THREADS;
+      const int j = e / KPADM, k = e - j * KPADM;
+      const bool ok = e < FILL && j < n && k < n;
+      v[u] = Op[ok ? (size_t)j * n + k : 0];
+      if (!ok) v[u] = MF::zero();
+    }
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int e = e0 + u * GEMM2_THREADS;
+      const int j = e / KPADM, k = e - j * KPADM;
+      if (e < FILL) opl[(size_t)j * ld + k] = v[u];
+    }
   }
   __syncthreads();
 
@@ -338,6 +356,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     const bool cvalid = strip < nstrips && c < total_cols;
     int64_t base, step;
     locate(cvalid ? c : 0, base, step);
+    const int64_t sb = in_scale ? base % nscale : 0;
 #pragma unroll
     for (int s = 0; s < KSMAX; ++s)
 #pragma unroll
@@ -346,6 +365,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
         bool ok = cvalid && k < n;
         int64_t a = ok ? base + (int64_t)k * step : 0;
         double x = Conv<Tin>::to_f64(in[a]);
+        if (in_scale) x *= in_scale[ok ? sb + (int64_t)k * step : 0];
         bv[s][u] = ok ? MF::from_f64(x) : MF::zero();
       }
   };
@@ -357,6 +377,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     const bool cvalid = c < total_cols;
     int64_t base, step;
     locate(cvalid ? c : 0, base, step);
+    const int64_t sb = out_scale ? base % nscale : 0;
     typename MF::acc acc[QMAX];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
@@ -387,7 +408,11 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           int j = 16 * t + MF::out_row(kg, v);
-          if (j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64((double)acc[t][v]);
+          if (j < n) {
+            double y = (double)acc[t][v];
+            if (out_scale) y *= out_scale[sb + (int64_t)j * step];
+            out[base + (int64_t)j * step] = Conv<Tout>::from_f64(y);
+          }
         }
     }
     // fringe rows on the vector ALU from the B registers
@@ -402,7 +427,10 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
           sum += MF::to_f64(orow[s * MF::KSTEP + u]) * MF::to_f64(bv[s][u]);
       sum += __shfl_xor(sum, 16, 64);
       sum += __shfl_xor(sum, 32, 64);
-      if (kg == 0 && cvalid && jr < n) out[base + (int64_t)jr * step] = Conv<Tout>::from_f64(sum);
+      if (kg == 0 && cvalid && jr < n) {
+        if (out_scale) sum *= out_scale[sb + (int64_t)jr * step];
+        out[base + (int64_t)jr * step] = Conv<Tout>::from_f64(sum);
+      }
     }
   };
   // one strip in flight per wave while the current one is multiplied

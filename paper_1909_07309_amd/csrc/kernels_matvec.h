@@ -19,29 +19,32 @@
 
 namespace stig {
 
-// Axis with inner stride > 1: one thread per column (o, i), sliding a register
-// window of 2P+1 entries along the axis, so each input entry is read once and
-// loads are coalesced across i.
+// Axis with inner stride > 1: one thread per column (o, i) and chunk of jc
+// entries along the axis (blockIdx.y), sliding a register window of 2P+1
+// entries, so each input entry is read once per chunk (plus a 2P halo) and
+// loads are coalesced across i.  Chunks only split the axis when there are too
+// few columns to fill the device.
 template <int P>
 __global__ void band_pass_strided(const double *__restrict__ in1, const double *__restrict__ in2,
                                   double *__restrict__ out1, double *__restrict__ out2,
                                   const double *__restrict__ Ba, const double *__restrict__ Bb,
                                   const double *__restrict__ Bc, int n, int64_t inner,
-                                  int64_t total_cols) {
+                                  int64_t total_cols, int jc) {
   constexpr int B = 2 * P + 1;
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= total_cols) return;
+  const int j0 = (int)blockIdx.y * jc, j1 = j0 + jc < n ? j0 + jc : n;
+  if (c >= total_cols || j0 >= n) return;
   int64_t o = c / inner, i = c - o * inner;
   int64_t base = o * (int64_t)n * inner + i;
   double w1[B], w2[B];
 #pragma unroll
   for (int m = 0; m < B; ++m) {
-    int j = m - P;  // window holds entries j-P .. j+P for j = 0
+    int j = j0 + m - P;  // window holds entries j-P .. j+P for j = j0
     w1[m] = (j >= 0 && j < n) ? in1[base + (int64_t)j * inner] : 0.0;
     w2[m] = (in2 && j >= 0 && j < n) ? in2[base + (int64_t)j * inner] : 0.0;
   }
   cptr<double> cBa = as_const(Ba), cBb = as_const(Bb), cBc = as_const(Bc);
-  for (int j = 0; j < n; ++j) {
+  for (int j = j0; j < j1; ++j) {
     cptr<double> ra = cBa + (size_t)j * B;
     cptr<double> rb = cBb + (size_t)j * B;
     cptr<double> rc = cBc + (size_t)j * B;
@@ -74,18 +77,20 @@ __global__ void band_pass_strided(const double *__restrict__ in1, const double *
 }
 
 // The last pass of the matvec fused with the residual: for each spatial
-// column (stride inner along t), r = f - (sum_m Bb[j][m] b[j+m-P] + Bc[j][m]
-// a[j+m-P]) and this block's share of r . r in partial[blockIdx.x] (fixed-order
-// block reduction).
+// column (stride inner along t) and chunk of jc time levels (blockIdx.y),
+// r = f - (sum_m Bb[j][m] b[j+m-P] + Bc[j][m] a[j+m-P]) and this block's share
+// of r . r in partial[blockIdx.y * gridDim.x + blockIdx.x] (fixed-order block
+// reduction).
 template <int P>
 __global__ void __launch_bounds__(256)
 time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
                    const double *__restrict__ f, double *__restrict__ r,
                    const double *__restrict__ Bb, const double *__restrict__ Bc, int n,
-                   int64_t inner, int64_t total_cols, double *__restrict__ partial) {
+                   int64_t inner, int64_t total_cols, int jc, double *__restrict__ partial) {
   constexpr int B = 2 * P + 1;
   __shared__ double red[4];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = (int)blockIdx.y * jc, j1 = j0 + jc < n ? j0 + jc : n;
   double acc = 0.0;
   if (c < total_cols) {
     const int64_t o = c / inner, i = c - o * inner;
@@ -93,12 +98,12 @@ time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
     double wa[B], wb[B];
 #pragma unroll
     for (int m = 0; m < B; ++m) {
-      const int j = m - P;
+      const int j = j0 + m - P;
       wa[m] = (j >= 0 && j < n) ? a[base + (int64_t)j * inner] : 0.0;
       wb[m] = (j >= 0 && j < n) ? b[base + (int64_t)j * inner] : 0.0;
     }
     cptr<double> cBb = as_const(Bb), cBc = as_const(Bc);
-    for (int j = 0; j < n; ++j) {
+    for (int j = j0; j < j1; ++j) {
       cptr<double> rb = cBb + (size_t)j * B;
       cptr<double> rc = cBc + (size_t)j * B;
       const int64_t e = base + (int64_t)j * inner;
@@ -122,7 +127,8 @@ time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0)
+    partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Contiguous axis (inner == 1): one thread per output entry; the 2P+1 reads
@@ -223,6 +229,94 @@ __global__ void csr_spmv(const int64_t *__restrict__ rowptr, const int32_t *__re
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) y[row] = s;
+  }
+}
+
+// Spatial part of the matvec with general sparse spatial factors (Section 4.5:
+// only the spatial and time factors of A are stored): for every slice s of
+// ns entries (one time level of one right-hand side),
+//     a[s][i] = sum_k Me[k][i] x[s][ce[k][i]],   b[s][i] = sum_k Ke[k][i] x[s][ce[k][i]].
+// M_s and K_s share one pattern, stored padded and column-major: entry k of
+// row i at k * ns + i (padding: column i, value 0), with the width a multiple
+// of KU, so the loads of a wavefront's rows are coalesced.  A thread owns row i
+// for TT consecutive slices: each matrix entry is loaded once per TT slices,
+// and neighbouring rows read neighbouring columns of x.  The entries are taken
+// KU at a time, the next group's loaded while the current group's KU x TT
+// gathers of x are in flight.  Blocks are numbered so that the slice chunks of
+// one row block run on one XCD (blocks are dispatched round-robin over the 8
+// XCDs): its rows' matrix entries come from HBM once into that XCD's L2.
+constexpr int ELL_KU = 2;  // the padded width is a multiple of this
+
+template <int TT, int KU>
+__global__ void __launch_bounds__(256)
+spatial_ell_pair(const double *__restrict__ x, double *__restrict__ a, double *__restrict__ b,
+                 const int32_t *__restrict__ ce, const double *__restrict__ me,
+                 const double *__restrict__ ke, int width, int64_t ns, int64_t nslices,
+                 int nchunks) {
+  const unsigned nb = gridDim.x, q = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8;
+  const unsigned g = xcd * q + (xcd < rem ? xcd : rem) + blockIdx.x / 8;
+  const int64_t i = (int64_t)(g / nchunks) * blockDim.x + threadIdx.x;
+  const int64_t s0 = (int64_t)(g % nchunks) * TT;
+  if (i >= ns || s0 >= nslices) return;
+  const int nt = (int)(nslices - s0 < TT ? nslices - s0 : TT);
+  const double *xs = x + s0 * ns;
+  double sa[TT], sb[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) sa[t] = sb[t] = 0.0;
+  int cn[KU];
+  double mn[KU], kn[KU];
+#pragma unroll
+  for (int u = 0; u < KU; ++u) {
+    cn[u] = ce[(int64_t)u * ns + i];
+    mn[u] = me[(int64_t)u * ns + i];
+    kn[u] = ke[(int64_t)u * ns + i];
+  }
+  for (int k0 = 0; k0 < width; k0 += KU) {
+    int c[KU];
+    double mv[KU], kv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      c[u] = cn[u];
+      mv[u] = mn[u];
+      kv[u] = kn[u];
+    }
+    if (k0 + KU < width) {
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int64_t e = (int64_t)(k0 + KU + u) * ns + i;
+        cn[u] = ce[e];
+        mn[u] = me[e];
+        kn[u] = ke[e];
+      }
+    }
+    if (nt == TT) {
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          const double xv = xs[(int64_t)t * ns + c[u]];
+          sa[t] += mv[u] * xv;
+          sb[t] += kv[u] * xv;
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          if (t < nt) {
+            const double xv = xs[(int64_t)t * ns + c[u]];
+            sa[t] += mv[u] * xv;
+            sb[t] += kv[u] * xv;
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    if (t < nt) {
+      a[(s0 + t) * ns + i] = sa[t];
+      b[(s0 + t) * ns + i] = sb[t];
+    }
   }
 }
 

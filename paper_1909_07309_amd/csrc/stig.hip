@@ -54,8 +54,14 @@ constexpr int64_t GEMM2_GRID = 1024;  // persistent blocks of the small-n GEMM
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
-  ~DevBuf() {
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
     if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
   }
   stig_status ensure(size_t need) {
     if (need <= bytes) return STIG_OK;
@@ -122,6 +128,9 @@ struct stig_plan {
   const int32_t *csr_col = nullptr;
   const double *csr_val = nullptr;
   int64_t csr_nnz = 0;
+  // sparse spatial factors M_s, K_s (padded column-major, [0] as given, [1] transposed)
+  int ell_w[2] = {0, 0};
+  DevBuf ellC[2], ellM[2], ellK[2];
   // scratch
   DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, AZ, w, tmp, partial, small, flag, lift0, lift1;
   // pinned host staging of the small Krylov transfers: 4 coefficient slots of
@@ -330,25 +339,34 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
                              const double *out_scale) {
   typedef typename Mfma<TC>::elem E;
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
-  if (n <= GEMM2_MAX_N && !in_scale && !out_scale) {
-    // LDS as sized inside mode_gemm_small: compile-time n for 65 / 49, else GEMM2_MAX_N
-    const int nm = (n == 65 || n == 49) ? n : GEMM2_MAX_N;
+  // streaming kernel: compile-time sizes of the workloads' spatial directions
+  // (65, 49: cube; 32: extruded annulus; 130: annulus), runtime n up to GEMM2_MAX_N
+  const bool fixed = n == 65 || n == 49 || n == 32 || n == 130;
+  if (fixed || n <= GEMM2_MAX_N) {
+    // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N
+    const int nm = fixed ? n : GEMM2_MAX_N;
     size_t lds = (size_t)round_up(nm, 16) * lds_ld<TC>(nm) * sizeof(E);
+    if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
     unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID);
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
-    // compile-time sizes of the workloads' spatial directions, runtime n otherwise
-    if (n == 65)
-      hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC, 65>), dim3(grid), dim3(GEMM2_THREADS), lds,
-                         p->stream, in, out, op, n, inner, total_cols);
-    else if (n == 49)
-      hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC, 49>), dim3(grid), dim3(GEMM2_THREADS), lds,
-                         p->stream, in, out, op, n, inner, total_cols);
-    else
-      hipLaunchKernelGGL((mode_gemm_small<Tin, Tout, TC, 0>), dim3(grid), dim3(GEMM2_THREADS), lds,
-                         p->stream, in, out, op, n, inner, total_cols);
-    HIP_TRY(hipGetLastError());
-    return STIG_OK;
+    static size_t configured[5] = {0, 0, 0, 0, 0};  // per kernel of this type triple
+    auto go = [&](auto kern, int slot) -> stig_status {
+      if (lds > 65536 && lds > configured[slot]) {
+        HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        configured[slot] = lds;
+      }
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(GEMM2_THREADS), lds, p->stream, in, out, op, n,
+                         inner, total_cols, in_scale, out_scale, p->N);
+      HIP_TRY(hipGetLastError());
+      return STIG_OK;
+    };
+    if (n == 65) return go(mode_gemm_small<Tin, Tout, TC, 65>, 0);
+    if (n == 49) return go(mode_gemm_small<Tin, Tout, TC, 49>, 1);
+    if (n == 32) return go(mode_gemm_small<Tin, Tout, TC, 32>, 2);
+    if (n == 130) return go(mode_gemm_small<Tin, Tout, TC, 130>, 3);
+    return go(mode_gemm_small<Tin, Tout, TC, 0>, 4);
   }
   const int jt = (n + 15) / 16;
   const int ld = lds_ld<TC>(n);
@@ -819,6 +837,19 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
 
 // --------------------------------------------------------------- band passes
 
+// Chunks along a strided axis of length n with `cols` columns: split only when
+// the columns alone give fewer than 4096 wavefronts, into chunks of at least
+// 2 (2P + 1) entries (the 2P halo entries are read twice).
+int axis_chunks(int64_t cols, int n, int P) {
+  const int64_t waves = (cols + 63) / 64;
+  if (waves >= 4096) return 1;
+  const int want = (int)((4096 + waves - 1) / waves);
+  const int most = std::max(1, n / (2 * (2 * P + 1)));
+  const int ch = std::min(want, most);
+  const int jc = (n + ch - 1) / ch;
+  return (n + jc - 1) / jc;
+}
+
 template <int P>
 stig_status band_pass_p(stig_plan *p, const double *in1, const double *in2, double *out1,
                         double *out2, const double *Ba, const double *Bb, const double *Bc, int n,
@@ -829,9 +860,10 @@ stig_status band_pass_p(stig_plan *p, const double *in1, const double *in2, doub
     hipLaunchKernelGGL(band_pass_contig<P>, dim3(grid_for(total, 256)), dim3(256), 0, p->stream,
                        in1, in2, out1, out2, Ba, Bb, Bc, n, total);
   } else {
-    int64_t cols = total / n;
-    hipLaunchKernelGGL(band_pass_strided<P>, dim3(grid_for(cols, 256)), dim3(256), 0, p->stream,
-                       in1, in2, out1, out2, Ba, Bb, Bc, n, inner, cols);
+    const int64_t cols = total / n;
+    const int ch = axis_chunks(cols, n, P), jc = (n + ch - 1) / ch;
+    hipLaunchKernelGGL(band_pass_strided<P>, dim3(grid_for(cols, 256), ch), dim3(256), 0,
+                       p->stream, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, cols, jc);
   }
   HIP_TRY(hipGetLastError());
   return STIG_OK;
@@ -925,10 +957,38 @@ stig_status launch_stencil(stig_plan *p, const double *x, double *a, double *b, 
   return fail(STIG_EINVAL, "unsupported degree");
 }
 
-// spatial part of the banded matvec: a = x (x) M_s, b = x (x) K_s (all d axes)
-stig_status matvec_spatial(stig_plan *p, const double *x, int nrhs, const double **a,
-                           const double **b) {
+// a = M_s x, b = K_s x per slice with the sparse spatial factors (transposed
+// factors for the adjoint product)
+stig_status launch_spatial_ell(stig_plan *p, const double *x, double *a, double *b, int nrhs,
+                               int transpose) {
+  constexpr int TT = 8;
+  const int q = transpose ? 1 : 0;
+  const int64_t slices = (int64_t)p->nt * nrhs;
+  const int64_t chunks = (slices + TT - 1) / TT, rblocks = (p->Ns + 255) / 256;
+  if (chunks * rblocks >= ((int64_t)1 << 31))
+    return fail(STIG_EINVAL, "too many blocks for the sparse spatial pass");
+  ProfScope ps(p, STIG_K_CSR,
+               (double)p->N * nrhs * 24 + (double)p->ell_w[q] * p->Ns * 20);
+  hipLaunchKernelGGL((spatial_ell_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)), dim3(256),
+                     0, p->stream, x, a, b, p->ellC[q].as<int32_t>(), p->ellM[q].as<double>(),
+                     p->ellK[q].as<double>(), p->ell_w[q], p->Ns, slices, (int)chunks);
+  HIP_TRY(hipGetLastError());
+  return STIG_OK;
+}
+
+// spatial part of the banded matvec: a = x (x) M_s, b = x (x) K_s (all d axes),
+// from the sparse spatial factors when they are set
+stig_status matvec_spatial(stig_plan *p, const double *x, int nrhs, int transpose,
+                           const double **a, const double **b) {
   const int64_t tot = p->N * nrhs;
+  if (p->ell_w[0] > 0) {
+    STIG_TRY(p->m0.ensure(tot * sizeof(double)));
+    STIG_TRY(p->m1.ensure(tot * sizeof(double)));
+    STIG_TRY(launch_spatial_ell(p, x, p->m0.as<double>(), p->m1.as<double>(), nrhs, transpose));
+    *a = p->m0.as<double>();
+    *b = p->m1.as<double>();
+    return STIG_OK;
+  }
   if (stencil_fits(p)) {
     // spatial part in one stencil pass per (rhs, t) slice
     STIG_TRY(p->m0.ensure(tot * sizeof(double)));
@@ -943,13 +1003,22 @@ stig_status matvec_spatial(stig_plan *p, const double *x, int nrhs, const double
   return spatial_chain(p, x, tot, true, a, b, bufs);
 }
 
+// blocks along the spatial columns and chunks along t of the fused residual pass
+void residual_grid(const stig_plan *p, int64_t *blocks, int *chunks) {
+  *blocks = (p->Ns + 255) / 256;
+  *chunks = axis_chunks(p->Ns, p->nt, p->pt);
+}
+
 template <int P>
 stig_status launch_time_residual(stig_plan *p, const double *a, const double *b, const double *f,
-                                 double *r, int transpose, double *partial, int64_t blocks) {
+                                 double *r, int transpose, double *partial, int64_t blocks,
+                                 int chunks) {
   const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
+  const int jc = (p->nt + chunks - 1) / chunks;
   ProfScope ps(p, STIG_K_BAND_PASS, (double)p->N * 8 * 4);
-  hipLaunchKernelGGL(time_pass_residual<P>, dim3((unsigned)blocks), dim3(256), 0, p->stream, a, b,
-                     f, r, p->tnM.as<double>(), gW, p->nt, p->Ns, p->Ns, partial);
+  hipLaunchKernelGGL(time_pass_residual<P>, dim3((unsigned)blocks, chunks), dim3(256), 0,
+                     p->stream, a, b, f, r, p->tnM.as<double>(), gW, p->nt, p->Ns, p->Ns, jc,
+                     partial);
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
@@ -961,17 +1030,19 @@ stig_status run_residual_banded(stig_plan *p, const double *f, const double *x, 
                                 int transpose, double *partial, int64_t partial_cap,
                                 int64_t *nparts) {
   if (p->csr_rowptr) return fail(STIG_EINVAL, "no banded form");
-  const int64_t blocks = (p->Ns + 255) / 256;
-  if (blocks > partial_cap) return fail(STIG_EINVAL, "residual partials do not fit");
+  int64_t blocks;
+  int ch;
+  residual_grid(p, &blocks, &ch);
+  if (blocks * ch > partial_cap) return fail(STIG_EINVAL, "residual partials do not fit");
   const double *a, *b;
-  STIG_TRY(matvec_spatial(p, x, 1, &a, &b));
-  *nparts = blocks;
+  STIG_TRY(matvec_spatial(p, x, 1, transpose, &a, &b));
+  *nparts = blocks * ch;
   switch (p->pt) {
-    case 1: return launch_time_residual<1>(p, a, b, f, r, transpose, partial, blocks);
-    case 2: return launch_time_residual<2>(p, a, b, f, r, transpose, partial, blocks);
-    case 3: return launch_time_residual<3>(p, a, b, f, r, transpose, partial, blocks);
-    case 4: return launch_time_residual<4>(p, a, b, f, r, transpose, partial, blocks);
-    case 5: return launch_time_residual<5>(p, a, b, f, r, transpose, partial, blocks);
+    case 1: return launch_time_residual<1>(p, a, b, f, r, transpose, partial, blocks, ch);
+    case 2: return launch_time_residual<2>(p, a, b, f, r, transpose, partial, blocks, ch);
+    case 3: return launch_time_residual<3>(p, a, b, f, r, transpose, partial, blocks, ch);
+    case 4: return launch_time_residual<4>(p, a, b, f, r, transpose, partial, blocks, ch);
+    case 5: return launch_time_residual<5>(p, a, b, f, r, transpose, partial, blocks, ch);
   }
   return fail(STIG_EINVAL, "unsupported degree");
 }
@@ -989,7 +1060,7 @@ stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int t
     return STIG_OK;
   }
   const double *a, *b;
-  STIG_TRY(matvec_spatial(p, x, nrhs, &a, &b));
+  STIG_TRY(matvec_spatial(p, x, nrhs, transpose, &a, &b));
   // time pass: y = nu (b x_t M_t) + gamma (a x_t W_t)
   const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
   STIG_TRY(band_pass(p, p->pt, a, b, nullptr, y, nullptr, p->tnM.as<double>(), gW, p->nt, p->Ns,
@@ -1066,7 +1137,10 @@ struct Krylov {
   stig_status residual_of(const double *f, const double *u, double *r, double *tmp,
                           int transpose, double *norm) {
     const int64_t cap = (int64_t)(p->partial.bytes / sizeof(double));
-    if (!p->csr_rowptr && (p->Ns + 255) / 256 <= cap) {
+    int64_t rblocks;
+    int rch;
+    residual_grid(p, &rblocks, &rch);
+    if (!p->csr_rowptr && rblocks * rch <= cap) {
       int64_t nparts = 0;
       STIG_TRY(run_residual_banded(p, f, u, r, transpose, partial(), cap, &nparts));
       hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(KRY_BLOCK), 0, p->stream, partial(),
@@ -1874,10 +1948,44 @@ stig_status stig_set_A_csr(stig_plan *p, const int64_t *rowptr, const int32_t *c
     return STIG_OK;
   }
   if (!col || !val || nnz < 0) return fail(STIG_EINVAL, "bad CSR arrays");
+  p->ell_w[0] = p->ell_w[1] = 0;
   p->csr_rowptr = rowptr;
   p->csr_col = col;
   p->csr_val = val;
   p->csr_nnz = nnz;
+  return STIG_OK;
+}
+
+stig_status stig_set_spatial_factors(stig_plan *p, const int64_t *rowptr, const int32_t *col,
+                                     const double *valM, const double *valK) {
+  STIG_TRY(check_plan(p, false));
+  if (!rowptr) {
+    p->ell_w[0] = p->ell_w[1] = 0;
+    for (int q = 0; q < 2; ++q) {
+      p->ellC[q].release();
+      p->ellM[q].release();
+      p->ellK[q].release();
+    }
+    return STIG_OK;
+  }
+  if (!col || !valM || !valK) return fail(STIG_EINVAL, "null spatial factor array");
+  std::vector<int32_t> ce[2];
+  std::vector<double> me[2], ke[2];
+  int w[2];
+  for (int q = 0; q < 2; ++q) {
+    w[q] = spatial_ell(p->Ns, rowptr, col, valM, valK, q == 1, ELL_KU, &ce[q], &me[q], &ke[q]);
+    if (w[q] < 0) return fail(STIG_EINVAL, "spatial factors: bad row pointers or columns");
+  }
+  p->ell_w[0] = p->ell_w[1] = 0;
+  for (int q = 0; q < 2; ++q) {
+    STIG_TRY(upload(p->ellC[q], ce[q], p->stream));
+    STIG_TRY(upload(p->ellM[q], me[q], p->stream));
+    STIG_TRY(upload(p->ellK[q], ke[q], p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->ell_w[0] = w[0];
+  p->ell_w[1] = w[1];
+  p->csr_rowptr = nullptr;
   return STIG_OK;
 }
 
@@ -2075,12 +2183,13 @@ size_t stig_plan_device_bytes(const stig_plan *p) {
                         &p->aTab32[1], &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
                         &p->tR64[0], &p->tR64[1], &p->tR32[0], &p->tR32[1],
                         &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->s0, &p->s1, &p->tscr, &p->m0,
-                        &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->w, &p->tmp, &p->partial,
+                        &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->AZ, &p->w, &p->tmp, &p->partial,
                         &p->small, &p->flag, &p->lift0, &p->lift1};
   for (auto *b : bs) t += b->bytes;
   for (int l = 0; l < 3; ++l) {
     t += p->U64[l].bytes + p->UT64[l].bytes + p->U32[l].bytes + p->UT32[l].bytes +
          p->U16[l].bytes + p->UT16[l].bytes + p->sK[l].bytes + p->sM[l].bytes;
+  for (int q = 0; q < 2; ++q) t += p->ellC[q].bytes + p->ellM[q].bytes + p->ellK[q].bytes;
     for (int q = 0; q < 3; ++q)
       t += p->hFE[q][l].bytes + p->hFO[q][l].bytes + p->hBE[q][l].bytes + p->hBO[q][l].bytes;
   }

@@ -37,6 +37,16 @@ int64_t assemble_3d(int n_el, int p, int nq, const double *c11, const double *c2
                     const double *c33, const double *c00, int64_t *rowptr, int32_t *col,
                     double *valK, double *valM);
 
+// Padded column-major copy of a square CSR pair (M, K) with one shared pattern
+// (or of its transpose pair): entry k of row i at k * n + i, the width the
+// longest row rounded up to a multiple of align, shorter rows padded with column
+// i and value 0.  Returns the width, or -1 if a column is out of range or rowptr
+// is not non-decreasing (outputs untouched).  With ce == nullptr only the width
+// is computed.
+int spatial_ell(int64_t n, const int64_t *rowptr, const int32_t *col, const double *valM,
+                const double *valK, bool transpose, int align, std::vector<int32_t> *ce,
+                std::vector<double> *me, std::vector<double> *ke);
+
 // Separable (rank-one, log-space) approximation of 3D samples [e3][e2][e1]:
 // C00 ~ phi1 phi2 phi3 and C_ll ~ Phi_l prod_{m != l} phi_m.
 void separate_3d(int n1, int n2, int n3, const double *C11, const double *C22, const double *C33,

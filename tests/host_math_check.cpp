@@ -197,6 +197,70 @@ int main() {
       }
     check(err < 1e-13, "separation", n1, n2, err);
   }
+  // padded column-major copy of a sparse pair: dense reconstruction of the matrix and of its
+  // transpose, padding with column i and value 0, and rejection of bad input
+  {
+    const int64_t n = 7;
+    // irregular pattern: row i holds columns (i * 3 + j * 5) % n for j < 1 + i % 4 (distinct)
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> col;
+    Vec vM, vK, DM(n * n, 0.0), DK(n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int64_t j = 0; j < 1 + i % 4; ++j) {
+        const int32_t c = (int32_t)((i * 3 + j * 5) % n);
+        col.push_back(c);
+        vM.push_back(1.0 + i + 0.1 * c);
+        vK.push_back(-2.0 + 0.5 * i - 0.3 * c);
+        DM[i * n + c] += vM.back();
+        DK[i * n + c] += vK.back();
+      }
+      rp[i + 1] = (int64_t)col.size();
+    }
+    for (int tr = 0; tr < 2; ++tr) {
+      std::vector<int32_t> ce;
+      Vec me, ke;
+      const int align = tr ? 3 : 1;
+      const int w =
+          spatial_ell(n, rp.data(), col.data(), vM.data(), vK.data(), tr == 1, align, &ce, &me, &ke);
+      check(w == spatial_ell(n, rp.data(), col.data(), vM.data(), vK.data(), tr == 1, align, nullptr,
+                             nullptr, nullptr),
+            "ell width query", tr, w, 0.0);
+      int longest = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        int len = 0;
+        for (int64_t e = 0; e < rp[n]; ++e) len += tr ? (col[e] == i) : (e >= rp[i] && e < rp[i + 1]);
+        longest = std::max(longest, len);
+      }
+      check(w == (longest + align - 1) / align * align && ce.size() == (size_t)(w * n), "ell width", tr,
+            w, longest);
+      Vec RM(n * n, 0.0), RK(n * n, 0.0);
+      for (int64_t k = 0; k < w; ++k)
+        for (int64_t i = 0; i < n; ++i) {
+          const size_t e = (size_t)(k * n + i);
+          check(ce[e] >= 0 && ce[e] < n, "ell column range", tr, (int)e, ce[e]);
+          if (me[e] == 0.0 && ke[e] == 0.0) check(ce[e] == i, "ell padding column", tr, (int)e, ce[e]);
+          RM[i * n + ce[e]] += me[e];
+          RK[i * n + ce[e]] += ke[e];
+        }
+      double err = 0.0;
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          const size_t src = tr ? (size_t)(j * n + i) : (size_t)(i * n + j);
+          err = std::max(err, std::fabs(RM[i * n + j] - DM[src]) + std::fabs(RK[i * n + j] - DK[src]));
+        }
+      check(err == 0.0, "ell reproduces the matrix", tr, 0, err);
+    }
+    std::vector<int32_t> bad = col;
+    bad[3] = (int32_t)n;
+    check(spatial_ell(n, rp.data(), bad.data(), vM.data(), vK.data(), false, 1, nullptr, nullptr, nullptr) ==
+              -1,
+          "ell rejects a column out of range", 0, 0, 0.0);
+    std::vector<int64_t> brp = rp;
+    brp[4] = brp[3] - 1;
+    check(spatial_ell(n, brp.data(), col.data(), vM.data(), vK.data(), true, 1, nullptr, nullptr, nullptr) ==
+              -1,
+          "ell rejects decreasing row pointers", 0, 0, 0.0);
+  }
   std::printf("%s: %d failed checks\n", fails ? "host math FAILED" : "host math ok", fails);
   return fails;
 }

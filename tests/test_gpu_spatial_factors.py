@@ -1,0 +1,130 @@
+"""GPU parity for the matvec with sparse spatial factors (Section 4.5: only the
+spatial and time factors of A are stored) on the quarter annulus (2D, p = 4)
+and the extruded quarter annulus (3D, p = 2): plain and transposed products,
+batches, the residual path inside (F)GMRES and the adjoint solve, against the
+oracle's independent assembly.  Shapes span several 256-row blocks with a
+ragged last block and time levels that are not a multiple of the 8-level
+chunks of the spatial pass."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from paper_1909_07309_amd._lib import StigError
+from oracle.annulus import AnnulusProblem
+from oracle.annulus3d import Annulus3DProblem
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _setup(d, n_el, matvec="factored"):
+    if d == 2:
+        from paper_1909_07309_amd.annulus import AnnulusSetup as Setup
+        base, Oracle = wl.WORKLOADS["annulus_p4_n128"], AnnulusProblem
+    else:
+        from paper_1909_07309_amd.annulus3d import Annulus3DSetup as Setup
+        base, Oracle = wl.WORKLOADS["annulus3d_p2_n32"], Annulus3DProblem
+    w = wl.scaled(base, n_el) if n_el else base
+    a = Setup(w)
+    return w, a, a.make_plan(matvec=matvec), Oracle(w)
+
+
+def _oracle_transposed(o, x):
+    """A^T x = (W_t^T (x) M_s^T + M_t^T (x) K_s^T) x from the oracle's factor matrices."""
+    X = np.asarray(x).reshape(o.w.n_t, -1)
+    MX = (o.Ms.T @ X.T).T
+    KX = (o.Ks.T @ X.T).T
+    return (o.Wt.T @ MX + o.Mt.T @ KX).reshape(np.shape(x))
+
+
+@pytest.mark.parametrize("d,n_el", [(2, 6), (2, 20), (3, 4), (3, 9)])
+def test_factored_matvec_matches_dense_oracle(d, n_el):
+    w, a, plan, o = _setup(d, n_el)
+    x = wl.random_tensor((2,) + w.shape, 11)
+    A = o.dense_A()
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
+    for r in range(2):
+        ref = A @ x[r].ravel()
+        reft = A.T @ x[r].ravel()
+        assert np.abs(y[r].ravel() - ref).max() <= 1e-13 * np.abs(ref).max()
+        assert np.abs(yt[r].ravel() - reft).max() <= 1e-13 * np.abs(reft).max()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_factored_form_replaces_and_is_replaced_by_csr(d):
+    w, a, plan, o = _setup(d, 6, matvec="csr")
+    x = wl.random_tensor(w.shape, 2)
+    ref = o.matvec(x)
+    y_csr = plan.matvec_A(_dev(x)).cpu().numpy()
+    with pytest.raises(StigError):
+        plan.matvec_A(_dev(x), transpose=True)       # the CSR form has no transpose
+    plan.set_spatial_factors(a.space)                 # clears the CSR
+    y_fac = plan.matvec_A(_dev(x)).cpu().numpy()
+    plan.matvec_A(_dev(x), transpose=True)
+    rowptr, col, val = plan.kron_csr(a.space, a.Wt, a.Mt)
+    plan.set_A_csr(rowptr, col, val)                  # clears the factors
+    with pytest.raises(StigError):
+        plan.matvec_A(_dev(x), transpose=True)
+    plan.set_A_csr(None, None, None)
+    plan.set_spatial_factors(None)                    # back to the plan's Kronecker factors
+    y_kron = plan.matvec_A(_dev(x)).cpu().numpy()
+    for y in (y_csr, y_fac):
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the Kronecker factors are the separated approximation, not A
+    assert np.abs(y_kron - ref).max() > 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_factored_form_rejects_bad_pattern(d):
+    w, a, plan, o = _setup(d, 6)
+    rp, col, vK, vM = a.space
+    bad = col.copy()
+    bad[5] = plan.N_s
+    with pytest.raises(StigError):
+        plan.set_spatial_factors((rp, bad, vK, vM))
+    # nothing changed: the factors set before still give A x
+    x = wl.random_tensor(w.shape, 4)
+    ref = o.matvec(x)
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_factored_full_size_matvec_transpose_and_solve(d):
+    """2D: 130^2 x 131 = 2,213,900 unknowns; 3D: 32^3 x 33 = 1,081,344 unknowns."""
+    w, a, plan, o = _setup(d, None)
+    x = wl.random_tensor(w.shape, 5)
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    ref = o.matvec(x)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
+    reft = _oracle_transposed(o, x)
+    assert np.abs(yt - reft).max() <= 1e-13 * np.abs(reft).max()
+    f = a.source()
+    f_ref = o.source()
+    u, info = plan.gmres_solve(f, restart=30, rtol=1e-8, maxit=300, flexible=True, prec="fp32")
+    r = f_ref - o.matvec(u.cpu().numpy())
+    relres = np.linalg.norm(r) / np.linalg.norm(f_ref)
+    print(f"d={d} factored matvec: {info['iters']} FGMRES iterations, oracle residual {relres:.2e}")
+    assert relres <= 1e-8
+    assert abs(info["relres_true"] - relres) <= 1e-3 * relres + 1e-15
+    it_csr = 18 if d == 2 else 12     # iterations of the same solve with the space-time CSR
+    assert abs(info["iters"] - it_csr) <= 1
+
+
+@pytest.mark.parametrize("d,n_el", [(2, 12), (3, 6)])
+def test_factored_adjoint_solve_matches_dense_oracle(d, n_el):
+    w, a, plan, o = _setup(d, n_el)
+    g = wl.random_tensor(w.shape, 8)
+    lam, info = plan.gmres_solve(_dev(g), restart=30, rtol=1e-10, maxit=300, transpose=True)
+    At = o.dense_A().T
+    lam = lam.cpu().numpy().ravel()
+    res = np.linalg.norm(g.ravel() - At @ lam) / np.linalg.norm(g)
+    assert res <= 1e-10
+    ref = np.linalg.solve(At, g.ravel())
+    assert np.linalg.norm(lam - ref) / np.linalg.norm(ref) <= 1e-7
