@@ -289,10 +289,12 @@ constexpr int GEMM2_THREADS = 256;
 // NC = n as a compile-time constant (0: n taken from the argument).  With NC
 // fixed, the MFMA chain has no runtime guards, so the accumulators stay in
 // place instead of being copied at every branch.
-// in_scale / out_scale (optional, length nscale, index taken modulo nscale):
-// per-entry factors multiplied in on load / on store; a column's entries lie in
-// one period of nscale, so the modulo is taken once per column.
-template <typename Tin, typename Tout, typename TC, int NC>
+// SC: in_scale / out_scale (optional, length nscale, index taken modulo
+// nscale) are per-entry factors multiplied in on load / on store; a column's
+// entries lie in one period of nscale, so the modulo is taken once per column.
+// The scaled form loads each strip just before multiplying it (no prefetch of
+// the next strip: the factors take those registers).  SC false: both null.
+template <typename Tin, typename Tout, typename TC, int NC, bool SC>
 __global__ void __launch_bounds__(GEMM2_THREADS)
 mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
                 const typename Mfma<TC>::elem *__restrict__ Op, int n_arg, int64_t inner,
@@ -356,17 +358,47 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     const bool cvalid = strip < nstrips && c < total_cols;
     int64_t base, step;
     locate(cvalid ? c : 0, base, step);
-    const int64_t sb = in_scale ? base % nscale : 0;
+    if (!SC || !in_scale) {
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s)
+#pragma unroll
+        for (int u = 0; u < MF::KPL; ++u) {
+          int k = s * MF::KSTEP + kg * MF::KPL + u;
+          bool ok = cvalid && k < n;
+          int64_t a = ok ? base + (int64_t)k * step : 0;
+          double x = Conv<Tin>::to_f64(in[a]);
+          bv[s][u] = ok ? MF::from_f64(x) : MF::zero();
+        }
+      return;
+    }
+    // scaled: every load of the strip (values, then factors) is issued before
+    // the first product, so the two sets of loads overlap
+    const int64_t sb = base % nscale;
+    Tin xr[KSMAX][MF::KPL];
+    double sc[KSMAX][MF::KPL];
 #pragma unroll
     for (int s = 0; s < KSMAX; ++s)
 #pragma unroll
       for (int u = 0; u < MF::KPL; ++u) {
         int k = s * MF::KSTEP + kg * MF::KPL + u;
         bool ok = cvalid && k < n;
-        int64_t a = ok ? base + (int64_t)k * step : 0;
-        double x = Conv<Tin>::to_f64(in[a]);
-        if (in_scale) x *= in_scale[ok ? sb + (int64_t)k * step : 0];
-        bv[s][u] = ok ? MF::from_f64(x) : MF::zero();
+        xr[s][u] = in[ok ? base + (int64_t)k * step : 0];
+      }
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+#pragma unroll
+      for (int u = 0; u < MF::KPL; ++u) {
+        int k = s * MF::KSTEP + kg * MF::KPL + u;
+        bool ok = cvalid && k < n;
+        sc[s][u] = in_scale[ok ? sb + (int64_t)k * step : 0];
+      }
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+#pragma unroll
+      for (int u = 0; u < MF::KPL; ++u) {
+        int k = s * MF::KSTEP + kg * MF::KPL + u;
+        bool ok = cvalid && k < n;
+        bv[s][u] = ok ? MF::from_f64(Conv<Tin>::to_f64(xr[s][u]) * sc[s][u]) : MF::zero();
       }
   };
   // Process one strip whose B operand is already in registers: full row tiles
@@ -377,7 +409,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     const bool cvalid = c < total_cols;
     int64_t base, step;
     locate(cvalid ? c : 0, base, step);
-    const int64_t sb = out_scale ? base % nscale : 0;
+    const int64_t sb = SC && out_scale ? base % nscale : 0;
     typename MF::acc acc[QMAX];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
@@ -402,23 +434,13 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       // every LDS read of the loop and the register count quadruples
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (cvalid) {
+    // fringe rows on the vector ALU from the B registers (before the stores,
+    // so that the B registers are free while output factors are loaded)
+    constexpr int NFR = NMAX - 16 * QMAX;
+    double fr[NFR > 0 ? NFR : 1];
 #pragma unroll
-      for (int t = 0; t < QMAX; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int j = 16 * t + MF::out_row(kg, v);
-          if (j < n) {
-            double y = (double)acc[t][v];
-            if (out_scale) y *= out_scale[sb + (int64_t)j * step];
-            out[base + (int64_t)j * step] = Conv<Tout>::from_f64(y);
-          }
-        }
-    }
-    // fringe rows on the vector ALU from the B registers
-#pragma unroll
-    for (int jr = 16 * QMAX; jr < NMAX; ++jr) {
-      const E *orow = opl + (size_t)jr * ld + kg * MF::KPL;
+    for (int q = 0; q < NFR; ++q) {
+      const E *orow = opl + (size_t)(16 * QMAX + q) * ld + kg * MF::KPL;
       double sum = 0.0;
 #pragma unroll
       for (int s = 0; s < KSMAX; ++s)
@@ -427,14 +449,59 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
           sum += MF::to_f64(orow[s * MF::KSTEP + u]) * MF::to_f64(bv[s][u]);
       sum += __shfl_xor(sum, 16, 64);
       sum += __shfl_xor(sum, 32, 64);
-      if (kg == 0 && cvalid && jr < n) {
-        if (out_scale) sum *= out_scale[sb + (int64_t)jr * step];
-        out[base + (int64_t)jr * step] = Conv<Tout>::from_f64(sum);
+      fr[q] = sum;
+    }
+    if (!cvalid) return;
+    double yv[QMAX][4];
+#pragma unroll
+    for (int t = 0; t < QMAX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) yv[t][v] = (double)acc[t][v];
+    if (SC && out_scale) {
+      // all output factors of the lane in flight at once
+      double sc[QMAX][4], sf[NFR > 0 ? NFR : 1];
+#pragma unroll
+      for (int t = 0; t < QMAX; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int j = 16 * t + MF::out_row(kg, v);
+          sc[t][v] = out_scale[j < n ? sb + (int64_t)j * step : sb];
+        }
+#pragma unroll
+      for (int q = 0; q < NFR; ++q) {
+        int j = 16 * QMAX + q;
+        sf[q] = out_scale[j < n ? sb + (int64_t)j * step : sb];
       }
+#pragma unroll
+      for (int t = 0; t < QMAX; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yv[t][v] *= sc[t][v];
+#pragma unroll
+      for (int q = 0; q < NFR; ++q) fr[q] *= sf[q];
+    }
+#pragma unroll
+    for (int t = 0; t < QMAX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int j = 16 * t + MF::out_row(kg, v);
+        if (j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(yv[t][v]);
+      }
+#pragma unroll
+    for (int q = 0; q < NFR; ++q) {
+      int j = 16 * QMAX + q;
+      if (kg == 0 && j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(fr[q]);
     }
   };
-  // one strip in flight per wave while the current one is multiplied
   int64_t strip = (int64_t)blockIdx.x * (GEMM2_THREADS / 64) + wave;
+  if (SC) {
+    for (; strip < nstrips; strip += wstride) {
+      E bv[KSMAX][MF::KPL];
+      load_b(strip, bv);
+      process(strip, bv);
+    }
+    return;
+  }
+  // one strip in flight per wave while the current one is multiplied
   E bnext[KSMAX][MF::KPL];
   load_b(strip, bnext);
   for (; strip < nstrips; strip += wstride) {

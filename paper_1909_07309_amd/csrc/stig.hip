@@ -340,17 +340,20 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   typedef typename Mfma<TC>::elem E;
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
   // streaming kernel: compile-time sizes of the workloads' spatial directions
-  // (65, 49: cube; 32: extruded annulus; 130: annulus), runtime n up to GEMM2_MAX_N
-  const bool fixed = n == 65 || n == 49 || n == 32 || n == 130;
-  if (fixed || n <= GEMM2_MAX_N) {
+  // (65, 49: cube; 32: extruded annulus; 130: annulus; scaled: 32, 130), runtime
+  // n up to GEMM2_MAX_N otherwise
+  const bool sc = in_scale || out_scale;
+  const int nc = sc ? ((n == 32 || n == 130) ? n : 0)
+                    : ((n == 65 || n == 49 || n == 32 || n == 130) ? n : 0);
+  if (nc != 0 || n <= GEMM2_MAX_N) {
     // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N
-    const int nm = fixed ? n : GEMM2_MAX_N;
+    const int nm = nc ? nc : GEMM2_MAX_N;
     size_t lds = (size_t)round_up(nm, 16) * lds_ld<TC>(nm) * sizeof(E);
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
     unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID);
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
-    static size_t configured[5] = {0, 0, 0, 0, 0};  // per kernel of this type triple
+    static size_t configured[10] = {};  // per kernel of this type triple
     auto go = [&](auto kern, int slot) -> stig_status {
       if (lds > 65536 && lds > configured[slot]) {
         HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -362,11 +365,16 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
       HIP_TRY(hipGetLastError());
       return STIG_OK;
     };
-    if (n == 65) return go(mode_gemm_small<Tin, Tout, TC, 65>, 0);
-    if (n == 49) return go(mode_gemm_small<Tin, Tout, TC, 49>, 1);
-    if (n == 32) return go(mode_gemm_small<Tin, Tout, TC, 32>, 2);
-    if (n == 130) return go(mode_gemm_small<Tin, Tout, TC, 130>, 3);
-    return go(mode_gemm_small<Tin, Tout, TC, 0>, 4);
+    if (sc) {
+      if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, true>, 5);
+      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, true>, 6);
+      return go(mode_gemm_small<Tin, Tout, TC, 0, true>, 7);
+    }
+    if (nc == 65) return go(mode_gemm_small<Tin, Tout, TC, 65, false>, 0);
+    if (nc == 49) return go(mode_gemm_small<Tin, Tout, TC, 49, false>, 1);
+    if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, false>, 2);
+    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false>, 3);
+    return go(mode_gemm_small<Tin, Tout, TC, 0, false>, 4);
   }
   const int jt = (n + 15) / 16;
   const int ld = lds_ld<TC>(n);
