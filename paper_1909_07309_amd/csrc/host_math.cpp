@@ -15,6 +15,7 @@
 #include <cstring>
 #include <numeric>
 #include <stdexcept>
+#include <unordered_set>
 #include <vector>
 
 #include "stig_internal.h"
@@ -421,6 +422,43 @@ int spatial_ell(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
       (*ke)[slot] = valK[e];
     }
   return (int)width;
+}
+
+int spatial_dia(int64_t n, const int64_t *rowptr, const int32_t *col, const double *valM,
+                const double *valK, bool transpose, int align, int max_diags,
+                std::vector<int32_t> *offs, std::vector<double> *me, std::vector<double> *ke) {
+  if (rowptr[0] != 0) return -1;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return -1;
+  const int64_t nnz = rowptr[n];
+  for (int64_t e = 0; e < nnz; ++e)
+    if (col[e] < 0 || col[e] >= n) return -1;
+  // distinct offsets of the stored matrix (transpose: offsets negated)
+  std::unordered_set<int64_t> seen;
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      seen.insert(transpose ? r - col[e] : col[e] - r);
+      if ((int64_t)seen.size() > max_diags) return 0;
+    }
+  std::vector<int64_t> o(seen.begin(), seen.end());
+  if (o.empty()) o.push_back(0);
+  std::sort(o.begin(), o.end());
+  align = std::max(align, 1);
+  const int64_t nd = ((int64_t)o.size() + align - 1) / align * align;
+  if (nd > max_diags) return 0;
+  if (!offs) return (int)nd;
+  offs->assign((size_t)nd, 0);
+  for (int64_t k = 0; k < nd; ++k) (*offs)[(size_t)k] = (int32_t)o[std::min<int64_t>(k, o.size() - 1)];
+  me->assign((size_t)(nd * n), 0.0);
+  ke->assign((size_t)(nd * n), 0.0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      const int64_t i = transpose ? col[e] : r, j = transpose ? r : col[e];
+      const int64_t k = std::lower_bound(o.begin(), o.end(), j - i) - o.begin();
+      (*me)[(size_t)(k * n + i)] += valM[e];
+      (*ke)[(size_t)(k * n + i)] += valK[e];
+    }
+  return (int)nd;
 }
 
 void separate_3d(int n1, int n2, int n3, const double *C11, const double *C22, const double *C33,

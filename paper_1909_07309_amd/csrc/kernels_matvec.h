@@ -320,6 +320,71 @@ spatial_ell_pair(const double *__restrict__ x, double *__restrict__ a, double *_
   }
 }
 
+// The same product with M_s and K_s stored by diagonals: diagonal k holds the
+// entries at offset offs[k] = col - row, row i's at k * ns + i (zero where the
+// row has none, e.g. near the boundary of a tensor-product pattern).  The
+// column of every lane is i + offs[k] with a uniform offset, so no column
+// indices are loaded and a wavefront's gathers stay contiguous.  Padding
+// entries have value 0 and a column clamped into [0, ns).
+template <int TT, int KU>
+__global__ void __launch_bounds__(256)
+spatial_dia_pair(const double *__restrict__ x, double *__restrict__ a, double *__restrict__ b,
+                 const int32_t *__restrict__ offs, const double *__restrict__ me,
+                 const double *__restrict__ ke, int ndiag, int64_t ns, int64_t nslices,
+                 int nchunks) {
+  const unsigned nb = gridDim.x, q = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8;
+  const unsigned g = xcd * q + (xcd < rem ? xcd : rem) + blockIdx.x / 8;
+  const int64_t i = (int64_t)(g / nchunks) * blockDim.x + threadIdx.x;
+  const int64_t s0 = (int64_t)(g % nchunks) * TT;
+  if (i >= ns || s0 >= nslices) return;
+  const int nt = (int)(nslices - s0 < TT ? nslices - s0 : TT);
+  const double *xs = x + s0 * ns;
+  cptr<int32_t> co = as_const(offs);
+  double sa[TT], sb[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) sa[t] = sb[t] = 0.0;
+  for (int k0 = 0; k0 < ndiag; k0 += KU) {
+    int64_t c[KU];
+    double mv[KU], kv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int64_t e = (int64_t)(k0 + u) * ns + i;
+      mv[u] = me[e];
+      kv[u] = ke[e];
+      const int64_t cc = i + co[k0 + u];
+      c[u] = cc < 0 ? 0 : (cc >= ns ? ns - 1 : cc);
+    }
+    if (nt == TT) {
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          const double xv = xs[(int64_t)t * ns + c[u]];
+          sa[t] += mv[u] * xv;
+          sb[t] += kv[u] * xv;
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          if (t < nt) {
+            const double xv = xs[(int64_t)t * ns + c[u]];
+            sa[t] += mv[u] * xv;
+            sb[t] += kv[u] * xv;
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    if (t < nt) {
+      a[(s0 + t) * ns + i] = sa[t];
+      b[(s0 + t) * ns + i] = sb[t];
+    }
+  }
+}
+
 // Spatial part of the matvec in one pass over each (rhs, t) slice (d = 2, 3):
 //   a = x x_1 M_1 x_2 M_2 x_3 M_3,   b = x x_1 K_1 x_2 M_2 x_3 M_3
 //       + x x_1 M_1 x_2 K_2 x_3 M_3 + x x_1 M_1 x_2 M_2 x_3 K_3

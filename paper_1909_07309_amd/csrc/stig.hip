@@ -128,8 +128,10 @@ struct stig_plan {
   const int32_t *csr_col = nullptr;
   const double *csr_val = nullptr;
   int64_t csr_nnz = 0;
-  // sparse spatial factors M_s, K_s (padded column-major, [0] as given, [1] transposed)
+  // sparse spatial factors M_s, K_s ([0] as given, [1] transposed): by diagonals
+  // (ell_dia, offsets in ellC) or padded column-major rows (columns in ellC)
   int ell_w[2] = {0, 0};
+  bool ell_dia[2] = {false, false};
   DevBuf ellC[2], ellM[2], ellK[2];
   // scratch
   DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, AZ, w, tmp, partial, small, flag, lift0, lift1;
@@ -976,10 +978,17 @@ stig_status launch_spatial_ell(stig_plan *p, const double *x, double *a, double 
   if (chunks * rblocks >= ((int64_t)1 << 31))
     return fail(STIG_EINVAL, "too many blocks for the sparse spatial pass");
   ProfScope ps(p, STIG_K_CSR,
-               (double)p->N * nrhs * 24 + (double)p->ell_w[q] * p->Ns * 20);
-  hipLaunchKernelGGL((spatial_ell_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)), dim3(256),
-                     0, p->stream, x, a, b, p->ellC[q].as<int32_t>(), p->ellM[q].as<double>(),
-                     p->ellK[q].as<double>(), p->ell_w[q], p->Ns, slices, (int)chunks);
+               (double)p->N * nrhs * 24 + (double)p->ell_w[q] * p->Ns * (p->ell_dia[q] ? 16 : 20));
+  if (p->ell_dia[q])
+    hipLaunchKernelGGL((spatial_dia_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)),
+                       dim3(256), 0, p->stream, x, a, b, p->ellC[q].as<int32_t>(),
+                       p->ellM[q].as<double>(), p->ellK[q].as<double>(), p->ell_w[q], p->Ns,
+                       slices, (int)chunks);
+  else
+    hipLaunchKernelGGL((spatial_ell_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)),
+                       dim3(256), 0, p->stream, x, a, b, p->ellC[q].as<int32_t>(),
+                       p->ellM[q].as<double>(), p->ellK[q].as<double>(), p->ell_w[q], p->Ns,
+                       slices, (int)chunks);
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
@@ -1980,9 +1989,18 @@ stig_status stig_set_spatial_factors(stig_plan *p, const int64_t *rowptr, const 
   std::vector<int32_t> ce[2];
   std::vector<double> me[2], ke[2];
   int w[2];
+  bool dia[2];
   for (int q = 0; q < 2; ++q) {
-    w[q] = spatial_ell(p->Ns, rowptr, col, valM, valK, q == 1, ELL_KU, &ce[q], &me[q], &ke[q]);
-    if (w[q] < 0) return fail(STIG_EINVAL, "spatial factors: bad row pointers or columns");
+    // by diagonals when there are at most 5/4 as many as entries in the longest row
+    const int wr = spatial_ell(p->Ns, rowptr, col, valM, valK, q == 1, ELL_KU, nullptr, nullptr,
+                               nullptr);
+    if (wr < 0) return fail(STIG_EINVAL, "spatial factors: bad row pointers or columns");
+    const int nd = spatial_dia(p->Ns, rowptr, col, valM, valK, q == 1, ELL_KU, wr + wr / 4,
+                               &ce[q], &me[q], &ke[q]);
+    dia[q] = nd > 0;
+    w[q] = dia[q] ? nd
+                  : spatial_ell(p->Ns, rowptr, col, valM, valK, q == 1, ELL_KU, &ce[q], &me[q],
+                                &ke[q]);
   }
   p->ell_w[0] = p->ell_w[1] = 0;
   for (int q = 0; q < 2; ++q) {
@@ -1993,6 +2011,8 @@ stig_status stig_set_spatial_factors(stig_plan *p, const int64_t *rowptr, const 
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->ell_w[0] = w[0];
   p->ell_w[1] = w[1];
+  p->ell_dia[0] = dia[0];
+  p->ell_dia[1] = dia[1];
   p->csr_rowptr = nullptr;
   return STIG_OK;
 }

@@ -47,6 +47,17 @@ int spatial_ell(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
                 const double *valK, bool transpose, int align, std::vector<int32_t> *ce,
                 std::vector<double> *me, std::vector<double> *ke);
 
+// Diagonal layout of the same pair (or of its transpose pair) when it has few
+// distinct offsets o = col - row: offs[k] (ascending, padded to a multiple of
+// align with repeats of the last offset), and the values of diagonal k of row i
+// at k * n + i (zero where row i has no entry at offset o_k; duplicates
+// summed).  Returns the number of diagonals, 0 if it would exceed max_diags
+// (outputs untouched), -1 on a bad rowptr or column as spatial_ell.  With
+// offs == nullptr only the count is computed.
+int spatial_dia(int64_t n, const int64_t *rowptr, const int32_t *col, const double *valM,
+                const double *valK, bool transpose, int align, int max_diags,
+                std::vector<int32_t> *offs, std::vector<double> *me, std::vector<double> *ke);
+
 // Separable (rank-one, log-space) approximation of 3D samples [e3][e2][e1]:
 // C00 ~ phi1 phi2 phi3 and C_ll ~ Phi_l prod_{m != l} phi_m.
 void separate_3d(int n1, int n2, int n3, const double *C11, const double *C22, const double *C33,

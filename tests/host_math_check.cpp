@@ -261,6 +261,75 @@ int main() {
               -1,
           "ell rejects decreasing row pointers", 0, 0, 0.0);
   }
+  // diagonal layout: dense reconstruction of the matrix and its transpose (with a duplicate
+  // entry, summed), clamped padding, and the diagonal-count limit
+  {
+    const int64_t n = 9;
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> col;
+    Vec vM, vK, DM(n * n, 0.0), DK(n * n, 0.0);
+    const int offsets[4] = {-3, -1, 0, 2};
+    for (int64_t i = 0; i < n; ++i) {
+      for (int o : offsets) {
+        const int64_t j = i + o;
+        if (j < 0 || j >= n || (i + o) % 4 == 3) continue;  // a few holes away from the boundary
+        col.push_back((int32_t)j);
+        vM.push_back(1.0 + 0.5 * i - 0.25 * j);
+        vK.push_back(2.0 - 0.125 * i + 0.75 * j);
+        DM[i * n + j] += vM.back();
+        DK[i * n + j] += vK.back();
+      }
+      if (i == 4) {  // a duplicate of (4, 4)
+        col.push_back(4);
+        vM.push_back(0.5);
+        vK.push_back(-1.5);
+        DM[4 * n + 4] += 0.5;
+        DK[4 * n + 4] += -1.5;
+      }
+      rp[i + 1] = (int64_t)col.size();
+    }
+    for (int tr = 0; tr < 2; ++tr) {
+      std::vector<int32_t> offs;
+      Vec me, ke;
+      const int nd = spatial_dia(n, rp.data(), col.data(), vM.data(), vK.data(), tr == 1, 3, 64, &offs,
+                                 &me, &ke);
+      check(nd == 6 && offs.size() == 6 && me.size() == (size_t)(6 * n), "dia count", tr, nd, 0.0);
+      for (int k = 1; k < nd; ++k) check(offs[k] >= offs[k - 1], "dia offsets ascending", tr, k, offs[k]);
+      Vec RM(n * n, 0.0), RK(n * n, 0.0);
+      double pad = 0.0;
+      for (int64_t k = 0; k < nd; ++k)
+        for (int64_t i = 0; i < n; ++i) {
+          const size_t e = (size_t)(k * n + i);
+          const int64_t j = i + offs[k];
+          if (j < 0 || j >= n) {
+            pad = std::max(pad, std::fabs(me[e]) + std::fabs(ke[e]));
+            continue;
+          }
+          if (k > 0 && offs[k] == offs[k - 1]) {  // alignment padding repeats the last offset
+            pad = std::max(pad, std::fabs(me[e]) + std::fabs(ke[e]));
+            continue;
+          }
+          RM[i * n + j] += me[e];
+          RK[i * n + j] += ke[e];
+        }
+      check(pad == 0.0, "dia padding is zero", tr, 0, pad);
+      double err = 0.0;
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          const size_t src = tr ? (size_t)(j * n + i) : (size_t)(i * n + j);
+          err = std::max(err, std::fabs(RM[i * n + j] - DM[src]) + std::fabs(RK[i * n + j] - DK[src]));
+        }
+      check(err < 1e-15, "dia reproduces the matrix", tr, 0, err);
+    }
+    check(spatial_dia(n, rp.data(), col.data(), vM.data(), vK.data(), false, 1, 3, nullptr, nullptr,
+                      nullptr) == 0,
+          "dia gives up beyond the limit", 0, 0, 0.0);
+    std::vector<int32_t> bad = col;
+    bad[2] = -1;
+    check(spatial_dia(n, rp.data(), bad.data(), vM.data(), vK.data(), false, 1, 64, nullptr, nullptr,
+                      nullptr) == -1,
+          "dia rejects a bad column", 0, 0, 0.0);
+  }
   std::printf("%s: %d failed checks\n", fails ? "host math FAILED" : "host math ok", fails);
   return fails;
 }

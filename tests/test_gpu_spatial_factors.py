@@ -128,3 +128,44 @@ def test_factored_adjoint_solve_matches_dense_oracle(d, n_el):
     assert res <= 1e-10
     ref = np.linalg.solve(At, g.ravel())
     assert np.linalg.norm(lam - ref) / np.linalg.norm(ref) <= 1e-7
+
+
+def _dense_kron(Wt, Mt, Ms, Ks):
+    """W_t (x) M_s + M_t (x) K_s (eq. syst_mat with gamma = nu = 1), dense."""
+    return np.kron(Wt, Ms) + np.kron(Mt, Ks)
+
+
+def _csr_to_dense(rp, col, val, n):
+    D = np.zeros((n, n))
+    for r in range(n):
+        for e in range(rp[r], rp[r + 1]):
+            D[r, col[e]] += val[e]
+    return D
+
+
+@pytest.mark.parametrize("layout", ["diagonals", "rows"])
+@pytest.mark.parametrize("n_el", [6, 20])
+def test_nonsymmetric_spatial_factors_both_layouts(layout, n_el):
+    """Random non-symmetric values, on the annulus pattern (stored by diagonals) or on a
+    scattered random pattern (too many distinct offsets: stored by padded rows); plain
+    and transposed products against the dense Kronecker sum."""
+    w, a, plan, o = _setup(2, n_el, matvec=None)
+    Ns = plan.N_s
+    rng = np.random.default_rng(100 + n_el)
+    if layout == "diagonals":
+        rp, col = a.space[0], a.space[1]
+    else:
+        rows = [np.unique(rng.integers(0, Ns, size=1 + r % 9)) for r in range(Ns)]
+        rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+        col = np.concatenate(rows).astype(np.int32)
+    vK = rng.standard_normal(col.size)
+    vM = rng.standard_normal(col.size)
+    plan.set_spatial_factors((rp, col, vK, vM))
+    A = _dense_kron(a.Wt, a.Mt, _csr_to_dense(rp, col, vM, Ns), _csr_to_dense(rp, col, vK, Ns))
+    x = wl.random_tensor((2,) + w.shape, 21)
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
+    for r in range(2):
+        ref, reft = A @ x[r].ravel(), A.T @ x[r].ravel()
+        assert np.abs(y[r].ravel() - ref).max() <= 1e-13 * np.abs(ref).max()
+        assert np.abs(yt[r].ravel() - reft).max() <= 1e-13 * np.abs(reft).max()
