@@ -22,9 +22,9 @@ namespace stig {
 // Axis with inner stride > 1: one thread per column (o, i) and chunk of jc
 // entries along the axis (blockIdx.y), sliding a register window of 2P+1
 // entries, so each input entry is read once per chunk (plus a 2P halo) and
-// loads are coalesced across i.  Chunks only split the axis when there are too
-// few columns to fill the device.
-template <int P>
+// loads are coalesced across i.  Chunks (CH) only split the axis when there are
+// too few columns to fill the device; CH false is the one-chunk form (jc unused).
+template <int P, bool CH>
 __global__ void band_pass_strided(const double *__restrict__ in1, const double *__restrict__ in2,
                                   double *__restrict__ out1, double *__restrict__ out2,
                                   const double *__restrict__ Ba, const double *__restrict__ Bb,
@@ -32,7 +32,8 @@ __global__ void band_pass_strided(const double *__restrict__ in1, const double *
                                   int64_t total_cols, int jc) {
   constexpr int B = 2 * P + 1;
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = (int)blockIdx.y * jc, j1 = j0 + jc < n ? j0 + jc : n;
+  const int j0 = CH ? (int)blockIdx.y * jc : 0;
+  const int j1 = CH ? (j0 + jc < n ? j0 + jc : n) : n;
   if (c >= total_cols || j0 >= n) return;
   int64_t o = c / inner, i = c - o * inner;
   int64_t base = o * (int64_t)n * inner + i;
@@ -81,7 +82,7 @@ __global__ void band_pass_strided(const double *__restrict__ in1, const double *
 // r = f - (sum_m Bb[j][m] b[j+m-P] + Bc[j][m] a[j+m-P]) and this block's share
 // of r . r in partial[blockIdx.y * gridDim.x + blockIdx.x] (fixed-order block
 // reduction).
-template <int P>
+template <int P, bool CH>
 __global__ void __launch_bounds__(256)
 time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
                    const double *__restrict__ f, double *__restrict__ r,
@@ -90,7 +91,8 @@ time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
   constexpr int B = 2 * P + 1;
   __shared__ double red[4];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = (int)blockIdx.y * jc, j1 = j0 + jc < n ? j0 + jc : n;
+  const int j0 = CH ? (int)blockIdx.y * jc : 0;
+  const int j1 = CH ? (j0 + jc < n ? j0 + jc : n) : n;
   double acc = 0.0;
   if (c < total_cols) {
     const int64_t o = c / inner, i = c - o * inner;
@@ -128,7 +130,8 @@ time_pass_residual(const double *__restrict__ a, const double *__restrict__ b,
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0)
-    partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    partial[CH ? (int64_t)blockIdx.y * gridDim.x + blockIdx.x : (int64_t)blockIdx.x] =
+        red[0] + red[1] + red[2] + red[3];
 }
 
 // Contiguous axis (inner == 1): one thread per output entry; the 2P+1 reads

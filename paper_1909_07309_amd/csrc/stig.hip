@@ -872,8 +872,12 @@ stig_status band_pass_p(stig_plan *p, const double *in1, const double *in2, doub
   } else {
     const int64_t cols = total / n;
     const int ch = axis_chunks(cols, n, P), jc = (n + ch - 1) / ch;
-    hipLaunchKernelGGL(band_pass_strided<P>, dim3(grid_for(cols, 256), ch), dim3(256), 0,
-                       p->stream, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, cols, jc);
+    if (ch > 1)
+      hipLaunchKernelGGL((band_pass_strided<P, true>), dim3(grid_for(cols, 256), ch), dim3(256), 0,
+                         p->stream, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, cols, jc);
+    else
+      hipLaunchKernelGGL((band_pass_strided<P, false>), dim3(grid_for(cols, 256)), dim3(256), 0,
+                         p->stream, in1, in2, out1, out2, Ba, Bb, Bc, n, inner, cols, n);
   }
   HIP_TRY(hipGetLastError());
   return STIG_OK;
@@ -1033,9 +1037,14 @@ stig_status launch_time_residual(stig_plan *p, const double *a, const double *b,
   const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
   const int jc = (p->nt + chunks - 1) / chunks;
   ProfScope ps(p, STIG_K_BAND_PASS, (double)p->N * 8 * 4);
-  hipLaunchKernelGGL(time_pass_residual<P>, dim3((unsigned)blocks, chunks), dim3(256), 0,
-                     p->stream, a, b, f, r, p->tnM.as<double>(), gW, p->nt, p->Ns, p->Ns, jc,
-                     partial);
+  if (chunks > 1)
+    hipLaunchKernelGGL((time_pass_residual<P, true>), dim3((unsigned)blocks, chunks), dim3(256), 0,
+                       p->stream, a, b, f, r, p->tnM.as<double>(), gW, p->nt, p->Ns, p->Ns, jc,
+                       partial);
+  else
+    hipLaunchKernelGGL((time_pass_residual<P, false>), dim3((unsigned)blocks), dim3(256), 0,
+                       p->stream, a, b, f, r, p->tnM.as<double>(), gW, p->nt, p->Ns, p->Ns, jc,
+                       partial);
   HIP_TRY(hipGetLastError());
   return STIG_OK;
 }
