@@ -15,7 +15,6 @@
 #include <cstring>
 #include <numeric>
 #include <stdexcept>
-#include <unordered_set>
 #include <vector>
 
 #include "stig_internal.h"
@@ -434,15 +433,18 @@ int spatial_dia(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
   for (int64_t e = 0; e < nnz; ++e)
     if (col[e] < 0 || col[e] >= n) return -1;
   // distinct offsets of the stored matrix (transpose: offsets negated)
-  std::unordered_set<int64_t> seen;
+  // sorted set of the offsets seen so far (at most max_diags + 1 of them)
+  std::vector<int64_t> o;
   for (int64_t r = 0; r < n; ++r)
     for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      seen.insert(transpose ? r - col[e] : col[e] - r);
-      if ((int64_t)seen.size() > max_diags) return 0;
+      const int64_t d = transpose ? r - col[e] : col[e] - r;
+      auto it = std::lower_bound(o.begin(), o.end(), d);
+      if (it == o.end() || *it != d) {
+        o.insert(it, d);
+        if ((int64_t)o.size() > max_diags) return 0;
+      }
     }
-  std::vector<int64_t> o(seen.begin(), seen.end());
   if (o.empty()) o.push_back(0);
-  std::sort(o.begin(), o.end());
   align = std::max(align, 1);
   const int64_t nd = ((int64_t)o.size() + align - 1) / align * align;
   if (nd > max_diags) return 0;
