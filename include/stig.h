@@ -153,8 +153,11 @@ stig_status stig_set_A_csr(stig_plan *plan, const int64_t *rowptr,
  * both: rowptr (N_s + 1 int64, rowptr[0] = 0, non-decreasing), col (int32 in
  * [0, N_s), any order within a row), valM, valK (FP64), spatial unknown order
  * [x_d]..[x_1].  The library keeps its own device copies of M_s, K_s and of
- * their transposes in a padded column-major layout: 2 x width x N_s x 20 bytes,
- * width = the longest row (or column).  stig_matvec_A then runs one sparse
+ * their transposes: by diagonals (2 x diagonals x N_s x 16 bytes) when the
+ * pattern has at most 5/4 as many distinct offsets col - row as entries in its
+ * longest row, as every tensor-product spline pattern does, else as padded rows
+ * (2 x width x N_s x 20 bytes, width = the longest row or column); duplicate
+ * entries add up.  stig_matvec_A then runs one sparse
  * spatial pass per time level and one banded pass along t; transposed products
  * are supported.  Synchronises.  rowptr = NULL removes the factors.  Setting
  * the factors clears a matrix given to stig_set_A_csr, and setting that matrix
