@@ -388,6 +388,82 @@ spatial_dia_pair(const double *__restrict__ x, double *__restrict__ a, double *_
   }
 }
 
+// The diagonal form with x staged in LDS, for patterns whose offsets span
+// little: a block's rows [i0, i0 + 256) read columns [i0 + omin, i0 + 255 +
+// omax] only, so the block copies that range of its TT slices to LDS with
+// coalesced loads and gathers from there (the gathers of the global form are
+// bound by the L1 access rate).  Dynamic LDS: TT * span doubles.
+template <int TT, int KU>
+__global__ void __launch_bounds__(256)
+spatial_dia_lds(const double *__restrict__ x, double *__restrict__ a, double *__restrict__ b,
+                const int32_t *__restrict__ offs, const double *__restrict__ me,
+                const double *__restrict__ ke, int ndiag, int64_t ns, int64_t nslices, int nchunks,
+                int omin, int span) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *xl = reinterpret_cast<double *>(smem);  // [TT][span]
+  const unsigned nb = gridDim.x, q = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8;
+  const unsigned g = xcd * q + (xcd < rem ? xcd : rem) + blockIdx.x / 8;
+  const int64_t i0 = (int64_t)(g / nchunks) * blockDim.x;
+  const int64_t i = i0 + threadIdx.x;
+  const int64_t s0 = (int64_t)(g % nchunks) * TT;
+  const int nt = (int)(nslices - s0 < TT ? nslices - s0 : TT);
+  // staged columns [cb, cb + span), clamped to the matrix
+  int64_t cb = i0 + omin;
+  if (cb < 0) cb = 0;
+  const double *xs = x + s0 * ns;
+  constexpr int FU = 8;
+  for (int e0 = threadIdx.x; e0 < TT * span; e0 += 256 * FU) {
+    double v[FU];
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int e = e0 + u * 256;
+      const int t = e / span, j = e - t * span;
+      const int64_t col = cb + j;
+      const bool ok = e < TT * span && t < nt && col < ns;
+      v[u] = xs[ok ? (int64_t)t * ns + col : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int e = e0 + u * 256;
+      if (e < TT * span) xl[e] = v[u];
+    }
+  }
+  __syncthreads();
+  if (i >= ns) return;
+  cptr<int32_t> co = as_const(offs);
+  double sa[TT], sb[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) sa[t] = sb[t] = 0.0;
+  for (int k0 = 0; k0 < ndiag; k0 += KU) {
+    int c[KU];
+    double mv[KU], kv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int64_t e = (int64_t)(k0 + u) * ns + i;
+      mv[u] = me[e];
+      kv[u] = ke[e];
+      int64_t cc = i + co[k0 + u];
+      cc = cc < 0 ? 0 : (cc >= ns ? ns - 1 : cc);
+      c[u] = (int)(cc - cb);
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const double xv = xl[t * span + c[u]];
+        sa[t] += mv[u] * xv;
+        sb[t] += kv[u] * xv;
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    if (t < nt) {
+      a[(s0 + t) * ns + i] = sa[t];
+      b[(s0 + t) * ns + i] = sb[t];
+    }
+  }
+}
+
 // Spatial part of the matvec in one pass over each (rhs, t) slice (d = 2, 3):
 //   a = x x_1 M_1 x_2 M_2 x_3 M_3,   b = x x_1 K_1 x_2 M_2 x_3 M_3
 //       + x x_1 M_1 x_2 K_2 x_3 M_3 + x x_1 M_1 x_2 M_2 x_3 K_3

@@ -132,6 +132,7 @@ struct stig_plan {
   // (ell_dia, offsets in ellC) or padded column-major rows (columns in ellC)
   int ell_w[2] = {0, 0};
   bool ell_dia[2] = {false, false};
+  int ell_omin[2] = {0, 0}, ell_omax[2] = {0, 0};  // offset range (diagonal form)
   DevBuf ellC[2], ellM[2], ellK[2];
   // scratch
   DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, AZ, w, tmp, partial, small, flag, lift0, lift1;
@@ -983,7 +984,18 @@ stig_status launch_spatial_ell(stig_plan *p, const double *x, double *a, double 
     return fail(STIG_EINVAL, "too many blocks for the sparse spatial pass");
   ProfScope ps(p, STIG_K_CSR,
                (double)p->N * nrhs * 24 + (double)p->ell_w[q] * p->Ns * (p->ell_dia[q] ? 16 : 20));
-  if (p->ell_dia[q])
+  // diagonal form with a narrow column span: x staged in LDS, 4 slices per block
+  constexpr int TL = 4;
+  const int64_t span = 256 + (int64_t)p->ell_omax[q] - p->ell_omin[q];
+  if (p->ell_dia[q] && span * TL * (int64_t)sizeof(double) <= 48 * 1024) {
+    const int64_t lch = (slices + TL - 1) / TL;
+    if (lch * rblocks >= ((int64_t)1 << 31))
+      return fail(STIG_EINVAL, "too many blocks for the sparse spatial pass");
+    hipLaunchKernelGGL((spatial_dia_lds<TL, ELL_KU>), dim3((unsigned)(lch * rblocks)), dim3(256),
+                       (size_t)(span * TL * sizeof(double)), p->stream, x, a, b,
+                       p->ellC[q].as<int32_t>(), p->ellM[q].as<double>(), p->ellK[q].as<double>(),
+                       p->ell_w[q], p->Ns, slices, (int)lch, p->ell_omin[q], (int)span);
+  } else if (p->ell_dia[q])
     hipLaunchKernelGGL((spatial_dia_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)),
                        dim3(256), 0, p->stream, x, a, b, p->ellC[q].as<int32_t>(),
                        p->ellM[q].as<double>(), p->ellK[q].as<double>(), p->ell_w[q], p->Ns,
@@ -2022,6 +2034,10 @@ stig_status stig_set_spatial_factors(stig_plan *p, const int64_t *rowptr, const 
   p->ell_w[1] = w[1];
   p->ell_dia[0] = dia[0];
   p->ell_dia[1] = dia[1];
+  for (int q = 0; q < 2; ++q) {
+    p->ell_omin[q] = dia[q] ? ce[q].front() : 0;  // offsets ascending
+    p->ell_omax[q] = dia[q] ? ce[q].back() : 0;
+  }
   p->csr_rowptr = nullptr;
   return STIG_OK;
 }
