@@ -294,7 +294,12 @@ constexpr int GEMM2_THREADS = 256;
 // entries lie in one period of nscale, so the modulo is taken once per column.
 // The scaled form loads each strip just before multiplying it (no prefetch of
 // the next strip: the factors take those registers).  SC false: both null.
-template <typename Tin, typename Tout, typename TC, int NC, bool SC>
+// RS > 1: the full 16-row tiles are split into RS parts, one per block of a
+// group of RS consecutive blocks (numbered so that a group shares an XCD), and
+// each block holds only its part of Op (plus the fringe rows, computed by the
+// last part) in LDS: smaller blocks, more of them per CU, shorter MFMA chains.
+// The grid is then a multiple of RS.
+template <typename Tin, typename Tout, typename TC, int NC, bool SC, int RS = 1>
 __global__ void __launch_bounds__(GEMM2_THREADS)
 mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
                 const typename Mfma<TC>::elem *__restrict__ Op, int n_arg, int64_t inner,
@@ -304,12 +309,25 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   typedef typename MF::elem E;
   constexpr int NMAX = NC ? NC : GEMM2_MAX_N;
   constexpr int KSMAX = (NMAX + MF::KSTEP - 1) / MF::KSTEP;
-  constexpr int QMAX = NMAX / 16;
+  constexpr int QALL = NMAX / 16;
+  static_assert(QALL % RS == 0, "row tiles must split evenly");
+  constexpr int QMAX = QALL / RS;  // full row tiles of this block
   const int n = NC ? NC : n_arg;
   extern __shared__ __align__(16) unsigned char smem[];
   // Op tile in LDS, sized for NMAX (the runtime-n variant reads the full NMAX
-  // range unguarded; every entry with j >= n or k >= n is zero)
-  constexpr int NROWS = (NMAX + 15) / 16 * 16;
+  // range unguarded; every entry with j >= n or k >= n is zero).  Local row j
+  // is Op row row0 + j below 16 QMAX, fringe row 16 QALL + (j - 16 QMAX) above.
+  constexpr int NROWS = RS == 1 ? (NMAX + 15) / 16 * 16 : 16 * QMAX + (NMAX - 16 * QALL);
+  unsigned gb = blockIdx.x;
+  if (RS > 1) {
+    const unsigned nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, xcd = blockIdx.x % 8;
+    gb = xcd * q8 + (xcd < r8 ? xcd : r8) + blockIdx.x / 8;
+  }
+  const int part = RS > 1 ? (int)(gb % RS) : 0;
+  const bool lastp = part == RS - 1;
+  const int row0 = 16 * QMAX * part;
+  const int64_t sblk = RS > 1 ? (int64_t)(gb / RS) : (int64_t)blockIdx.x;
+  const int64_t nsblk = RS > 1 ? (int64_t)(gridDim.x / RS) : (int64_t)gridDim.x;
   constexpr int KPADM = KSMAX * MF::KSTEP;
   const int ld = lds_ld<TC>(NMAX);
   E *opl = reinterpret_cast<E *>(smem);  // [NROWS][ld]
@@ -323,8 +341,9 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     for (int u = 0; u < FU; ++u) {
       const int e = e0 + u * GEMM2_THREADS;
       const int j = e / KPADM, k = e - j * KPADM;
-      const bool ok = e < FILL && j < n && k < n;
-      v[u] = Op[ok ? (size_t)j * n + k : 0];
+      const int gj = j < 16 * QMAX ? row0 + j : 16 * QALL + (j - 16 * QMAX);
+      const bool ok = e < FILL && gj < n && k < n;
+      v[u] = Op[ok ? (size_t)gj * n + k : 0];
       if (!ok) v[u] = MF::zero();
     }
 #pragma unroll
@@ -340,7 +359,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   const int64_t slab = (int64_t)n * inner;
   const uint32_t uinner = (uint32_t)inner;
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t wstride = (int64_t)gridDim.x * (GEMM2_THREADS / 64);
+  const int64_t wstride = nsblk * (GEMM2_THREADS / 64);
   // column c -> (base address, stride along the contracted axis)
   auto locate = [&](int64_t c, int64_t &base, int64_t &step) {
     if (inner == 1) {
@@ -435,11 +454,13 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       __builtin_amdgcn_sched_barrier(0);
     }
     // fringe rows on the vector ALU from the B registers (before the stores,
-    // so that the B registers are free while output factors are loaded)
-    constexpr int NFR = NMAX - 16 * QMAX;
-    double fr[NFR > 0 ? NFR : 1];
+    // so that the B registers are free while output factors are loaded); the
+    // last part only
+    constexpr int NFR = NMAX - 16 * QALL;
+    double fr[NFR > 0 ? NFR : 1] = {};
 #pragma unroll
     for (int q = 0; q < NFR; ++q) {
+      if (!lastp) break;
       const E *orow = opl + (size_t)(16 * QMAX + q) * ld + kg * MF::KPL;
       double sum = 0.0;
 #pragma unroll
@@ -464,12 +485,12 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       for (int t = 0; t < QMAX; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          int j = 16 * t + MF::out_row(kg, v);
+          int j = row0 + 16 * t + MF::out_row(kg, v);
           sc[t][v] = out_scale[j < n ? sb + (int64_t)j * step : sb];
         }
 #pragma unroll
       for (int q = 0; q < NFR; ++q) {
-        int j = 16 * QMAX + q;
+        int j = 16 * QALL + q;
         sf[q] = out_scale[j < n ? sb + (int64_t)j * step : sb];
       }
 #pragma unroll
@@ -483,16 +504,16 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     for (int t = 0; t < QMAX; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int j = 16 * t + MF::out_row(kg, v);
+        int j = row0 + 16 * t + MF::out_row(kg, v);
         if (j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(yv[t][v]);
       }
 #pragma unroll
     for (int q = 0; q < NFR; ++q) {
-      int j = 16 * QMAX + q;
-      if (kg == 0 && j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(fr[q]);
+      int j = 16 * QALL + q;
+      if (lastp && kg == 0 && j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(fr[q]);
     }
   };
-  int64_t strip = (int64_t)blockIdx.x * (GEMM2_THREADS / 64) + wave;
+  int64_t strip = sblk * (GEMM2_THREADS / 64) + wave;
   if (SC) {
     for (; strip < nstrips; strip += wstride) {
       E bv[KSMAX][MF::KPL];

@@ -349,12 +349,15 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   const int nc = sc ? ((n == 32 || n == 130) ? n : 0)
                     : ((n == 65 || n == 49 || n == 32 || n == 130) ? n : 0);
   if (nc != 0 || n <= GEMM2_MAX_N) {
-    // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N
+    // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N;
+    // n = 130 splits its 8 full row tiles over 2 blocks (rows: 64 + 2 fringe)
     const int nm = nc ? nc : GEMM2_MAX_N;
-    size_t lds = (size_t)round_up(nm, 16) * lds_ld<TC>(nm) * sizeof(E);
+    const int rs = nc == 130 ? 2 : 1;
+    const int rows = rs == 1 ? round_up(nm, 16) : 16 * (nm / 16 / rs) + nm % 16;
+    size_t lds = (size_t)rows * lds_ld<TC>(nm) * sizeof(E);
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
-    unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID);
+    unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID) * rs;
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
     static size_t configured[10] = {};  // per kernel of this type triple
     auto go = [&](auto kern, int slot) -> stig_status {
@@ -370,13 +373,13 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     };
     if (sc) {
       if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, true>, 5);
-      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, true>, 6);
+      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, true, 2>, 6);
       return go(mode_gemm_small<Tin, Tout, TC, 0, true>, 7);
     }
     if (nc == 65) return go(mode_gemm_small<Tin, Tout, TC, 65, false>, 0);
     if (nc == 49) return go(mode_gemm_small<Tin, Tout, TC, 49, false>, 1);
     if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, false>, 2);
-    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false>, 3);
+    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false, 2>, 3);
     return go(mode_gemm_small<Tin, Tout, TC, 0, false>, 4);
   }
   const int jt = (n + 15) / 16;

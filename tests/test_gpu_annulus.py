@@ -60,6 +60,17 @@ def test_annulus_full_size_csr_and_solve():
     y = plan.matvec_A(_dev(x)).cpu().numpy()
     ref = o.matvec(x)
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the FP64 / FP32 A-hat^G apply at n_s = 130 (mode products split over two
+    # blocks per strip group, diagonal scaling fused), against the oracle's
+    # fast diagonalization; the FP64 bar grows like n_s^2 (see the cube tests)
+    ref_s = o.preconditioner().apply(x)
+    s64 = plan.apply_Pinv(_dev(x)).cpu().numpy()
+    assert np.abs(s64 - ref_s).max() <= 1e-12 * (130 / 65) ** 2 * np.abs(ref_s).max()
+    s32 = plan.apply_Pinv(_dev(x), prec="fp32").cpu().numpy()
+    assert np.abs(s32 - ref_s).max() <= 1e-4 * np.abs(ref_s).max()
+    st = plan.apply_Pinv(_dev(x), transpose=True).cpu().numpy()
+    ref_t = o.preconditioner().apply(x, transpose=True)
+    assert np.abs(st - ref_t).max() <= 1e-12 * (130 / 65) ** 2 * np.abs(ref_t).max()
     f = a.source()
     u, info = plan.gmres_solve(f, restart=30, rtol=1e-8, maxit=300, flexible=True, prec="fp32")
     f_ref = o.source()
