@@ -1,5 +1,6 @@
 """Quarter-annulus workload on the HIP side: variable conductivity and heat capacity,
-full space-time CSR system matrix, geometry-aware preconditioner (Section 4.3).
+A x from the sparse spatial factors and the time bands (Section 4.5) or from the
+full space-time CSR, geometry-aware preconditioner (Section 4.3).
 
 Geometry (problem data): the polar map F(eta) = ((1+eta_1) cos(pi eta_2/2),
 (1+eta_1) sin(pi eta_2/2)) onto the quarter annulus with radii 1 and 2.  Its

@@ -1,6 +1,7 @@
 """Extruded quarter-annulus workload on the HIP side: the 3D geometry-aware
-preconditioner of Section 4.3 with variable conductivity and heat capacity, a
-full space-time CSR system matrix and the 3D separation of the coefficients.
+preconditioner of Section 4.3 with variable conductivity and heat capacity, A x
+from the sparse spatial factors (Section 4.5) or a full space-time CSR, and the
+3D separation of the coefficients.
 
 Geometry (problem data): F(eta) = ((1+eta_1) cos(pi eta_2/2), (1+eta_1)
 sin(pi eta_2/2), eta_3), the quarter annulus with radii 1 and 2 extruded over
