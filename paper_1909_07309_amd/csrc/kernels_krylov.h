@@ -90,8 +90,8 @@ krylov_dots(const double *__restrict__ V, int64_t ldv, int nv, const double *__r
 
 // w_new = w + sign * sum_i coef[i] V_i (coef in device memory; w == nullptr
 // reads as zero), written as dst = scale * w_new (dst may be w); then, if with_dots, partial dots
-// V_i . w_new and w_new . w_new as in krylov_dots (with_norm = 1).  The dot
-// products re-read V_i[e] right after the update read it (cache hits).
+// V_i . w_new and w_new . w_new as in krylov_dots (with_norm = 1), from the
+// V_i[e] values the update loaded.
 template <int NV>
 __global__ void __launch_bounds__(KRY_BLOCK)
 krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *__restrict__ coef,
@@ -114,6 +114,9 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
       const int64_t e = e0 + u * stride;
       we[u] = (w && e < N) ? w[e] : 0.0;
     }
+    // the basis entries stay in registers for the dot products below (for large
+    // bases a second read would miss the caches)
+    double vv[NV][U];
 #pragma unroll
     for (int i = 0; i < NV; ++i)
       if (i < nv) {
@@ -122,7 +125,8 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t e = e0 + u * stride;
-          we[u] += c * (e < N ? vi[e] : 0.0);
+          vv[i][u] = e < N ? vi[e] : 0.0;
+          we[u] += c * vv[i][u];
         }
       }
 #pragma unroll
@@ -134,12 +138,8 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
 #pragma unroll
       for (int i = 0; i < NV; ++i)
         if (i < nv) {
-          const double *vi = V + i * ldv;
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int64_t e = e0 + u * stride;
-            acc[i] += (e < N ? vi[e] : 0.0) * we[u];
-          }
+          for (int u = 0; u < U; ++u) acc[i] += vv[i][u] * we[u];
         }
 #pragma unroll
       for (int u = 0; u < U; ++u) acc[NV] += we[u] * we[u];
