@@ -464,6 +464,80 @@ spatial_dia_lds(const double *__restrict__ x, double *__restrict__ a, double *__
   }
 }
 
+// The diagonal form for wide patterns whose offsets come in runs of
+// consecutive values (a tensor-product pattern: runs of 2p+1 along x_1).  For
+// run g (first offset goff[g], length glen[g] <= ELL_RUN_MAX, first diagonal
+// gdiag[g]) a wavefront loads the window x[i0w + goff[g] .. i0w + goff[g] + 63 +
+// glen[g] - 1] of each of its TT slices once into its own LDS and every lane
+// reads its glen[g] shifted values from there, instead of one L1-bound gather
+// per diagonal.  Diagonals are summed in the same order as spatial_dia_pair.
+// Window indices are clamped into [0, ns): such entries only meet zero values.
+constexpr int ELL_RUN_MAX = 32;
+
+template <int TT>
+__global__ void __launch_bounds__(256)
+spatial_dia_runs(const double *__restrict__ x, double *__restrict__ a, double *__restrict__ b,
+                 const int32_t *__restrict__ runs, const double *__restrict__ me,
+                 const double *__restrict__ ke, int nruns, int64_t ns, int64_t nslices,
+                 int nchunks) {
+  __shared__ double win[4][TT][64 + ELL_RUN_MAX];
+  const unsigned nb = gridDim.x, q = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8;
+  const unsigned g = xcd * q + (xcd < rem ? xcd : rem) + blockIdx.x / 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0w = (int64_t)(g / nchunks) * blockDim.x + wave * 64;
+  const int64_t i = i0w + lane;
+  const int64_t s0 = (int64_t)(g % nchunks) * TT;
+  const int nt = (int)(nslices - s0 < TT ? nslices - s0 : TT);
+  if (i0w >= ns) return;  // whole wavefront past the rows (no block barrier below)
+  const bool valid = i < ns;
+  const int64_t iv = valid ? i : 0;
+  const double *xs = x + s0 * ns;
+  cptr<int32_t> cr = as_const(runs);  // [nruns][3]: first offset, length, first diagonal
+  double sa[TT], sb[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) sa[t] = sb[t] = 0.0;
+  auto clampc = [&](int64_t c) { return c < 0 ? (int64_t)0 : (c >= ns ? ns - 1 : c); };
+  for (int r = 0; r < nruns; ++r) {
+    const int o = cr[3 * r], len = cr[3 * r + 1], k0 = cr[3 * r + 2];
+    const int64_t c0 = clampc(i0w + o + lane), c1 = clampc(i0w + o + 64 + lane);
+    double w0[TT], w1[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const int tt = t < nt ? t : 0;
+      w0[t] = xs[(int64_t)tt * ns + c0];
+      w1[t] = lane < len - 1 ? xs[(int64_t)tt * ns + c1] : 0.0;
+    }
+    // the previous run's reads of the window are done before it is overwritten
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      win[wave][t][lane] = w0[t];
+      if (lane < ELL_RUN_MAX) win[wave][t][64 + lane] = w1[t];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int d = 0; d < len; ++d) {
+      const int64_t e = (int64_t)(k0 + d) * ns + iv;
+      const double mv = me[e], kv = ke[e];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const double xv = win[wave][t][lane + d];
+        sa[t] += mv * xv;
+        sb[t] += kv * xv;
+      }
+    }
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    if (t < nt) {
+      a[(s0 + t) * ns + i] = sa[t];
+      b[(s0 + t) * ns + i] = sb[t];
+    }
+  }
+}
+
 // Spatial part of the matvec in one pass over each (rhs, t) slice (d = 2, 3):
 //   a = x x_1 M_1 x_2 M_2 x_3 M_3,   b = x x_1 K_1 x_2 M_2 x_3 M_3
 //       + x x_1 M_1 x_2 K_2 x_3 M_3 + x x_1 M_1 x_2 M_2 x_3 K_3

@@ -133,6 +133,8 @@ struct stig_plan {
   int ell_w[2] = {0, 0};
   bool ell_dia[2] = {false, false};
   int ell_omin[2] = {0, 0}, ell_omax[2] = {0, 0};  // offset range (diagonal form)
+  int ell_nruns[2] = {0, 0};  // runs of consecutive offsets (diagonal form)
+  DevBuf ellR[2];             // [run][3]: first offset, length, first diagonal
   DevBuf ellC[2], ellM[2], ellK[2];
   // scratch
   DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, AZ, w, tmp, partial, small, flag, lift0, lift1;
@@ -998,6 +1000,11 @@ stig_status launch_spatial_ell(stig_plan *p, const double *x, double *a, double 
                        (size_t)(span * TL * sizeof(double)), p->stream, x, a, b,
                        p->ellC[q].as<int32_t>(), p->ellM[q].as<double>(), p->ellK[q].as<double>(),
                        p->ell_w[q], p->Ns, slices, (int)lch, p->ell_omin[q], (int)span);
+  } else if (p->ell_dia[q] && 2 * p->ell_nruns[q] <= p->ell_w[q]) {
+    // wide span, offsets in runs: one window load per run and wavefront
+    hipLaunchKernelGGL((spatial_dia_runs<TT>), dim3((unsigned)(chunks * rblocks)), dim3(256), 0,
+                       p->stream, x, a, b, p->ellR[q].as<int32_t>(), p->ellM[q].as<double>(),
+                       p->ellK[q].as<double>(), p->ell_nruns[q], p->Ns, slices, (int)chunks);
   } else if (p->ell_dia[q])
     hipLaunchKernelGGL((spatial_dia_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)),
                        dim3(256), 0, p->stream, x, a, b, p->ellC[q].as<int32_t>(),
@@ -2006,6 +2013,8 @@ stig_status stig_set_spatial_factors(stig_plan *p, const int64_t *rowptr, const 
       p->ellC[q].release();
       p->ellM[q].release();
       p->ellK[q].release();
+      p->ellR[q].release();
+      p->ell_nruns[q] = 0;
     }
     return STIG_OK;
   }
@@ -2040,6 +2049,23 @@ stig_status stig_set_spatial_factors(stig_plan *p, const int64_t *rowptr, const 
   for (int q = 0; q < 2; ++q) {
     p->ell_omin[q] = dia[q] ? ce[q].front() : 0;  // offsets ascending
     p->ell_omax[q] = dia[q] ? ce[q].back() : 0;
+    p->ell_nruns[q] = 0;
+    if (!dia[q]) continue;
+    // maximal runs of consecutive offsets, at most ELL_RUN_MAX diagonals each
+    std::vector<int32_t> runs;
+    for (int k = 0; k < w[q]; ++k) {
+      const int nr = (int)runs.size() / 3;
+      if (nr > 0 && ce[q][k] == ce[q][k - 1] + 1 && runs[3 * (nr - 1) + 1] < ELL_RUN_MAX) {
+        ++runs[3 * (nr - 1) + 1];
+      } else {
+        runs.push_back(ce[q][k]);
+        runs.push_back(1);
+        runs.push_back(k);
+      }
+    }
+    STIG_TRY(upload(p->ellR[q], runs, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->ell_nruns[q] = (int)runs.size() / 3;
   }
   p->csr_rowptr = nullptr;
   return STIG_OK;
@@ -2245,7 +2271,8 @@ size_t stig_plan_device_bytes(const stig_plan *p) {
   for (int l = 0; l < 3; ++l) {
     t += p->U64[l].bytes + p->UT64[l].bytes + p->U32[l].bytes + p->UT32[l].bytes +
          p->U16[l].bytes + p->UT16[l].bytes + p->sK[l].bytes + p->sM[l].bytes;
-  for (int q = 0; q < 2; ++q) t += p->ellC[q].bytes + p->ellM[q].bytes + p->ellK[q].bytes;
+  for (int q = 0; q < 2; ++q)
+    t += p->ellC[q].bytes + p->ellM[q].bytes + p->ellK[q].bytes + p->ellR[q].bytes;
     for (int q = 0; q < 3; ++q)
       t += p->hFE[q][l].bytes + p->hFO[q][l].bytes + p->hBE[q][l].bytes + p->hBO[q][l].bytes;
   }

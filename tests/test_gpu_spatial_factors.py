@@ -194,3 +194,37 @@ def test_factored_batched_solve_matches_one_by_one(d, n_el):
         res = np.linalg.norm(fh[r].ravel() - A @ x) / np.linalg.norm(fh[r])
         assert res <= 1e-9
         assert np.linalg.norm(x - y) / np.linalg.norm(y) <= 1e-7
+
+
+def test_isolated_wide_offsets_plain_diagonal_form():
+    """A pattern with five isolated offsets spanning most of the grid (stored by diagonals,
+    too wide to stage in LDS, runs of length one), plain and transposed, against sparse
+    Kronecker products of the plan's time factors."""
+    import scipy.sparse as sp
+    w, a, plan, o = _setup(3, 12, matvec=None)
+    Ns = plan.N_s
+    rng = np.random.default_rng(7)
+    offsets = (-(Ns // 2), -7, 0, 5, Ns // 3)
+    rows, cols = [], []
+    for r in range(Ns):
+        for d in offsets:
+            if 0 <= r + d < Ns and (r * 7 + d) % 5 != 1:
+                rows.append(r)
+                cols.append(r + d)
+    rows, cols = np.array(rows), np.array(cols)
+    vK, vM = rng.standard_normal(rows.size), rng.standard_normal(rows.size)
+    Ks = sp.csr_matrix((vK, (rows, cols)), shape=(Ns, Ns))
+    Ms = sp.csr_matrix((vM, (rows, cols)), shape=(Ns, Ns))
+    Ks.sort_indices()
+    Ms.sort_indices()
+    assert np.array_equal(Ks.indptr, Ms.indptr) and np.array_equal(Ks.indices, Ms.indices)
+    plan.set_spatial_factors((Ks.indptr.astype(np.int64), Ks.indices.astype(np.int32), Ks.data,
+                              Ms.data))
+    A = (sp.kron(sp.csr_matrix(a.Wt), Ms) + sp.kron(sp.csr_matrix(a.Mt), Ks)).tocsr()
+    x = wl.random_tensor((2,) + w.shape, 23)
+    y = plan.matvec_A(_dev(x)).cpu().numpy()
+    yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
+    for r in range(2):
+        ref, reft = A @ x[r].ravel(), A.T @ x[r].ravel()
+        assert np.abs(y[r].ravel() - ref).max() <= 1e-13 * np.abs(ref).max()
+        assert np.abs(yt[r].ravel() - reft).max() <= 1e-13 * np.abs(reft).max()
