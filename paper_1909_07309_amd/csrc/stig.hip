@@ -989,10 +989,16 @@ stig_status launch_spatial_ell(stig_plan *p, const double *x, double *a, double 
     return fail(STIG_EINVAL, "too many blocks for the sparse spatial pass");
   ProfScope ps(p, STIG_K_CSR,
                (double)p->N * nrhs * 24 + (double)p->ell_w[q] * p->Ns * (p->ell_dia[q] ? 16 : 20));
-  // diagonal form with a narrow column span: x staged in LDS, 4 slices per block
+  // diagonal form: offsets in runs of consecutive values (one window load per
+  // run and wavefront), else a narrow column span staged in LDS (4 slices per
+  // block), else plain gathers
   constexpr int TL = 4;
   const int64_t span = 256 + (int64_t)p->ell_omax[q] - p->ell_omin[q];
-  if (p->ell_dia[q] && span * TL * (int64_t)sizeof(double) <= 48 * 1024) {
+  if (p->ell_dia[q] && 2 * p->ell_nruns[q] <= p->ell_w[q]) {
+    hipLaunchKernelGGL((spatial_dia_runs<TT>), dim3((unsigned)(chunks * rblocks)), dim3(256), 0,
+                       p->stream, x, a, b, p->ellR[q].as<int32_t>(), p->ellM[q].as<double>(),
+                       p->ellK[q].as<double>(), p->ell_nruns[q], p->Ns, slices, (int)chunks);
+  } else if (p->ell_dia[q] && span * TL * (int64_t)sizeof(double) <= 48 * 1024) {
     const int64_t lch = (slices + TL - 1) / TL;
     if (lch * rblocks >= ((int64_t)1 << 31))
       return fail(STIG_EINVAL, "too many blocks for the sparse spatial pass");
@@ -1000,11 +1006,6 @@ stig_status launch_spatial_ell(stig_plan *p, const double *x, double *a, double 
                        (size_t)(span * TL * sizeof(double)), p->stream, x, a, b,
                        p->ellC[q].as<int32_t>(), p->ellM[q].as<double>(), p->ellK[q].as<double>(),
                        p->ell_w[q], p->Ns, slices, (int)lch, p->ell_omin[q], (int)span);
-  } else if (p->ell_dia[q] && 2 * p->ell_nruns[q] <= p->ell_w[q]) {
-    // wide span, offsets in runs: one window load per run and wavefront
-    hipLaunchKernelGGL((spatial_dia_runs<TT>), dim3((unsigned)(chunks * rblocks)), dim3(256), 0,
-                       p->stream, x, a, b, p->ellR[q].as<int32_t>(), p->ellM[q].as<double>(),
-                       p->ellK[q].as<double>(), p->ell_nruns[q], p->Ns, slices, (int)chunks);
   } else if (p->ell_dia[q])
     hipLaunchKernelGGL((spatial_dia_pair<TT, ELL_KU>), dim3((unsigned)(chunks * rblocks)),
                        dim3(256), 0, p->stream, x, a, b, p->ellC[q].as<int32_t>(),

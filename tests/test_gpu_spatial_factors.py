@@ -196,21 +196,20 @@ def test_factored_batched_solve_matches_one_by_one(d, n_el):
         assert np.linalg.norm(x - y) / np.linalg.norm(y) <= 1e-7
 
 
-def test_isolated_wide_offsets_plain_diagonal_form():
-    """A pattern with five isolated offsets spanning most of the grid (stored by diagonals,
-    too wide to stage in LDS, runs of length one), plain and transposed, against sparse
-    Kronecker products of the plan's time factors."""
+def _isolated_offsets_case(d, n_el, offsets, seed):
+    """Random values on a pattern of isolated offsets (stored by diagonals, runs of length
+    one), plain and transposed, against sparse Kronecker products of the plan's time
+    factors."""
     import scipy.sparse as sp
-    w, a, plan, o = _setup(3, 12, matvec=None)
+    w, a, plan, o = _setup(d, n_el, matvec=None)
     Ns = plan.N_s
-    rng = np.random.default_rng(7)
-    offsets = (-(Ns // 2), -7, 0, 5, Ns // 3)
+    rng = np.random.default_rng(seed)
     rows, cols = [], []
     for r in range(Ns):
-        for d in offsets:
-            if 0 <= r + d < Ns and (r * 7 + d) % 5 != 1:
+        for off in offsets(Ns):
+            if 0 <= r + off < Ns and (r * 7 + off) % 5 != 1:
                 rows.append(r)
-                cols.append(r + d)
+                cols.append(r + off)
     rows, cols = np.array(rows), np.array(cols)
     vK, vM = rng.standard_normal(rows.size), rng.standard_normal(rows.size)
     Ks = sp.csr_matrix((vK, (rows, cols)), shape=(Ns, Ns))
@@ -221,10 +220,21 @@ def test_isolated_wide_offsets_plain_diagonal_form():
     plan.set_spatial_factors((Ks.indptr.astype(np.int64), Ks.indices.astype(np.int32), Ks.data,
                               Ms.data))
     A = (sp.kron(sp.csr_matrix(a.Wt), Ms) + sp.kron(sp.csr_matrix(a.Mt), Ks)).tocsr()
-    x = wl.random_tensor((2,) + w.shape, 23)
+    x = wl.random_tensor((2,) + w.shape, seed + 16)
     y = plan.matvec_A(_dev(x)).cpu().numpy()
     yt = plan.matvec_A(_dev(x), transpose=True).cpu().numpy()
     for r in range(2):
         ref, reft = A @ x[r].ravel(), A.T @ x[r].ravel()
         assert np.abs(y[r].ravel() - ref).max() <= 1e-13 * np.abs(ref).max()
         assert np.abs(yt[r].ravel() - reft).max() <= 1e-13 * np.abs(reft).max()
+
+
+def test_isolated_wide_offsets_plain_diagonal_form():
+    """Five isolated offsets spanning most of a 12^3 grid: too wide to stage in LDS,
+    plain gathers."""
+    _isolated_offsets_case(3, 12, lambda Ns: (-(Ns // 2), -7, 0, 5, Ns // 3), 7)
+
+
+def test_isolated_narrow_offsets_staged_diagonal_form():
+    """Five isolated offsets within +-7 on a 22^2 grid: x staged in LDS."""
+    _isolated_offsets_case(2, 20, lambda Ns: (-5, -2, 0, 3, 7), 9)
