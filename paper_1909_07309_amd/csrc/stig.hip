@@ -352,9 +352,11 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
                     : ((n == 65 || n == 49 || n == 32 || n == 130) ? n : 0);
   if (nc != 0 || n <= GEMM2_MAX_N) {
     // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N;
-    // n = 130 splits its 8 full row tiles over 2 blocks (rows: 64 + 2 fringe)
+    // n = 130 splits its 8 full row tiles over 4 blocks in FP64 (rows: 32 + 2
+    // fringe) and over 2 in FP32 / BF16 (64 + 2), the faster split for each
+    constexpr int RS130 = sizeof(E) == 8 ? 4 : 2;
     const int nm = nc ? nc : GEMM2_MAX_N;
-    const int rs = nc == 130 ? 2 : 1;
+    const int rs = nc == 130 ? RS130 : 1;
     const int rows = rs == 1 ? round_up(nm, 16) : 16 * (nm / 16 / rs) + nm % 16;
     size_t lds = (size_t)rows * lds_ld<TC>(nm) * sizeof(E);
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
@@ -375,13 +377,13 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     };
     if (sc) {
       if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, true>, 5);
-      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, true, 2>, 6);
+      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, true, RS130>, 6);
       return go(mode_gemm_small<Tin, Tout, TC, 0, true>, 7);
     }
     if (nc == 65) return go(mode_gemm_small<Tin, Tout, TC, 65, false>, 0);
     if (nc == 49) return go(mode_gemm_small<Tin, Tout, TC, 49, false>, 1);
     if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, false>, 2);
-    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false, 2>, 3);
+    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false, RS130>, 3);
     return go(mode_gemm_small<Tin, Tout, TC, 0, false>, 4);
   }
   const int jt = (n + 15) / 16;
