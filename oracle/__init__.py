@@ -26,9 +26,16 @@ isogeometric Galerkin methods for parabolic problems", arXiv:1909.07309):
                   the geometry-aware preconditioner A-hat^G (Section 4.3).
 * ``annulus3d`` - the same on the quarter annulus extruded to 3D, with the
                   3D separation of the coefficients (Section 4.3 in 3D).
-* ``convergence`` - errors of a manufactured solution (Section 5.1 rates).
+* ``convergence`` - errors of manufactured solutions (Section 5.1 rates): on
+                  the unit square and cube, and on the quarter annulus with the
+                  annulus workload's variable conductivity and heat capacity,
+                  which pins that workload's assembly.
 * ``adjoint``   - dense adjoint gradients of a quadratic loss.
 * ``problems``  - load vectors of the synthetic workloads.
 
 Functions without an independent pin say "parity unpinned" in their docstring.
+The variable-coefficient assembly of ``annulus`` is pinned by the manufactured
+rates and by an exact Kronecker form for a polar-separable conductivity; the 3D
+assembly of ``annulus3d`` by the exact Kronecker form for a conductivity
+separable in (r, theta, z) and by sharing the pinned 1/c-weighted time factor.
 """

@@ -215,15 +215,100 @@ def test_banded_solve_rejects_zero_pivot():
 
 # ------------------------------------------------------ discretisation error
 
-@pytest.mark.parametrize("p", [1, 2, 3])
-def test_manufactured_solution_rates(p):
-    """Section 5.1 and eq. a-riori-error-bound: L2 order p+1, X-type norm order p."""
-    e8 = manufactured_errors(2, 8, p)
-    e16 = manufactured_errors(2, 16, p)
-    r_l2 = np.log2(e8[0] / e16[0])
-    r_x = np.log2(e8[1] / e16[1])
+@pytest.mark.parametrize("d,p,n_el", [(2, 1, 8), (2, 2, 8), (2, 3, 8),
+                                       (3, 1, 6), (3, 2, 6), (3, 3, 6)])
+def test_manufactured_solution_rates(d, p, n_el):
+    """Section 5.1 and eq. a-riori-error-bound: L2 order p+1, X-type norm order p, on the
+    unit square (d = 2) and cube (d = 3), from n_el to 2 n_el elements."""
+    e1 = manufactured_errors(d, n_el, p)
+    e2 = manufactured_errors(d, 2 * n_el, p)
+    r_l2 = np.log2(e1[0] / e2[0])
+    r_x = np.log2(e1[1] / e2[1])
     assert abs(r_l2 - (p + 1)) < 0.15, r_l2
     assert abs(r_x - p) < 0.15, r_x
+
+
+def test_annulus_exact_solution_is_admissible_and_its_derivatives_are_right():
+    """The annulus manufactured solution vanishes on the spatial boundary, and its hand-written
+    gradient and Laplacian (and the conductivity's gradient) agree with central differences."""
+    from oracle.convergence import annulus_conductivity_gradient, annulus_solution
+    th = np.linspace(0, np.pi / 2, 7)
+    for r in (1.0, 2.0):
+        assert np.abs(annulus_solution(r * np.cos(th), r * np.sin(th))[0]).max() < 1e-14
+    rr = np.linspace(1, 2, 7)
+    assert np.abs(annulus_solution(0 * rr, rr)[0]).max() < 1e-14
+    assert np.abs(annulus_solution(rr, 0 * rr)[0]).max() < 1e-14
+    rng = np.random.default_rng(4)
+    x, y = rng.uniform(0.3, 1.3, 20), rng.uniform(0.3, 1.3, 20)
+    h = 1e-5
+    u = lambda a, b: annulus_solution(a, b)[0]
+    _, ux, uy, lap = annulus_solution(x, y)
+    assert np.allclose(ux, (u(x + h, y) - u(x - h, y)) / (2 * h), rtol=0, atol=1e-8)
+    assert np.allclose(uy, (u(x, y + h) - u(x, y - h)) / (2 * h), rtol=0, atol=1e-8)
+    h2 = 1e-4
+    lap_fd = (u(x + h2, y) + u(x - h2, y) + u(x, y + h2) + u(x, y - h2) - 4 * u(x, y)) / h2 ** 2
+    assert np.allclose(lap, lap_fd, rtol=0, atol=1e-5)
+    kx, ky = annulus_conductivity_gradient(x, y)
+    k = wl.annulus_conductivity
+    assert np.allclose(kx, (k(x + h, y) - k(x - h, y)) / (2 * h), rtol=0, atol=1e-8)
+    assert np.allclose(ky, (k(x, y + h) - k(x, y - h)) / (2 * h), rtol=0, atol=1e-8)
+
+
+def _annulus_p(n_el, p):
+    from oracle.annulus import AnnulusProblem
+    return AnnulusProblem(wl.scaled(wl.WORKLOADS["annulus_p4_n128"], n_el, p=p))
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_annulus_manufactured_solution_rates(p):
+    """The annulus workload's own system (variable conductivity, 1/c-weighted M_t, polar
+    map) solved for the 2D analogue of the paper's Section 5.1 solution: L2 order p+1 and
+    X-type order p, 16 -> 32 elements.  This pins the variable-coefficient assembly."""
+    from oracle.convergence import annulus_manufactured_errors
+    e1 = annulus_manufactured_errors(_annulus_p(16, p))
+    e2 = annulus_manufactured_errors(_annulus_p(32, p))
+    r_l2, r_x = np.log2(e1[0] / e2[0]), np.log2(e1[1] / e2[1])
+    assert abs(r_l2 - (p + 1)) < 0.15, r_l2
+    assert abs(r_x - p) < 0.15, r_x
+
+
+def _plant_annulus(kind, n_el, p, monkeypatch):
+    import oracle.annulus as oa
+    if kind == "kappa at parametric points":
+        monkeypatch.setattr(oa, "physical_point", lambda e1, e2: (e1, e2))
+    elif kind == "kappa at swapped parametric coordinates":
+        orig = oa.physical_point
+        monkeypatch.setattr(oa, "physical_point", lambda e1, e2: orig(e2, e1))
+    elif kind == "radial and angular metric swapped":
+        orig_c = oa.polar_coefficients
+        monkeypatch.setattr(oa, "polar_coefficients",
+                            lambda e1, e2: (lambda c: (c[1], c[0], c[2]))(orig_c(e1, e2)))
+    o = _annulus_p(n_el, p)
+    monkeypatch.undo()
+    if kind == "M_t without the 1/c weight":
+        o.Mt = bs.time_matrices(n_el, p)[1]
+    elif kind == "M_t weighted by c":
+        o.Mt = bs.time_matrices(n_el, p, mass_weight=wl.annulus_heat_capacity)[1]
+    elif kind == "W_t weighted by c":
+        xt = bs.open_uniform_knots(n_el, p)
+        x, w = bs.gauss_points(xt, p + 3)
+        B, D = bs.basis(xt, p, x), bs.basis_derivative(xt, p, x)
+        o.Wt = bs.restrict_time(B.T @ ((w * wl.annulus_heat_capacity(x))[:, None] * D))
+    return o
+
+
+@pytest.mark.parametrize("kind", ["kappa at parametric points",
+                                  "kappa at swapped parametric coordinates",
+                                  "radial and angular metric swapped",
+                                  "M_t without the 1/c weight", "M_t weighted by c",
+                                  "W_t weighted by c"])
+def test_pins_catch_annulus_coefficient_mistakes(kind, monkeypatch):
+    """Each plausible misreading of the variable-coefficient assembly makes the discrete
+    solution converge to the wrong limit: the L2 error stops falling."""
+    from oracle.convergence import annulus_manufactured_errors
+    e1 = annulus_manufactured_errors(_plant_annulus(kind, 8, 3, monkeypatch))
+    e2 = annulus_manufactured_errors(_plant_annulus(kind, 16, 3, monkeypatch))
+    assert np.log2(e1[0] / e2[0]) < 1.0 and e2[0] > 1e-3, (kind, e1, e2)
 
 
 # ----------------------------------------------------------- planted mistakes
@@ -342,6 +427,36 @@ def test_annulus_stiffness_separates_for_constant_conductivity(monkeypatch):
     assert np.allclose(np.outer(phi2, Phi1), np.pi * (1 + E1) / 2, rtol=1e-13)
 
 
+def _sep_kappa_2d(x, y):
+    """kappa = a(r) b(theta), separable in the polar coordinates (not in x and y)."""
+    r, th = np.hypot(x, y), np.arctan2(y, x)
+    return (1.0 + 0.3 * r * r) * (2.0 + np.sin(3.0 * th))
+
+
+def test_annulus_stiffness_is_exact_for_polar_separable_conductivity(monkeypatch):
+    """For kappa = a(r) b(theta) the polar-map stiffness is the Kronecker sum
+    M_th[b] (x) K_r[a pi r/2] + K_th[b] (x) M_r[a 2/(pi r)] of weighted 1D matrices, assembled
+    here by the 1D routines (same Gauss rule), independently of the 2D element assembly."""
+    monkeypatch.setattr(wl, "annulus_conductivity", _sep_kappa_2d)
+    n_el, p = 5, 4
+    o = _annulus(n_el)
+    xi = bs.open_uniform_knots(n_el, p)
+    a = lambda e1: 1.0 + 0.3 * (1 + e1) ** 2
+    b = lambda e2: 2.0 + np.sin(1.5 * np.pi * e2)
+    Kr = bs.restrict_space(bs.stiffness(xi, p, weight=lambda x: a(x) * np.pi * (1 + x) / 2, nq=p + 3))
+    Mr = bs.restrict_space(bs.mass(xi, p, weight=lambda x: a(x) * 2 / (np.pi * (1 + x)), nq=p + 3))
+    Kth = bs.restrict_space(bs.stiffness(xi, p, weight=b, nq=p + 3))
+    Mth = bs.restrict_space(bs.mass(xi, p, weight=b, nq=p + 3))
+    ref = np.kron(Mth, Kr) + np.kron(Kth, Mr)
+    assert np.abs(o.Ks.toarray() - ref).max() < 1e-13 * np.abs(ref).max()
+    # the same conductivity sampled at swapped parametric coordinates is caught
+    import oracle.annulus as oa
+    orig = oa.physical_point
+    monkeypatch.setattr(oa, "physical_point", lambda e1, e2: orig(e2, e1))
+    bad = _annulus(n_el)
+    assert np.abs(bad.Ks.toarray() - ref).max() > 1e-2 * np.abs(ref).max()
+
+
 def test_annulus_geometry_preconditioner_matches_dense():
     """A-hat^G = D^{1/2} A-tilde D^{1/2} (eq. prec_geo): FD apply against a dense solve,
     and diag(A-hat^G) = diag(A)."""
@@ -401,6 +516,33 @@ def test_annulus3d_stiffness_separates_for_constant_conductivity(monkeypatch):
     assert np.allclose(prod, c, rtol=1e-13)
     assert np.allclose(phi3[:, None, None] * phi2[None, :, None] * Phi1[None, None, :], c, rtol=1e-13)
     assert np.allclose(Phi3[:, None, None] * phi2[None, :, None] * phi1[None, None, :], c, rtol=1e-13)
+
+
+def test_annulus3d_stiffness_is_exact_for_separable_conductivity(monkeypatch):
+    """For kappa = a(r) b(theta) e(z) the extruded polar-map stiffness is the sum of three
+    Kronecker products of weighted 1D matrices (same Gauss rule), and the 3D time mass
+    matrix is the 1/c-weighted one of the 2D workload (pinned by the annulus rates)."""
+    a = lambda e1: 1.0 + 0.3 * (1 + e1) ** 2
+    b = lambda e2: 2.0 + np.sin(1.5 * np.pi * e2)
+    e = lambda e3: 1.5 + np.cos(2.0 * e3)
+
+    def kap(x, y, z):
+        r, th = np.hypot(x, y), np.arctan2(y, x)
+        return (1.0 + 0.3 * r * r) * (2.0 + np.sin(3.0 * th)) * (1.5 + np.cos(2.0 * z))
+    monkeypatch.setattr(wl, "annulus3d_conductivity", kap)
+    n_el, p = 4, 2
+    o = _annulus3d(n_el, p=p)
+    xi = bs.open_uniform_knots(n_el, p)
+    nq = p + 3
+    w1 = lambda f: bs.restrict_space(bs.mass(xi, p, weight=f, nq=nq))
+    k1 = lambda f: bs.restrict_space(bs.stiffness(xi, p, weight=f, nq=nq))
+    pr = lambda x: np.pi * (1 + x) / 2
+    ref = (np.kron(w1(e), np.kron(w1(b), k1(lambda x: a(x) * pr(x))))
+           + np.kron(w1(e), np.kron(k1(b), w1(lambda x: a(x) / pr(x))))
+           + np.kron(k1(e), np.kron(w1(b), w1(lambda x: a(x) * pr(x)))))
+    assert np.abs(o.Ks.toarray() - ref).max() < 1e-13 * np.abs(ref).max()
+    o2 = _annulus_p(n_el, p)
+    assert np.abs(o.Mt - o2.Mt).max() == 0.0
 
 
 def test_annulus3d_separation_is_exact_for_separable_samples(monkeypatch):
