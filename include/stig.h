@@ -12,10 +12,17 @@
  *    One tensor has N = n_t * n_1 * ... * n_d entries; a batch holds nrhs of them.
  *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
  *    memory on the plan's device.  The caller owns every buffer it passes; the
- *    library never frees caller memory.  The plan owns its own internal device
- *    workspace (eigenvector matrices, band coefficients, intermediate tensors,
- *    Krylov basis), allocated with hipMalloc by the calls that need it and freed
- *    by stig_plan_destroy.
+ *    library never frees caller memory.
+ *  - Memory: the setup calls (stig_setup_1d_pencils, stig_set_diag_scaling*,
+ *    stig_set_spatial_factors) allocate the plan's own factors (eigenvector
+ *    matrices, shifts, band coefficients, sparse spatial factors: a few MB to a
+ *    few hundred MB, reported by stig_plan_device_bytes) and a small pinned host
+ *    staging area; stig_plan_destroy frees them.  Everything a call needs beyond
+ *    that (the intermediate tensors of the apply, matvec, mass and lifting
+ *    products and the Krylov bases of GMRES) lives in a caller-owned device
+ *    workspace given by stig_set_workspace and sized by stig_workspace_bytes.
+ *    stig_apply_Pinv, stig_matvec_A, stig_apply_mass, stig_lift_* and
+ *    stig_gmres_solve never allocate or free device memory.
  *  - Every device operation is ordered on the plan's stream.  stig_apply_Pinv,
  *    stig_matvec_A and stig_apply_mass return as soon as their kernels are
  *    queued; stig_gmres_solve synchronises the stream (the Givens rotations run
@@ -62,8 +69,9 @@ typedef enum { STIG_FP64 = 0, STIG_FP32 = 1, STIG_BF16 = 2 } stig_prec;
 typedef struct {
   int iters;            /* total inner (Arnoldi) iterations over all restarts */
   int restarts;         /* number of restart cycles started after the first */
-  double relres_true;   /* ||f - A u||_2 / ||f||_2 at exit, in FP64 from products of A
-                           (see stig_gmres_solve), not from the GMRES estimate */
+  double relres_true;   /* ||f - A u||_2 / ||f||_2 at exit, from a fresh FP64
+                           product A u (see stig_gmres_solve), not from the GMRES
+                           estimate */
   double relres_est;    /* GMRES residual estimate at exit (relative) */
   double t_solve_ms;    /* wall time of the call (host clock, stream synchronised) */
 } stig_info;
@@ -84,6 +92,30 @@ void stig_plan_destroy(stig_plan *plan);
 /* Change the stream later calls are ordered on. */
 stig_status stig_set_stream(stig_plan *plan, void *stream);
 
+/* Bytes of device workspace that calls with up to nrhs right-hand sides need:
+ * stig_apply_Pinv in precision prec, stig_matvec_A, stig_apply_mass and
+ * stig_lift_*, and, when restart > 0, stig_gmres_solve with that restart length
+ * (its first restart cycle runs up to min(nrhs, 64) right-hand sides in
+ * lockstep; with a smaller workspace it runs fewer at a time).  Layout, per
+ * right-hand side, of the largest parts: the Krylov bases V (restart + 1
+ * vectors), Z = A-hat^{-1} V and A Z (restart vectors each) and two more
+ * vectors, all FP64 of N entries (Section 4.5: restarted GMRES); the two
+ * intermediate tensors of the apply in the storage type of prec (Algorithm 1,
+ * steps 2-4).  flexible does not change the size (GMRES and FGMRES keep the
+ * same vectors).  The result depends on the plan's setup and options (diagonal
+ * scaling, sparse spatial factors or CSR, kernel choices): query it after them.
+ * Returns 0 for a NULL plan or arguments out of range. */
+size_t stig_workspace_bytes(const stig_plan *plan, int restart, int flexible, stig_prec prec,
+                            int nrhs);
+
+/* Give the plan its workspace: ws (device, 256-byte aligned, on the plan's
+ * device) of `bytes` bytes, owned by the caller, kept alive and not used for
+ * anything else while calls on the plan are queued or running.  Calls check
+ * that their part fits (else STIG_EINVAL, nothing launched) and fail with
+ * STIG_ESTATE when no workspace was given.  Contents need not be initialised
+ * and are not preserved between calls.  ws = NULL detaches it. */
+stig_status stig_set_workspace(stig_plan *plan, void *ws, size_t bytes);
+
 /* Kernel choices of apply_Pinv (stig_set_option).  Every choice computes the
  * same result up to rounding order.
  *   STIG_OPT_PLANE_FUSION: 1 (default) = the mode-1 and mode-2 products of
@@ -99,7 +131,9 @@ stig_status stig_set_stream(stig_plan *plan, void *stream);
  *     form (Section 4.2.2, eq. time_eig_2, eq. block_LU): the time pencil
  *     transformed by the real block form of its arrowhead factorization (dense
  *     products along t on MFMA) and the arrowhead middle factor solved by block
- *     LU, for n_t = 34 and 66 (other n_t use 0).
+ *     LU, for n_t = 34 and 66 only: STIG_EINVAL for other n_t (or when the
+ *     set-up time pencil has no arrowhead factorization), and
+ *     stig_setup_1d_pencils returns STIG_EBREAKDOWN if it cannot build it.
  *   STIG_OPT_PARITY_SPLIT: 1 (default) = where a spatial pencil is
  *     persymmetric (stig_setup_1d_pencils then picks an eigenbasis of even and
  *     odd modes), its mode products run as two half-size products around a
@@ -271,9 +305,11 @@ stig_status stig_apply_mass(stig_plan *plan, const double *z, double *y, int nrh
  * removed first time function, restricted to the kept rows, and b (host, n_t)
  * the same column of the unrestricted M_t.  c0: device, nrhs * N_s doubles
  * ([rhs][x_d]..[x_1]); y: device, nrhs * N doubles.  The system solved for the
- * kept unknowns is then A u = f - y. */
+ * kept unknowns is A u = f - A_{I,0} c0: with f (device, nrhs * N doubles) given,
+ * y = f - A_{I,0} c0 is written directly (f may equal y); with f = NULL,
+ * y = A_{I,0} c0.  Synchronises (a and b are read from host memory). */
 stig_status stig_lift_apply(stig_plan *plan, const double *a_col, const double *b_col,
-                            const double *c0, double *y, int nrhs);
+                            const double *c0, const double *f, double *y, int nrhs);
 
 /* Spatial part of the initial-datum lifting (Section 3.1, non-homogeneous
  * initial condition): with a (host, n_t) = column of the unrestricted W for the
@@ -296,15 +332,22 @@ stig_status stig_lift_adjoint(stig_plan *plan, const double *a_col,
  * P^{-1} (V y) and saves one apply per cycle.  A zero initial guess skips the
  * first product (r_0 = f).  Arnoldi with classical Gram-Schmidt and one
  * re-orthogonalisation, all in FP64 on the device; Givens rotations on the host.
- * The true residual at the end of each restart cycle is r = r_0 - sum_i y_i (A z_i)
- * with the products A z_i of that cycle kept as computed (one stored vector per
- * iteration, m * N doubles) and r_0 the cycle's starting residual (f, or f - A u
- * by a direct product for a nonzero initial guess): FP64 products of A, so the
- * drift of the Hessenberg estimate does not enter it.
- * u: device, in = initial guess, out = solution.  Stops when that FP64 true
- * relative residual ||f - A u|| / ||f|| <= rtol, or after maxit inner iterations
- * per right-hand side (then STIG_NOT_CONVERGED).  Right-hand sides are solved one
- * after another.  info (host, may be NULL) receives the worst case over the batch. */
+ * A cycle ends when the GMRES estimate reaches rtol, on a happy breakdown, when
+ * maxit is spent, or after `restart` iterations.  In the first three cases the
+ * residual r = f - A u is computed afresh (one FP64 product of A); if it is still
+ * above rtol (and iterations remain), the next cycle starts from it.  After a
+ * full cycle without convergence the next cycle's residual is
+ * r_0 - sum_i y_i (A z_i), from the products A z_i of that cycle kept as computed
+ * (one stored vector per iteration, m * N doubles).  A nonzero initial guess
+ * gets its r_0 = f - A u from a direct product.
+ * u: device, in = initial guess, out = solution.  Returns STIG_OK when the fresh
+ * relative residual ||f - A u|| / ||f|| <= rtol (reported in info->relres_true),
+ * else STIG_NOT_CONVERGED after maxit inner iterations per right-hand side.
+ * Several right-hand sides: the first cycle runs in lockstep for as many as the
+ * workspace holds (batched applies and products, one host round trip per step
+ * for all of them); the others continue one after another.  info (host, may be
+ * NULL) receives the worst case over the batch.  Needs the workspace of
+ * stig_workspace_bytes(plan, restart, flexible, prec, 1) at least. */
 stig_status stig_gmres_solve(stig_plan *plan, const double *f, double *u, int nrhs,
                              int restart, double rtol, int maxit, int flexible,
                              int transpose, stig_prec prec, stig_info *info);
@@ -333,7 +376,8 @@ stig_status stig_profile_reset(stig_plan *plan);
 stig_status stig_profile_get(stig_plan *plan, int kind, double *total_ms, double *bytes,
                              long long *launches);
 
-/* Device bytes the plan currently holds (for reporting). */
+/* Device bytes the plan itself holds (its factors; the caller's workspace is
+ * not counted).  Constant after the setup calls. */
 size_t stig_plan_device_bytes(const stig_plan *plan);
 
 /* ------------------------------------------------------- 1D spline assembly */

@@ -45,7 +45,9 @@ SIGNATURES = {
     "stig_matvec_A": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int]),
     "stig_apply_mass": (C.c_int, [_vp, _vp, _vp, C.c_int]),
     "stig_lift_adjoint": (C.c_int, [_vp, _dp, _dp, _vp, _vp, C.c_int]),
-    "stig_lift_apply": (C.c_int, [_vp, _dp, _dp, _vp, _vp, C.c_int]),
+    "stig_lift_apply": (C.c_int, [_vp, _dp, _dp, _vp, _vp, _vp, C.c_int]),
+    "stig_workspace_bytes": (C.c_size_t, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "stig_set_workspace": (C.c_int, [_vp, _vp, C.c_size_t]),
     "stig_gmres_solve": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_double, C.c_int,
                                    C.c_int, C.c_int, C.c_int, C.POINTER(StigInfo)]),
     "stig_plan_device_bytes": (C.c_size_t, [_vp]),

@@ -2,6 +2,9 @@
 
 Device buffers are PyTorch CUDA (HIP) tensors in float64; every operation
 runs in libstig's kernels on torch's current stream.  Names follow the C ABI.
+PyTorch allocates all device memory the calls need: before each call the plan's
+workspace tensor is grown to stig_workspace_bytes for that call and handed to
+the library (stig_set_workspace), which allocates nothing in the call itself.
 """
 from __future__ import annotations
 
@@ -46,6 +49,7 @@ class Plan:
                                      _stream()))
         self._h = h
         self._keep = {}
+        self._ws = None  # caller-owned workspace (uint8 device tensor)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -58,6 +62,32 @@ class Plan:
 
     def _sync_stream(self):
         check(lib().stig_set_stream(self._h, _stream()))
+
+    def workspace_bytes(self, nrhs=1, restart=0, prec="fp64", flexible=False):
+        """stig_workspace_bytes: device bytes the calls with nrhs right-hand sides need
+        (restart > 0: GMRES with that restart length as well)."""
+        return int(lib().stig_workspace_bytes(self._h, int(restart), int(bool(flexible)),
+                                              PREC[prec], int(nrhs)))
+
+    def _ensure_workspace(self, need, device):
+        """Grow the workspace tensor to `need` bytes (torch allocation, outside the library
+        calls) and hand it to the plan."""
+        if self._ws is not None and self._ws.numel() >= need and self._ws.device == device:
+            return
+        self._ws = None  # release the old one first
+        self._ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=device)
+        check(lib().stig_set_workspace(self._h, C.c_void_p(self._ws.data_ptr()),
+                                       self._ws.numel()))
+
+    def set_workspace(self, ws):
+        """Use a caller-allocated uint8 device tensor as the workspace (None detaches)."""
+        if ws is None:
+            self._ws = None
+            check(lib().stig_set_workspace(self._h, None, 0))
+            return
+        assert ws.is_cuda and ws.dtype == torch.uint8 and ws.is_contiguous()
+        self._ws = ws
+        check(lib().stig_set_workspace(self._h, C.c_void_p(ws.data_ptr()), ws.numel()))
 
     def _nrhs(self, t):
         n = t.numel()
@@ -124,6 +154,7 @@ class Plan:
         nrhs = self._nrhs(r)
         if s is None:
             s = torch.empty_like(r)
+        self._ensure_workspace(self.workspace_bytes(nrhs, 0, prec), r.device)
         self._sync_stream()
         check(lib().stig_apply_Pinv(self._h, _dev(r, nrhs * self.N, "r"),
                                     _dev(s, nrhs * self.N, "s"), nrhs, int(bool(transpose)),
@@ -134,6 +165,7 @@ class Plan:
         nrhs = self._nrhs(x)
         if y is None:
             y = torch.empty_like(x)
+        self._ensure_workspace(self.workspace_bytes(nrhs), x.device)
         self._sync_stream()
         check(lib().stig_matvec_A(self._h, _dev(x, nrhs * self.N, "x"),
                                   _dev(y, nrhs * self.N, "y"), nrhs, int(bool(transpose))))
@@ -143,6 +175,7 @@ class Plan:
         nrhs = self._nrhs(z)
         if y is None:
             y = torch.empty_like(z)
+        self._ensure_workspace(self.workspace_bytes(nrhs), z.device)
         self._sync_stream()
         check(lib().stig_apply_mass(self._h, _dev(z, nrhs * self.N, "z"),
                                     _dev(y, nrhs * self.N, "y"), nrhs))
@@ -155,24 +188,28 @@ class Plan:
         assert a_col.shape == (self.n_t,) and b_col.shape == (self.n_t,)
         if g is None:
             g = torch.empty((nrhs,) + self.shape[1:], dtype=torch.float64, device=lam.device)
+        self._ensure_workspace(self.workspace_bytes(nrhs), lam.device)
         self._sync_stream()
         check(lib().stig_lift_adjoint(self._h, dptr(a_col), dptr(b_col),
                                       _dev(lam, nrhs * self.N, "lam"),
                                       _dev(g, nrhs * self.N_s, "g"), nrhs))
         return g
 
-    def lift_apply(self, a_col, b_col, c0, y=None):
-        """y = A_{I,0} c0 (initial-datum lifting), c0 of shape [rhs][x_d]..[x_1]."""
+    def lift_apply(self, a_col, b_col, c0, f=None, y=None):
+        """Initial-datum lifting, c0 of shape [rhs][x_d]..[x_1]: y = A_{I,0} c0, or
+        y = f - A_{I,0} c0 when f is given (the right-hand side of the kept unknowns)."""
         nrhs = c0.numel() // self.N_s
         a_col = np.ascontiguousarray(a_col, dtype=np.float64)
         b_col = np.ascontiguousarray(b_col, dtype=np.float64)
         assert a_col.shape == (self.n_t,) and b_col.shape == (self.n_t,)
         if y is None:
             y = torch.empty((nrhs,) + self.shape, dtype=torch.float64, device=c0.device)
+        fp = None if f is None else _dev(f, nrhs * self.N, "f")
+        self._ensure_workspace(self.workspace_bytes(nrhs), c0.device)
         self._sync_stream()
         check(lib().stig_lift_apply(self._h, dptr(a_col), dptr(b_col),
-                                    _dev(c0, nrhs * self.N_s, "c0"), _dev(y, nrhs * self.N, "y"),
-                                    nrhs))
+                                    _dev(c0, nrhs * self.N_s, "c0"), fp,
+                                    _dev(y, nrhs * self.N, "y"), nrhs))
         return y
 
     def gmres_solve(self, f, u=None, restart=30, rtol=1e-8, maxit=300, flexible=False,
@@ -181,6 +218,17 @@ class Plan:
         if u is None:
             u = torch.zeros_like(f)
         info = StigInfo()
+        # lockstep first cycle for as many right-hand sides as fit in 60 % of the
+        # free device memory (plus the current workspace)
+        nb = min(nrhs, 64)
+        need = self.workspace_bytes(nb, restart, prec, flexible)
+        if nb > 1:
+            free_b, _ = torch.cuda.mem_get_info(f.device)
+            budget = 0.6 * (free_b + (self._ws.numel() if self._ws is not None else 0))
+            while nb > 1 and need > budget:
+                nb -= 1
+                need = self.workspace_bytes(nb, restart, prec, flexible)
+        self._ensure_workspace(need, f.device)
         self._sync_stream()
         code = lib().stig_gmres_solve(self._h, _dev(f, nrhs * self.N, "f"),
                                       _dev(u, nrhs * self.N, "u"), nrhs, int(restart),

@@ -21,7 +21,8 @@ class STIGSolve(torch.autograd.Function):
         """f: [rhs][t][x_d]..[x_1] float64 (HIP); c0: [rhs][x_d]..[x_1] or None."""
         rhs = f.contiguous()
         if c0 is not None:
-            rhs = rhs - plan.lift_apply(a_col, b_col, c0.contiguous()).view_as(rhs)
+            # f - A_{I,0} c0 in one library call
+            rhs = plan.lift_apply(a_col, b_col, c0.contiguous(), f=rhs).view_as(rhs)
         u, info = plan.gmres_solve(rhs, **opts)
         ctx.plan, ctx.a_col, ctx.b_col, ctx.opts = plan, a_col, b_col, opts
         ctx.has_c0 = c0 is not None

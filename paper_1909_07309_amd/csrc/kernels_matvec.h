@@ -176,16 +176,22 @@ __global__ void time_weighted_sum(const double *__restrict__ in, double *__restr
   out[g] = acc;
 }
 
-// Outer product along t: out[rhs][t][s] = wa[t] * a[rhs][s] + wb[t] * b[rhs][s].
+// Outer product along t: out[rhs][t][s] = wa[t] * a[rhs][s] + wb[t] * b[rhs][s],
+// or f[rhs][t][s] minus it when f is given (f may be out).
 __global__ void time_outer2(const double *__restrict__ a, const double *__restrict__ b,
                             const double *__restrict__ wa, const double *__restrict__ wb,
-                            double *__restrict__ out, int nt, int64_t ns, int nrhs) {
+                            const double *f, double *out, int nt, int64_t ns, int nrhs) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ns * nrhs) return;
   int64_t rhs = g / ns, s = g - rhs * ns;
   double av = a[g], bv = b[g];
   double *o = out + rhs * ns * nt + s;
-  for (int t = 0; t < nt; ++t) o[(int64_t)t * ns] = wa[t] * av + wb[t] * bv;
+  if (f) {
+    const double *fi = f + rhs * ns * nt + s;
+    for (int t = 0; t < nt; ++t) o[(int64_t)t * ns] = fi[(int64_t)t * ns] - (wa[t] * av + wb[t] * bv);
+  } else {
+    for (int t = 0; t < nt; ++t) o[(int64_t)t * ns] = wa[t] * av + wb[t] * bv;
+  }
 }
 
 // Space-time CSR of W (x) M_s + M_t (x) K_s from the spatial CSR (rp2, col2,

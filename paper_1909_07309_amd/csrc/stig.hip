@@ -50,6 +50,8 @@ stig_status fail(stig_status s, const std::string &msg) {
 constexpr int MAX_P = 5;
 constexpr size_t GEMM_LDS_LIMIT = 160 * 1024;
 constexpr int64_t GEMM2_GRID = 1024;  // persistent blocks of the small-n GEMM
+constexpr int KRY_MAXB = 64;          // right-hand sides in one lockstep GMRES cycle
+constexpr size_t WS_ALIGN = 256;      // alignment of the workspace and of its views
 
 struct DevBuf {
   void *p = nullptr;
@@ -80,6 +82,24 @@ struct DevBuf {
   template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// A view of caller-owned memory (the workspace, or the static scratch array):
+// never allocated or freed here.  ensure() only checks that the view is large
+// enough, so every use states the bytes it needs.
+struct Span {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void set(char *base, size_t off, size_t n) {
+    p = base ? base + off : nullptr;
+    bytes = base ? n : 0;
+  }
+  stig_status ensure(size_t need) const {
+    if (need <= bytes && (p || need == 0)) return STIG_OK;
+    return fail(STIG_EINVAL, "workspace view of " + std::to_string(bytes) + " bytes, " +
+                                 std::to_string(need) + " needed (stig_workspace_bytes)");
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
 template <typename T> stig_status upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
   STIG_TRY(b.ensure(v.size() * sizeof(T)));
   HIP_TRY(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
@@ -105,8 +125,10 @@ struct stig_plan {
   bool split[3] = {false, false, false};
   DevBuf hFE[3][3], hFO[3][3], hBE[3][3], hBO[3][3];
   DevBuf lam;            // Ns doubles: lambda_k = sum_l lambda_{l,i_l}
-  DevBuf lamp;           // lam in a padded plane layout (stride lamp_ps)
-  int64_t lamp_ps = 0;
+  // lam in the padded plane layout of the fused x/y passes, one table per
+  // storage size of the intermediates (8, 4, 2 bytes: plane stride lamp_ps[i])
+  DevBuf lamp[3];
+  int64_t lamp_ps[3] = {0, 0, 0};
   DevBuf tW64, tWT64, tM64, tW32, tWT32, tM32;  // time bands (unscaled)
   DevBuf tR64[2], tR32[2];  // step records of [W; M] and [W^T; M] (right-looking solve)
   // arrowhead form of the time pencil (n_t = 32 q + 2): U^T and U in mode order
@@ -136,10 +158,18 @@ struct stig_plan {
   int ell_nruns[2] = {0, 0};  // runs of consecutive offsets (diagonal form)
   DevBuf ellR[2];             // [run][3]: first offset, length, first diagonal
   DevBuf ellC[2], ellM[2], ellK[2];
-  // scratch
-  DevBuf s0, s1, tscr, m0, m1, m2, m3, V, Z, AZ, w, tmp, partial, small, flag, lift0, lift1;
-  // pinned host staging of the small Krylov transfers: 4 coefficient slots of
-  // KRY_MAXV doubles, then the breakdown flag
+  // small buffers owned by the plan (setup): reduction partials, coefficient
+  // slots (4 KRY_MAXV doubles per right-hand side, KRY_MAXB of them), breakdown flag
+  DevBuf partial, small, flag;
+  // caller-owned workspace (stig_set_workspace) and the views of it that one
+  // call uses: apply intermediates s0/s1 and time scratch; matvec / mass /
+  // lifting intermediates m0..m3, lift0/lift1 and the lifting weights; the
+  // Krylov bases.  The views are laid out by bind_workspace at each call.
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  Span s0, s1, tscr, m0, m1, m2, m3, lift0, lift1, liftw, V, Z, AZ, w, tmp;
+  // pinned host staging of the small Krylov transfers (setup): 4 coefficient
+  // slots of KRY_MAXV doubles per right-hand side, then the breakdown flag
   double *pin = nullptr;
   size_t pin_n = 0;  // doubles in the pinned area
   // optional per-kernel timing with HIP events on the plan's stream
@@ -702,12 +732,38 @@ stig_status launch_time_arrow(stig_plan *p, const Tio *in, Tio *out, int nrhs, i
   return fail(STIG_EINVAL, "no arrowhead kernel for this n_t");
 }
 
+// (n_t, p_t) shapes with register-resident time kernels
+bool time_reg_shape(const stig_plan *p) {
+  return (p->nt == 66 && p->pt == 3) || (p->nt == 50 && p->pt == 3) || (p->nt == 9 && p->pt == 2);
+}
+bool time_arrow_shape(const stig_plan *p) {
+  return p->time_kernel == 4 && p->arrow_ok && (p->nt == 66 || p->nt == 34);
+}
+
+// Compute-type entries of scratch the time solve of `ns` systems per time row
+// and nrhs right-hand sides needs, for the kernel launch_time picks: none for
+// the arrowhead and register-resident kernels (they keep the forward-
+// substituted values in registers, or in the output when it has the compute
+// type), one tensor for the right-looking kernel that stores them in a
+// different type, P + 1 tensors for the generic kernel.
+int64_t time_scratch_elems(const stig_plan *p, int64_t ns, int nrhs, bool tc_f64, bool io_is_tc) {
+  const int64_t sys = ns * p->nt * nrhs;
+  if (time_arrow_shape(p)) return 0;
+  if (time_reg_shape(p)) {
+    if (p->time_kernel == 1) return (tc_f64 && !io_is_tc) ? sys : 0;
+    if (p->time_kernel == 0) return (p->time_recompute || io_is_tc) ? 0 : sys;
+  }
+  return (int64_t)(p->pt + 1) * sys;
+}
+
 template <typename Tio, typename TC>
 stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
                         TimeView tv) {
   // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
-  if (p->time_kernel == 4 && p->arrow_ok && (p->nt == 66 || p->nt == 34))
+  if (p->time_kernel == 4) {
+    if (!time_arrow_shape(p)) return fail(STIG_ESTATE, "no arrowhead factorization of the time pencil");
     return launch_time_arrow<Tio, typename TimeArrowType<Tio, TC>::type>(p, in, out, nrhs, transpose, tv);
+  }
   if (p->time_kernel == 1) {
     if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose, tv);
     if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose, tv);
@@ -744,6 +800,24 @@ __global__ void pad_shifts(const double *__restrict__ lam, double *__restrict__ 
   }
 }
 
+// The fused x/y passes of the apply run when modes 1 and 2 have the same size
+// n <= PLANE_MAX_N and no diagonal scaling is set.
+bool apply_fuses(const stig_plan *p) {
+  return p->d >= 2 && p->n[0] == p->n[1] && p->n[0] <= PLANE_MAX_N && !p->has_dmh &&
+         p->plane_fusion;
+}
+// x/y plane stride of the fused passes' intermediates for a storage size of
+// ss bytes: n_1 n_2 rounded up to 128 bytes
+int64_t padded_plane(const stig_plan *p, size_t ss) {
+  const int64_t nn = (int64_t)p->n[0] * p->n[1], q = 128 / (int64_t)ss;
+  return (nn + q - 1) / q * q;
+}
+// spatial indices per time row of the apply's intermediates
+int64_t apply_row(const stig_plan *p, size_t ss) {
+  if (!apply_fuses(p)) return p->Ns;
+  return padded_plane(p, ss) * (p->d == 3 ? p->n[2] : 1);
+}
+
 // Typed access to the eigenvector copies of one precision.
 template <typename TC> struct OpSet;
 template <> struct OpSet<double> {
@@ -770,32 +844,29 @@ template <> struct TimeCompute<double> { typedef double type; };
 template <typename S, typename TC>
 stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int transpose) {
   const double *scale = p->has_dmh ? p->dmh.as<double>() : nullptr;
-  const bool fuse = p->d >= 2 && p->n[0] == p->n[1] && p->n[0] <= PLANE_MAX_N && !scale &&
-                    p->plane_fusion;
+  const bool fuse = apply_fuses(p);
   auto use_sym = [&](int l) { return p->parity_split && p->split[l] && sym_size_ok(p->n[l]) && !scale; };
   // Intermediates between the fused plane passes: planes padded to a multiple
   // of 128 bytes, so that the strided passes (mode 3, time) read and write
   // whole cache lines.
   const int64_t nn = p->d >= 2 ? (int64_t)p->n[0] * p->n[1] : p->n[0];
-  const int64_t ps = fuse ? (nn + (128 / sizeof(S)) - 1) / (128 / sizeof(S)) * (128 / sizeof(S)) : nn;
+  const int64_t ps = fuse ? padded_plane(p, sizeof(S)) : nn;
   const int64_t nz = p->d == 3 ? p->n[2] : 1;
-  const int64_t ns = fuse ? nz * ps : p->Ns;       // spatial indices per time row
+  const int64_t ns = apply_row(p, sizeof(S));      // spatial indices per time row
   const int64_t tot = ns * p->nt * nrhs;           // entries of one intermediate tensor
   const int64_t planes = (int64_t)nrhs * p->nt * nz;
   STIG_TRY(p->s0.ensure(tot * sizeof(S)));
   STIG_TRY(p->s1.ensure(tot * sizeof(S)));
+  STIG_TRY(p->tscr.ensure(time_scratch_elems(p, ns, nrhs, sizeof(typename TimeCompute<TC>::type) == 8,
+                                             std::is_same<S, typename TimeCompute<TC>::type>::value) *
+                          sizeof(typename TimeCompute<TC>::type)));
   S *buf[2] = {p->s0.as<S>(), p->s1.as<S>()};
   int cur = 0;
   TimeView tv{p->Ns, p->lam.as<double>()};
   if (ps != nn) {
-    if (p->lamp_ps != ps) {
-      STIG_TRY(p->lamp.ensure((size_t)nz * ps * sizeof(double)));
-      hipLaunchKernelGGL(pad_shifts, dim3(grid_for(nz * ps, 256, 4096)), dim3(256), 0, p->stream,
-                         p->lam.as<double>(), p->lamp.as<double>(), nn, ps, nz);
-      HIP_TRY(hipGetLastError());
-      p->lamp_ps = ps;
-    }
-    tv = TimeView{ns, p->lamp.as<double>()};
+    const int li = sizeof(S) == 8 ? 0 : sizeof(S) == 4 ? 1 : 2;
+    if (p->lamp_ps[li] != ps) return fail(STIG_ESTATE, "padded shift table missing");
+    tv = TimeView{ns, p->lamp[li].as<double>()};
   }
   // one mode product, forward (U_l^T) or backward (U_l)
   auto mode = [&](auto tin, auto tout, int l, bool fwd, int64_t inner) -> stig_status {
@@ -908,7 +979,7 @@ stig_status band_pass(stig_plan *p, int P, const double *in1, const double *in2,
 // fastest d axes.  mass_only: out_a = x (x) M_1 .. M_d.  Otherwise a = mass
 // chain, b = stiffness sum; returns pointers to the final (a, b).
 stig_status spatial_chain(stig_plan *p, const double *x, int64_t tot, bool with_stiff,
-                          const double **a_out, const double **b_out, DevBuf *bufs[4]) {
+                          const double **a_out, const double **b_out, Span *bufs[4]) {
   const double *a = x, *b = nullptr;
   int slot = 0;
   int64_t inner = 1;
@@ -1044,7 +1115,7 @@ stig_status matvec_spatial(stig_plan *p, const double *x, int nrhs, int transpos
     *b = p->m1.as<double>();
     return STIG_OK;
   }
-  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+  Span *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
   for (auto *bb : bufs) STIG_TRY(bb->ensure(tot * sizeof(double)));
   return spatial_chain(p, x, tot, true, a, b, bufs);
 }
@@ -1116,6 +1187,103 @@ stig_status run_matvec(stig_plan *p, const double *x, double *y, int nrhs, int t
   const double *gW = transpose ? p->tgWT.as<double>() : p->tgW.as<double>();
   STIG_TRY(band_pass(p, p->pt, a, b, nullptr, y, nullptr, p->tnM.as<double>(), gW, p->nt, p->Ns,
                      tot));
+  return STIG_OK;
+}
+
+// --------------------------------------------------------------- workspace
+
+// What one call uses the operator part of the workspace for.
+enum { WS_APPLY = 1, WS_MATVEC = 2, WS_MASS = 4, WS_LIFT = 8, WS_ALL = 15 };
+
+inline size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+inline size_t store_size(stig_prec prec) { return prec == STIG_FP64 ? 8 : prec == STIG_FP32 ? 4 : 2; }
+inline size_t time_size(stig_prec prec) { return prec == STIG_FP64 ? 8 : 4; }
+
+// double intermediates of the spatial part of one matvec: the sparse spatial
+// factors and the fused stencil write a and b, the per-axis passes ping-pong
+// two pairs; the CSR form needs none
+int matvec_bufs(const stig_plan *p) {
+  if (p->csr_rowptr) return 0;
+  return (p->ell_w[0] > 0 || stencil_fits(p)) ? 2 : 4;
+}
+
+// Byte offsets of the views of one call.  The operator views (apply, matvec,
+// mass, lifting) all start at offset 0: one call runs one of them at a time.
+// The Krylov bases follow them.
+struct WsLayout {
+  size_t s0 = 0, s1 = 0, tscr = 0;        // apply: two intermediates, time scratch
+  size_t m = 0;                           // one matvec / mass intermediate
+  size_t lm = 0, lw = 0;                  // lifting: one spatial intermediate, weights
+  size_t op = 0;                          // operator part
+  size_t v = 0, z = 0, vec = 0;           // Krylov: V, Z and AZ, one vector block (w, tmp)
+  size_t total = 0;
+};
+
+WsLayout ws_layout(const stig_plan *p, int nrhs, stig_prec prec, int what, int nb, int m) {
+  WsLayout L;
+  const size_t ss = store_size(prec), ts = time_size(prec);
+  if (what & WS_APPLY) {
+    const int64_t ns = apply_row(p, ss);
+    L.s0 = L.s1 = ws_round((size_t)ns * p->nt * nrhs * ss);
+    L.tscr = ws_round((size_t)time_scratch_elems(p, ns, nrhs, ts == 8, ss == ts) * ts);
+    L.op = std::max(L.op, L.s0 + L.s1 + L.tscr);
+  }
+  L.m = ws_round((size_t)p->N * nrhs * sizeof(double));
+  if (what & WS_MATVEC) L.op = std::max(L.op, (size_t)matvec_bufs(p) * L.m);
+  if (what & WS_MASS) L.op = std::max(L.op, 2 * L.m);
+  if (what & WS_LIFT) {
+    L.lm = ws_round((size_t)p->Ns * nrhs * sizeof(double));
+    L.lw = ws_round((size_t)2 * p->nt * sizeof(double));
+    L.op = std::max(L.op, 6 * L.lm + L.lw);
+  }
+  if (nb > 0) {
+    L.vec = ws_round((size_t)nb * p->N * sizeof(double));
+    L.v = ws_round((size_t)(m + 1) * nb * p->N * sizeof(double));
+    L.z = ws_round((size_t)m * nb * p->N * sizeof(double));
+  }
+  L.total = L.op + L.v + 2 * L.z + 2 * L.vec;
+  return L;
+}
+
+// Lay the views of one call over the caller's workspace.
+stig_status bind_workspace(stig_plan *p, int nrhs, stig_prec prec, int what, int nb = 0,
+                           int m = 0) {
+  const WsLayout L = ws_layout(p, nrhs, prec, what, nb, m);
+  if (L.total > 0 && !p->ws)
+    return fail(STIG_ESTATE, "no workspace: give one of stig_workspace_bytes bytes to "
+                             "stig_set_workspace (" + std::to_string(L.total) + " bytes needed)");
+  if (L.total > p->ws_bytes)
+    return fail(STIG_EINVAL, "workspace of " + std::to_string(p->ws_bytes) + " bytes, " +
+                                 std::to_string(L.total) + " needed (stig_workspace_bytes)");
+  char *b = p->ws;
+  p->s0.set(b, 0, L.s0);
+  p->s1.set(b, L.s0, L.s1);
+  p->tscr.set(b, L.s0 + L.s1, L.tscr);
+  if (what & WS_LIFT) {
+    p->m0.set(b, 0, L.lm);
+    p->m1.set(b, L.lm, L.lm);
+    p->m2.set(b, 2 * L.lm, L.lm);
+    p->m3.set(b, 3 * L.lm, L.lm);
+    p->lift0.set(b, 4 * L.lm, L.lm);
+    p->lift1.set(b, 5 * L.lm, L.lm);
+    p->liftw.set(b, 6 * L.lm, L.lw);
+  } else {
+    const int nm = (what & WS_MATVEC) ? std::max(matvec_bufs(p), (what & WS_MASS) ? 2 : 0)
+                                      : ((what & WS_MASS) ? 2 : 0);
+    Span *ms[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
+    for (int i = 0; i < 4; ++i) ms[i]->set(i < nm ? b : nullptr, (size_t)i * L.m, L.m);
+    p->lift0 = p->lift1 = p->liftw = Span{};
+  }
+  size_t o = L.op;
+  p->V.set(nb ? b : nullptr, o, L.v);
+  o += L.v;
+  p->Z.set(nb ? b : nullptr, o, L.z);
+  o += L.z;
+  p->AZ.set(nb ? b : nullptr, o, L.z);
+  o += L.z;
+  p->w.set(nb ? b : nullptr, o, L.vec);
+  o += L.vec;
+  p->tmp.set(nb ? b : nullptr, o, L.vec);
   return STIG_OK;
 }
 
@@ -1213,6 +1381,14 @@ struct Krylov {
     HIP_TRY(hipGetLastError());
     return reduce(3);
   }
+  // r = f - Ax with ||r||^2 in slot 3 entry KRY_MAXV-1 (no synchronisation)
+  stig_status residual_async(const double *f, const double *Ax, double *r) {
+    ProfScope ps(p, STIG_K_KRYLOV, 3.0 * p->N * 8);
+    hipLaunchKernelGGL(residual_norm, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, f, Ax, r,
+                       p->N, partial());
+    HIP_TRY(hipGetLastError());
+    return reduce(3);
+  }
   // r = f - Ax; host value of ||r||_2 (synchronises)
   stig_status residual(const double *f, const double *Ax, double *r, double *norm) {
     ProfScope ps(p, STIG_K_KRYLOV, 3.0 * p->N * 8);
@@ -1258,8 +1434,8 @@ stig_status apply_dispatch(stig_plan *p, const double *r, double *s, int nrhs, i
   return fail(STIG_EINVAL, "unknown precision");
 }
 
-// pinned staging area of the plan (allocated on first use)
-stig_status ensure_pinned(stig_plan *p, size_t n = 4 * KRY_MAXV + 1) {
+// pinned staging area of the plan (allocated by the setup)
+stig_status ensure_pinned(stig_plan *p, size_t n) {
   if (p->pin && p->pin_n >= n) return STIG_OK;
   if (p->pin) (void)hipHostFree(p->pin);
   p->pin = nullptr;
@@ -1314,7 +1490,6 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *AZ = p->AZ.as<double>(),
          *w = p->w.as<double>(), *tmp = p->tmp.as<double>();
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  STIG_TRY(ensure_pinned(p));
   double *hs = p->pin;
 
   double fnorm, unorm;
@@ -1350,6 +1525,7 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
+    bool stop = false;  // estimate at rtol, breakdown or iteration budget spent
     for (int j = 0; j < m; ++j) {
       double *vj = V + (int64_t)j * N;
       double *zj = Z + (int64_t)j * N, *azj = AZ + (int64_t)j * N;
@@ -1410,7 +1586,8 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
       k = j + 1;
       info->relres_est = std::fabs(g[j + 1]) / fnorm;
       bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
-      if (info->relres_est <= rtol || breakdown || info->iters >= maxit) break;
+      stop = info->relres_est <= rtol || breakdown || info->iters >= maxit;
+      if (stop) break;
       if (j + 1 < m) {
         double *vn = V + (int64_t)(j + 1) * N;
         if (corrected) STIG_TRY(K.axpby(w, nullptr, vn, 1.0 / hnext, 0.0));
@@ -1436,12 +1613,20 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
     // u += Z y (u = Z y while u is the zero initial guess)
     if (cycle == 1 && unorm == 0.0) STIG_TRY(K.update(Z, k, K.slot(3), 1.0, nullptr, 0, 0, u));
     else STIG_TRY(K.update(Z, k, K.slot(3), 1.0, u, 0, 0));
-    // true residual from this cycle's products of A: r = r_0 - sum_i y_i A z_i
-    // = beta (v_0 - AZ y / beta), written over v_0, with its norm
-    STIG_TRY(K.update(AZ, k, K.slot(2), -1.0, V, 1, 3, V, beta));
-    double nsq;
-    STIG_TRY(K.fetch(3, KRY_MAXV - 1, &nsq));
-    beta *= std::sqrt(nsq);
+    if (stop) {
+      // the cycle that may end the solve: a fresh residual r = f - A u (one
+      // product of A), written over v_0; the solve restarts from it if it is
+      // still above rtol
+      STIG_TRY(K.residual_of(f, u, V, tmp, transpose, &beta));
+    } else {
+      // a full cycle without convergence: the next cycle's residual from this
+      // cycle's products of A, r = r_0 - sum_i y_i A z_i = beta (v_0 - AZ y / beta),
+      // written over v_0, with its norm
+      STIG_TRY(K.update(AZ, k, K.slot(2), -1.0, V, 1, 3, V, beta));
+      double nsq;
+      STIG_TRY(K.fetch(3, KRY_MAXV - 1, &nsq));
+      beta *= std::sqrt(nsq);
+    }
     if (!std::isfinite(beta)) return fail(STIG_ENONFINITE, "non-finite residual");
     info->relres_true = beta / fnorm;
   }
@@ -1466,8 +1651,9 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   STIG_TRY(p->AZ.ensure((size_t)m * ld * sizeof(double)));
   STIG_TRY(p->w.ensure((size_t)ld * sizeof(double)));
   STIG_TRY(p->tmp.ensure((size_t)ld * sizeof(double)));
-  STIG_TRY(p->small.ensure((size_t)nb * S4 * sizeof(double)));
-  STIG_TRY(ensure_pinned(p, (size_t)nb * S4 + 1));
+  if (nb > KRY_MAXB || p->small.bytes < (size_t)nb * S4 * sizeof(double) ||
+      p->pin_n < (size_t)nb * S4 + 1)
+    return fail(STIG_EINVAL, "too many right-hand sides in one lockstep cycle");
   double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *AZ = p->AZ.as<double>(),
          *w = p->w.as<double>(), *tmp = p->tmp.as<double>(), *hs = p->pin;
   std::vector<Krylov> K;
@@ -1618,14 +1804,16 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
                            hipMemcpyHostToDevice, p->stream));
     if (unorm[r] == 0.0) STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, nullptr, 0, 0, u + r * N));
     else STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, u + r * N, 0, 0));
-    // r = r_0 - sum_i y_i A z_i = beta (v_0 - AZ y / beta) over v_0, with its norm
-    STIG_TRY(K[r].update(AZ + r * N, kk[r], K[r].slot(2), -1.0, V + r * N, 1, 3, V + r * N,
-                         beta[r]));
   }
+  // fresh residuals r = f - A u of the whole batch: one batched product, then
+  // per right-hand side the difference and its norm (over v_0), one round trip
+  STIG_TRY(run_matvec(p, u, tmp, nb, transpose));
+  for (int r = 0; r < nb; ++r)
+    if (kk[r] > 0) STIG_TRY(K[r].residual_async(f + r * N, tmp + r * N, V + r * N));
   STIG_TRY(fetch_all(true));
   for (int r = 0; r < nb; ++r) {
     if (kk[r] == 0) continue;
-    const double bt = beta[r] * std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
+    const double bt = std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
     if (!std::isfinite(bt)) return fail(STIG_ENONFINITE, "non-finite residual");
     infos[r].relres_true = bt / fnorm[r];
     done[r] = infos[r].relres_true <= rtol;
@@ -1703,6 +1891,10 @@ stig_status stig_set_option(stig_plan *plan, int option, int value) {
       return STIG_OK;
     case STIG_OPT_TIME_KERNEL:
       if (value < 0 || value > 4) return fail(STIG_EINVAL, "time kernel takes 0 .. 4");
+      if (value == 4 && plan->nt != 34 && plan->nt != 66)
+        return fail(STIG_EINVAL, "the arrowhead time kernel needs n_t = 34 or 66");
+      if (value == 4 && plan->ready && !plan->arrow_ok)
+        return fail(STIG_EINVAL, "the time pencil has no arrowhead factorization");
       plan->time_kernel = value == 3 ? 0 : value;
       plan->time_recompute = value != 3;
       return STIG_OK;
@@ -1725,7 +1917,7 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
   p->ready = false;
   p->gamma = gamma;
   p->nu = nu;
-  p->lamp_ps = 0;  // padded shifts are rebuilt from the new ones
+  for (auto &v : p->lamp_ps) v = 0;  // padded shifts are rebuilt from the new ones
   hipStream_t s = p->stream;
   std::vector<std::vector<double>> lams(p->d);
   for (int l = 0; l < p->d; ++l) {
@@ -1800,6 +1992,22 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     lk[k] = v;
   }
   STIG_TRY(upload(p->lam, lk, s));
+  // the shifts in the padded plane layouts of the fused x/y passes (one per
+  // storage size of the intermediates); padding entries repeat the first shift
+  // of their z index (valid systems whose results are never read)
+  if (p->d >= 2 && p->n[0] == p->n[1] && p->n[0] <= PLANE_MAX_N) {
+    const int64_t nn = (int64_t)p->n[0] * p->n[1], nz = p->d == 3 ? p->n[2] : 1;
+    const size_t sizes[3] = {8, 4, 2};
+    for (int i = 0; i < 3; ++i) {
+      const int64_t ps = padded_plane(p, sizes[i]);
+      if (ps == nn) continue;
+      STIG_TRY(p->lamp[i].ensure((size_t)nz * ps * sizeof(double)));
+      hipLaunchKernelGGL(pad_shifts, dim3(grid_for(nz * ps, 256, 4096)), dim3(256), 0, s,
+                         p->lam.as<double>(), p->lamp[i].as<double>(), nn, ps, nz);
+      HIP_TRY(hipGetLastError());
+      p->lamp_ps[i] = ps;
+    }
+  }
   {
     std::vector<double> id(2 * p->ps + 1, 0.0), zero(2 * p->ps + 1, 0.0);
     id[p->ps] = 1.0;
@@ -1832,6 +2040,9 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     STIG_TRY(upload(p->tR32[tr], convert<float>(rec), s));
   }
   STIG_TRY(setup_arrowhead(p, Wt, Mt));
+  if (p->time_kernel == 4 && !p->arrow_ok)
+    return fail(STIG_EBREAKDOWN, "arrowhead factorization of the time pencil not reached "
+                                 "(time kernel 4 selected)");
   std::vector<double> gw(wb), gwt(wtb), nm(mb);
   for (auto &v : gw) v *= gamma;
   for (auto &v : gwt) v *= gamma;
@@ -1842,15 +2053,24 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
   STIG_TRY(p->flag.ensure(sizeof(int)));
   HIP_TRY(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
   STIG_TRY(p->partial.ensure((size_t)KRY_MAXV * KRY_GRID * sizeof(double)));
-  STIG_TRY(p->small.ensure((size_t)4 * KRY_MAXV * sizeof(double)));
+  STIG_TRY(p->small.ensure((size_t)KRY_MAXB * 4 * KRY_MAXV * sizeof(double)));
+  STIG_TRY(ensure_pinned(p, (size_t)KRY_MAXB * 4 * KRY_MAXV + 1));
   HIP_TRY(hipStreamSynchronize(s));
-  // pivot check: one FP64 time pass on a zero input factors every shifted system
+  // pivot check: one FP64 time pass on a zero input factors every shifted
+  // system (its own temporaries: no workspace is needed for setup)
   {
-    DevBuf zin, zout;
+    DevBuf zin, zout, zscr;
     STIG_TRY(zin.ensure(p->N * sizeof(double)));
     STIG_TRY(zout.ensure(p->N * sizeof(double)));
+    const size_t scr = time_scratch_elems(p, p->Ns, 1, true, true) * sizeof(double);
+    if (scr) STIG_TRY(zscr.ensure(scr));
+    const Span keep = p->tscr;
+    p->tscr.p = zscr.p;
+    p->tscr.bytes = scr;
     HIP_TRY(hipMemsetAsync(zin.p, 0, p->N * sizeof(double), s));
-    STIG_TRY((launch_time<double, double>(p, zin.as<double>(), zout.as<double>(), 1, 0)));
+    const stig_status st = launch_time<double, double>(p, zin.as<double>(), zout.as<double>(), 1, 0);
+    p->tscr = keep;
+    STIG_TRY(st);
     HIP_TRY(hipStreamSynchronize(s));
     STIG_TRY(check_flag(p));
   }
@@ -2079,21 +2299,50 @@ stig_status stig_apply_Pinv(stig_plan *p, const double *r, double *s, int nrhs, 
   STIG_TRY(check_plan(p, true));
   if (!r || !s || nrhs < 1) return fail(STIG_EINVAL, "bad apply arguments");
   if (r == s) return fail(STIG_EINVAL, "r and s must not overlap");
+  if (prec != STIG_FP64 && prec != STIG_FP32 && prec != STIG_BF16)
+    return fail(STIG_EINVAL, "unknown precision");
+  STIG_TRY(bind_workspace(p, nrhs, prec, WS_APPLY));
   return apply_dispatch(p, r, s, nrhs, transpose ? 1 : 0, prec);
 }
 
 stig_status stig_matvec_A(stig_plan *p, const double *x, double *y, int nrhs, int transpose) {
   STIG_TRY(check_plan(p, true));
   if (!x || !y || nrhs < 1 || x == y) return fail(STIG_EINVAL, "bad matvec arguments");
+  STIG_TRY(bind_workspace(p, nrhs, STIG_FP64, WS_MATVEC));
   return run_matvec(p, x, y, nrhs, transpose ? 1 : 0);
+}
+
+size_t stig_workspace_bytes(const stig_plan *p, int restart, int flexible, stig_prec prec,
+                            int nrhs) {
+  (void)flexible;  // GMRES and FGMRES keep the same vectors
+  if (!p || nrhs < 1 || restart < 0 || restart > KRY_MAXV - 1) return 0;
+  if (prec != STIG_FP64 && prec != STIG_FP32 && prec != STIG_BF16) return 0;
+  size_t need = ws_layout(p, nrhs, prec, WS_ALL, 0, 0).total;
+  if (restart > 0) {
+    const int nb = std::min(nrhs, KRY_MAXB);
+    need = std::max(need, ws_layout(p, nb, prec, WS_APPLY | WS_MATVEC, nb, restart).total);
+  }
+  return need;
+}
+
+stig_status stig_set_workspace(stig_plan *p, void *ws, size_t bytes) {
+  STIG_TRY(check_plan(p, false));
+  if (ws && (reinterpret_cast<uintptr_t>(ws) % WS_ALIGN))
+    return fail(STIG_EINVAL, "workspace must be aligned to 256 bytes");
+  p->ws = static_cast<char *>(ws);
+  p->ws_bytes = ws ? bytes : 0;
+  return STIG_OK;
 }
 
 stig_status stig_apply_mass(stig_plan *p, const double *z, double *y, int nrhs) {
   STIG_TRY(check_plan(p, true));
   if (!z || !y || nrhs < 1 || z == y) return fail(STIG_EINVAL, "bad mass-apply arguments");
   const int64_t tot = p->N * nrhs;
-  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
-  for (auto *b : bufs) STIG_TRY(b->ensure(tot * sizeof(double)));
+  STIG_TRY(bind_workspace(p, nrhs, STIG_FP64, WS_MASS));
+  // the mass chain alternates between slots 0 and 2
+  Span *bufs[4] = {&p->m0, nullptr, &p->m1, nullptr};
+  STIG_TRY(p->m0.ensure(tot * sizeof(double)));
+  STIG_TRY(p->m1.ensure(tot * sizeof(double)));
   const double *a, *b;
   STIG_TRY(spatial_chain(p, z, tot, false, &a, &b, bufs));
   return band_pass(p, p->pt, a, nullptr, y, nullptr, p->tM64.as<double>(), nullptr, nullptr, p->nt,
@@ -2105,19 +2354,16 @@ stig_status stig_lift_adjoint(stig_plan *p, const double *a_col, const double *b
   STIG_TRY(check_plan(p, true));
   if (!a_col || !b_col || !lam || !g || nrhs < 1) return fail(STIG_EINVAL, "bad lift arguments");
   const int64_t ts = p->Ns * nrhs;
-  std::vector<double> ab(a_col, a_col + p->nt), bb(b_col, b_col + p->nt);
-  DevBuf wa, wbv;
-  STIG_TRY(upload(wa, ab, p->stream));
-  STIG_TRY(upload(wbv, bb, p->stream));
-  STIG_TRY(p->lift0.ensure(ts * sizeof(double)));
-  STIG_TRY(p->lift1.ensure(ts * sizeof(double)));
+  STIG_TRY(bind_workspace(p, nrhs, STIG_FP64, WS_LIFT));
+  double *wa = p->liftw.as<double>(), *wbv = wa + p->nt;
+  HIP_TRY(hipMemcpyAsync(wa, a_col, p->nt * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(wbv, b_col, p->nt * sizeof(double), hipMemcpyHostToDevice, p->stream));
   hipLaunchKernelGGL(time_weighted_sum, dim3(grid_for(ts, 256)), dim3(256), 0, p->stream, lam,
-                     p->lift0.as<double>(), wa.as<double>(), p->nt, p->Ns, nrhs);
+                     p->lift0.as<double>(), wa, p->nt, p->Ns, nrhs);
   hipLaunchKernelGGL(time_weighted_sum, dim3(grid_for(ts, 256)), dim3(256), 0, p->stream, lam,
-                     p->lift1.as<double>(), wbv.as<double>(), p->nt, p->Ns, nrhs);
+                     p->lift1.as<double>(), wbv, p->nt, p->Ns, nrhs);
   HIP_TRY(hipGetLastError());
-  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
-  for (auto *b : bufs) STIG_TRY(b->ensure(ts * sizeof(double)));
+  Span *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
   const double *ma, *dummy, *sa, *sb;
   STIG_TRY(spatial_chain(p, p->lift0.as<double>(), ts, false, &ma, &dummy, bufs));
   // keep the mass result: copy it to g scaled, before the buffers are reused
@@ -2128,24 +2374,25 @@ stig_status stig_lift_adjoint(stig_plan *p, const double *a_col, const double *b
   hipLaunchKernelGGL(stig::axpby, dim3(grid_for(ts, 256, 8192)), dim3(256), 0, p->stream, g, sb,
                      g, 1.0, -p->nu, ts);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(p->stream));  // wa, wbv freed on return
+  HIP_TRY(hipStreamSynchronize(p->stream));  // the host weights are read by the copies above
   return STIG_OK;
 }
 
 stig_status stig_lift_apply(stig_plan *p, const double *a_col, const double *b_col,
-                            const double *c0, double *y, int nrhs) {
+                            const double *c0, const double *f, double *y, int nrhs) {
   STIG_TRY(check_plan(p, true));
   if (!a_col || !b_col || !c0 || !y || nrhs < 1) return fail(STIG_EINVAL, "bad lift arguments");
   const int64_t ts = p->Ns * nrhs;
-  std::vector<double> ab(a_col, a_col + p->nt), bb(b_col, b_col + p->nt);
-  for (auto &v : ab) v *= p->gamma;
-  for (auto &v : bb) v *= p->nu;
-  DevBuf wa, wbv;
-  STIG_TRY(upload(wa, ab, p->stream));
-  STIG_TRY(upload(wbv, bb, p->stream));
-  DevBuf *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
-  for (auto *b : bufs) STIG_TRY(b->ensure(ts * sizeof(double)));
-  STIG_TRY(p->lift0.ensure(ts * sizeof(double)));
+  std::vector<double> ab(2 * (size_t)p->nt);
+  for (int t = 0; t < p->nt; ++t) {
+    ab[t] = p->gamma * a_col[t];
+    ab[p->nt + t] = p->nu * b_col[t];
+  }
+  STIG_TRY(bind_workspace(p, nrhs, STIG_FP64, WS_LIFT));
+  double *wa = p->liftw.as<double>(), *wbv = wa + p->nt;
+  HIP_TRY(hipMemcpyAsync(wa, ab.data(), 2 * p->nt * sizeof(double), hipMemcpyHostToDevice,
+                         p->stream));
+  Span *bufs[4] = {&p->m0, &p->m1, &p->m2, &p->m3};
   const double *ma, *dummy, *sa, *sb;
   STIG_TRY(spatial_chain(p, c0, ts, false, &ma, &dummy, bufs));
   // keep M_s c0 aside before the buffers are reused by the stiffness chain
@@ -2154,10 +2401,9 @@ stig_status stig_lift_apply(stig_plan *p, const double *a_col, const double *b_c
   HIP_TRY(hipGetLastError());
   STIG_TRY(spatial_chain(p, c0, ts, true, &sa, &sb, bufs));
   hipLaunchKernelGGL(time_outer2, dim3(grid_for(ts, 256)), dim3(256), 0, p->stream,
-                     p->lift0.as<double>(), sb, wa.as<double>(), wbv.as<double>(), y, p->nt, p->Ns,
-                     nrhs);
+                     p->lift0.as<double>(), sb, wa, wbv, f, y, p->nt, p->Ns, nrhs);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(p->stream));  // wa, wbv freed on return
+  HIP_TRY(hipStreamSynchronize(p->stream));  // ab is read by the copy above
   return STIG_OK;
 }
 
@@ -2180,18 +2426,14 @@ stig_status stig_gmres_solve(stig_plan *p, const double *f, double *u, int nrhs,
     worst.relres_est = std::max(worst.relres_est, one.relres_est);
   };
   // Batches: the first restart cycle of up to nb right-hand sides in lockstep,
-  // nb chosen so that its bases, products and intermediates take at most 60 %
-  // of the free device memory; right-hand sides it leaves above rtol continue
-  // one by one from their current iterate.
-  int nb = 1;
-  if (nrhs > 1) {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-      const double per = (3.0 * restart + 8.0) * (double)p->N * sizeof(double);
-      nb = (int)std::max(1.0, std::min((double)nrhs, 0.6 * (double)free_b / per));
-    }
-    (void)hipGetLastError();
-  }
+  // nb the largest count (at most KRY_MAXB) whose bases, products and
+  // intermediates fit the workspace; right-hand sides it leaves above rtol
+  // continue one by one from their current iterate.
+  int nb = std::min(nrhs, KRY_MAXB);
+  while (nb > 1 &&
+         ws_layout(p, nb, prec, WS_APPLY | WS_MATVEC, nb, restart).total > p->ws_bytes)
+    --nb;
+  STIG_TRY(bind_workspace(p, nb, prec, WS_APPLY | WS_MATVEC, nb, restart));
   for (int r0 = 0; r0 < nrhs; r0 += nb) {
     const int cnt = std::min(nb, nrhs - r0);
     std::vector<stig_info> first(cnt, stig_info{0, 0, 0.0, 0.0, 0.0});
@@ -2263,13 +2505,12 @@ stig_status stig_profile_get(stig_plan *p, int kind, double *total_ms, double *b
 size_t stig_plan_device_bytes(const stig_plan *p) {
   if (!p) return 0;
   size_t t = 0;
-  const DevBuf *bs[] = {&p->lam, &p->lamp, &p->aTf[0], &p->aTf[1], &p->aTf[2], &p->aTb[0],
-                        &p->aTb[1], &p->aTb[2], &p->aTab64[0], &p->aTab64[1], &p->aTab32[0],
-                        &p->aTab32[1], &p->tW64, &p->tWT64, &p->tM64, &p->tW32, &p->tWT32, &p->tM32,
-                        &p->tR64[0], &p->tR64[1], &p->tR32[0], &p->tR32[1],
-                        &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->s0, &p->s1, &p->tscr, &p->m0,
-                        &p->m1, &p->m2, &p->m3, &p->V, &p->Z, &p->AZ, &p->w, &p->tmp, &p->partial,
-                        &p->small, &p->flag, &p->lift0, &p->lift1};
+  const DevBuf *bs[] = {&p->lam, &p->lamp[0], &p->lamp[1], &p->lamp[2], &p->aTf[0], &p->aTf[1],
+                        &p->aTf[2], &p->aTb[0], &p->aTb[1], &p->aTb[2], &p->aTab64[0],
+                        &p->aTab64[1], &p->aTab32[0], &p->aTab32[1], &p->tW64, &p->tWT64, &p->tM64,
+                        &p->tW32, &p->tWT32, &p->tM32, &p->tR64[0], &p->tR64[1], &p->tR32[0],
+                        &p->tR32[1], &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->sId, &p->sZero,
+                        &p->partial, &p->small, &p->flag};
   for (auto *b : bs) t += b->bytes;
   for (int l = 0; l < 3; ++l) {
     t += p->U64[l].bytes + p->UT64[l].bytes + p->U32[l].bytes + p->UT32[l].bytes +

@@ -97,9 +97,15 @@ def test_fused_plane_products_match_per_mode_passes(n_el):
 def test_time_kernels_match_oracle(name, n_el, kernel):
     """Every form of step 3, plain and transposed, FP64 and FP32 compute: the
     banded eliminations (n_t = 9, 50, 66 have register-resident kernels) and the
-    paper's arrowhead form (n_t = 34, 66; other n_t fall back to the default).
+    paper's arrowhead form (n_t = 34, 66; other n_t are refused with STIG_EINVAL).
     BF16: no less accurate than the default banded form."""
+    from paper_1909_07309_amd import StigError
     w, fac, plan, pr = _setup(name, n_el)
+    if kernel == "arrowhead" and w.n_t not in (34, 66):
+        with pytest.raises(StigError) as e:
+            plan.set_option("time_kernel", kernel)
+        assert e.value.code == -1
+        return
     plan.set_option("time_kernel", kernel)
     r = wl.random_tensor(w.shape, 13)
     rd = _dev(r)
@@ -308,6 +314,29 @@ def test_full_size_cube_apply_and_solve():
     r = f_ref - fd.kron_matvec(u, pr.Wt, pr.Mt, pr.K1d, pr.M1d)
     assert np.linalg.norm(r) / np.linalg.norm(f_ref) <= 1e-8
     assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_size_cube_mixed_precision_fgmres(prec):
+    """The 64-element cube with the FP32 / BF16 apply (FP32 accumulation) inside flexible
+    GMRES(30), FP64 Arnoldi, residual and matvec: the solution's residual, recomputed by the
+    oracle, reaches 1e-8, and its error against the oracle's solution (the FP64 fast
+    diagonalization of f, since A-hat = A on the cube) is recorded."""
+    from paper_1909_07309_amd.problem import source
+    w, fac, plan, pr = _setup("cube_p3_n64", None)
+    f = source(w, plan)
+    f_ref = pr.source()
+    u, info = plan.gmres_solve(f, restart=30, rtol=1e-8, maxit=300, flexible=True, prec=prec)
+    u = u.cpu().numpy()
+    r = f_ref - fd.kron_matvec(u, pr.Wt, pr.Mt, pr.K1d, pr.M1d)
+    relres = np.linalg.norm(r) / np.linalg.norm(f_ref)
+    ref = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt).apply(f_ref)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    print(f"cube FGMRES {prec}: {info['iters']} iterations, oracle residual {relres:.2e}, "
+          f"error vs oracle {err:.2e}")
+    assert relres <= 1e-8
+    assert err <= 1e-7
+    assert abs(info["relres_true"] - relres) <= 1e-3 * relres + 1e-15
 
 
 def test_degenerate_grid_solve_and_empty_batch():

@@ -162,11 +162,55 @@ def test_argument_validation_without_gpu():
     assert lib.stig_set_option(h, 0, 2) == -1
     assert all(lib.stig_set_option(h, 1, v) == 0 for v in (0, 1, 2, 3, 4))
     assert lib.stig_set_option(h, 1, 5) == -1 and lib.stig_set_option(h, 1, -1) == -1
+    assert lib.stig_set_option(h, 1, 0) == 0
     assert lib.stig_set_option(h, 2, 0) == 0 and lib.stig_set_option(h, 2, 1) == 0
     assert lib.stig_set_option(h, 2, 5) == -1
     assert lib.stig_set_option(h, 7, 0) == -1
+    # workspace: a misaligned pointer is refused; NULL detaches
+    assert lib.stig_set_workspace(h, C.c_void_p(8), 1 << 20) == -1
+    assert b"aligned" in lib.stig_last_error()
+    assert lib.stig_set_workspace(h, None, 0) == 0
     lib.stig_plan_destroy(h)
     assert lib.stig_status_string(-4) == b"breakdown (non-positive pivot)"
+    # the arrowhead time kernel exists for n_t = 34 and 66 only (n_t = 131: refused)
+    n2 = (C.c_int * 2)(130, 130)
+    assert lib.stig_plan_create(C.byref(h), 2, n2, 131, 4, 4, None) == 0
+    assert lib.stig_set_option(h, 1, 4) == -1
+    assert b"n_t" in lib.stig_last_error()
+    assert lib.stig_set_option(h, 1, 2) == 0
+    lib.stig_plan_destroy(h)
+
+
+def _round256(b):
+    return (b + 255) // 256 * 256
+
+
+def test_workspace_bytes_cover_each_calls_tensors():
+    """stig_workspace_bytes on the 64-element cube (65^3 x 66 unknowns): the FP64 apply keeps
+    two intermediates with x/y planes padded to 128 bytes (65^2 = 4225 -> 4240 entries), the
+    FP32 / BF16 ones to 4256 / 4288; GMRES(m) adds V (m+1 vectors), Z and A Z (m each) and two
+    more vectors of N doubles per right-hand side.  Sizes computed here from the tensor shapes."""
+    L = _lib()
+    lib = L.lib()
+    h = C.c_void_p()
+    n = (C.c_int * 3)(65, 65, 65)
+    assert lib.stig_plan_create(C.byref(h), 3, n, 66, 3, 3, None) == 0
+    N = 65 ** 3 * 66
+    try:
+        ws = lambda m, prec, nrhs: lib.stig_workspace_bytes(h, m, 0, prec, nrhs)
+        vec = _round256(N * 8)
+        for prec, size, plane in ((0, 8, 4240), (1, 4, 4256), (2, 2, 4288)):
+            apply_b = 2 * _round256(65 * plane * 66 * size)
+            op = max(apply_b, 2 * vec)  # matvec (fused stencil: a, b) and mass (two buffers)
+            assert ws(0, prec, 1) == op, prec
+            for m in (1, 30):
+                gm = _round256((m + 1) * N * 8) + 2 * _round256(m * N * 8) + 2 * vec
+                assert ws(m, prec, 1) == op + gm
+        # batches: every part scales with the right-hand sides
+        assert ws(0, 0, 3) == max(2 * _round256(3 * 65 * 4240 * 66 * 8), 2 * _round256(3 * N * 8))
+        assert ws(31, 0, 1) > 0 and ws(33, 0, 1) == 0 and ws(0, 0, 0) == 0 and ws(0, 7, 1) == 0
+    finally:
+        lib.stig_plan_destroy(h)
 
 
 @pytest.mark.parametrize("n_el,p", [(4, 2), (5, 3)])
