@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 (vector and matrix, dense)
+BF16_PEAK_TFLOPS = 2500.0    # MI355X BF16 MFMA, dense
 
 
 def log(*a):
@@ -52,6 +54,100 @@ def cpu_baseline(w, f_host, target_s=12.0):
                "sample": f"{reps} full FP64 applies of A-hat^-1 on the {w.N}-unknown tensor "
                          f"(numpy/scipy, BLAS threads={threads}, nproc={os.cpu_count()})",
                "s_per_apply": dt}
+
+
+def cpu_baseline_more():
+    """The oracle on the other workloads' unit of work (baseline only): the 48-element cube
+    (one right-hand side: the FD apply, and the solve = that apply, since A-hat = A, plus the
+    residual product that checks it) and the quarter annulus at 128 elements (the
+    geometry-aware FD apply and the factored matvec of Section 4.5)."""
+    from threadpoolctl import threadpool_info
+
+    import workloads as wl
+    from oracle import fd
+    from oracle.annulus import AnnulusProblem
+    from oracle.problems import CubeProblem
+    threads = int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+
+    def timed(fn, reps=3):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    wb = wl.WORKLOADS["cube_p3_n48_b32"]
+    pr = CubeProblem(wb)
+    P = fd.FDPreconditioner(pr.K1d, pr.M1d, pr.Wt, pr.Mt)
+    x = wl.random_tensor(wb.shape, 6)
+    ta = timed(lambda: P.apply(x))
+    tm = timed(lambda: fd.kron_matvec(x, pr.Wt, pr.Mt, pr.K1d, pr.M1d))
+    out["cube_p3_n48_apply"] = {"value": wb.N / ta, "unit": "DoF/s", "cores": threads,
+                                "kind": "oracle", "s_per_apply": ta,
+                                "sample": f"3 FP64 applies of A-hat^-1, {wb.N} unknowns (one "
+                                          "right-hand side of the batch)"}
+    out["cube_p3_n48_solve"] = {"value": wb.N / (ta + tm), "unit": "DoF/s", "cores": threads,
+                                "kind": "oracle", "s_per_solve": ta + tm,
+                                "sample": "one right-hand side: u = A-hat^-1 f (= A^-1 f) and "
+                                          "the residual product f - A u"}
+    wa = wl.WORKLOADS["annulus_p4_n128"]
+    o = AnnulusProblem(wa)
+    Pa = o.preconditioner()
+    xa = wl.random_tensor(wa.shape, 5)
+    ta = timed(lambda: Pa.apply(xa))
+    tm = timed(lambda: o.matvec(xa))
+    out["annulus_p4_n128_apply"] = {"value": wa.N / ta, "unit": "DoF/s", "cores": threads,
+                                    "kind": "oracle", "s_per_apply": ta,
+                                    "sample": f"3 FP64 applies of (A-hat^G)^-1, {wa.N} unknowns"}
+    out["annulus_p4_n128_factored_matvec"] = {
+        "value": wa.N / tm, "unit": "DoF/s", "cores": threads, "kind": "oracle",
+        "s_per_matvec": tm, "sample": "3 products W_t (x) M_s + M_t' (x) K_s with scipy CSR "
+                                      "spatial factors"}
+    return out
+
+
+def kernel_breakdown(prof, steps, N, flops_per_dof, peak_tflops=FP64_PEAK_TFLOPS):
+    """Per kernel class: mean launch time (HIP events), algorithmic bytes and flops per
+    launch, achieved rates, and the bound (the larger of the two time floors at peak)."""
+    kernels = {}
+    total = sum(x[0] for x in prof.values())
+    for k, v in prof.items():
+        if not v[2]:
+            continue
+        ms_l, by_l = v[0] / v[2], v[1] / v[2]
+        fl_l = flops_per_dof.get(k, 0) * N
+        t_hbm, t_mfma = by_l / (HBM_PEAK_GBS * 1e9), fl_l / (peak_tflops * 1e12)
+        kernels[k] = {"ms_per_launch": ms_l, "launches_per_step": v[2] / steps,
+                      "share": v[0] / total, "bytes_per_launch": by_l, "flops_per_launch": fl_l,
+                      "GBps": by_l / (ms_l * 1e-3) / 1e9,
+                      "TFLOPs": fl_l / (ms_l * 1e-3) / 1e12,
+                      "bound": "mfma" if t_mfma > t_hbm else "hbm"}
+    return kernels
+
+
+def roofline_of(kernels, traffic=None, peak_tflops=FP64_PEAK_TFLOPS):
+    """The roofline object of the dominant kernel class (largest share of event time)."""
+    dom = max(kernels, key=lambda k: kernels[k]["share"])
+    kd = kernels[dom]
+    if kd["bound"] == "mfma":
+        return {"kernel": dom, "bound": "mfma", "achieved": kd["TFLOPs"], "peak": peak_tflops,
+                "unit": "TFLOP/s", "frac": kd["TFLOPs"] / peak_tflops, "traffic": traffic,
+                "flops_per_launch": kd["flops_per_launch"],
+                "bytes_per_launch": kd["bytes_per_launch"], "ms_per_launch": kd["ms_per_launch"],
+                "hbm_GBps": kd["GBps"]}
+    return {"kernel": dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": kd["bytes_per_launch"], "ms_per_launch": kd["ms_per_launch"]}
+
+
+def apply_floor_ms(N, flops_per_dof, prec):
+    """Time floor of one whole apply: the larger of its algorithmic flops at the precision's
+    peak and its compulsory 16 bytes per unknown (FP64 in and out) at HBM peak."""
+    peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[prec]
+    t_mfma = flops_per_dof * N / (peak * 1e12) * 1e3
+    t_hbm = 16.0 * N / (HBM_PEAK_GBS * 1e9) * 1e3
+    return (t_mfma, "mfma") if t_mfma >= t_hbm else (t_hbm, "hbm")
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fd_apply_cube_p3_n64.json")
@@ -176,22 +272,8 @@ def main():
     # plane kernel does two of them (4n); the banded solve is counted as the
     # elimination with precomputed factors (4 p_t + 1, negligible: HBM-bound)
     flops_per_dof = {"mode_gemm": 2 * w.n_s, "plane_gemm": 4 * w.n_s, "time_solve": 4 * w.p + 1}
-    kernels = {}
-    for k, v in prof.items():
-        if not v[2]:
-            continue
-        ms_l, by_l = v[0] / v[2], v[1] / v[2]
-        fl_l = flops_per_dof.get(k, 0) * w.N
-        # the bound is the larger of the two time floors at peak
-        t_hbm, t_mfma = by_l / (HBM_PEAK_GBS * 1e9), fl_l / (FP64_PEAK_TFLOPS * 1e12)
-        kernels[k] = {"ms_per_launch": ms_l, "launches_per_step": v[2] / args.steps,
-                      "share": v[0] / sum(x[0] for x in prof.values()),
-                      "bytes_per_launch": by_l, "flops_per_launch": fl_l,
-                      "GBps": by_l / (ms_l * 1e-3) / 1e9,
-                      "TFLOPs": fl_l / (ms_l * 1e-3) / 1e12,
-                      "bound": "mfma" if t_mfma > t_hbm else "hbm"}
+    kernels = kernel_breakdown(prof, args.steps, w.N, flops_per_dof)
     dom = max(kernels, key=lambda k: kernels[k]["share"])
-    kd = kernels[dom]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         t = json.load(open(TRAFFIC_FILE))
@@ -210,27 +292,23 @@ def main():
                     traffic = sum((v["fetch_bytes"] + v["write_bytes"]) * v["dispatches"]
                                   for v in ks) / nd
                     break
-    if kd["bound"] == "mfma":
-        roofline = {"kernel": dom, "bound": "mfma", "achieved": kd["TFLOPs"],
-                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": kd["TFLOPs"] / FP64_PEAK_TFLOPS, "traffic": traffic,
-                    "flops_per_launch": kd["flops_per_launch"],
-                    "bytes_per_launch": kd["bytes_per_launch"], "ms_per_launch": kd["ms_per_launch"],
-                    "hbm_GBps": kd["GBps"]}
-    else:
-        roofline = {"kernel": dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
-                    "bytes_per_launch": kd["bytes_per_launch"], "ms_per_launch": kd["ms_per_launch"]}
+    roofline = roofline_of(kernels, traffic)
     # whole-apply view: FP64 flops 4*d*n_s per unknown for the transforms (+ time solves)
-    flops = (4 * w.d * w.n_s + 4 * w.p + 1) * w.N
+    apply_fpd = 4 * w.d * w.n_s + 4 * w.p + 1
+    flops = apply_fpd * w.N
     apply_tflops = flops / (ms_per_step * 1e-3) / 1e12
 
-    # ---- mixed-precision applies
+    # ---- mixed-precision applies, and each precision's whole apply against its floor
     mixed = {}
     for prec in ("fp32", "bf16"):
         dtp, _ = timed_applies(prec, args.steps, args.warmup)
         mixed[prec] = {"ms_per_apply": dtp / args.steps * 1e3, "DoF_per_s": w.N * args.steps / dtp}
         log(f"[bench] {prec} apply {mixed[prec]['ms_per_apply']:.3f} ms")
+    apply_roofline = {}
+    for prec, ms in (("fp64", ms_per_step), ("fp32", mixed["fp32"]["ms_per_apply"]),
+                     ("bf16", mixed["bf16"]["ms_per_apply"])):
+        floor, bound = apply_floor_ms(w.N, apply_fpd, prec)
+        apply_roofline[prec] = {"ms": ms, "floor_ms": floor, "bound": bound, "frac": floor / ms}
 
     # ---- FP64 matvec y = A x (the per-iteration product of the solves)
     for _ in range(args.warmup):
@@ -248,6 +326,7 @@ def main():
     # on all host threads, then one apply on one thread (beside the paper's serial timings)
     cpu = None
     cpu1 = None
+    cpu_more = None
     u_ref = None
     if not args.no_cpu_baseline:
         f_host = f.cpu().numpy()
@@ -259,6 +338,8 @@ def main():
         cpu1["cores"] = 1
         cpu1["sample"] = f"one full FP64 apply of A-hat^-1 on the {w.N}-unknown tensor, one thread"
         log(f"[bench] cpu oracle, one thread: {cpu1['s_per_apply']:.2f} s/apply")
+        cpu_more = cpu_baseline_more()
+        log(f"[bench] cpu oracle, other workloads: {cpu_more}")
 
     # ---- solves to 1e-8
     solves = {}
@@ -316,10 +397,29 @@ def main():
                         pl.apply_Pinv(f, s_, prec=prec)
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
-                    for _ in range(10):
+                    for _ in range(args.steps):
                         pl.apply_Pinv(f, s_, prec=prec)
                     torch.cuda.synchronize()
-                    r["apply_ms"] = (time.perf_counter() - t0) / 10 * 1e3
+                    r["apply_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
+                    r["apply_DoF_per_s"] = w.N / (r["apply_ms"] * 1e-3)
+                    if prec == "fp64" and form == "factored":
+                        # per-kernel event times of the same applies, and the
+                        # roofline of the dominant kernel class
+                        pl.profile_reset()
+                        pl.profile_enable(True)
+                        for _ in range(args.steps):
+                            pl.apply_Pinv(f, s_, prec=prec)
+                        prof = pl.profile()
+                        pl.profile_enable(False)
+                        n = w.n_s
+                        kern = kernel_breakdown(prof, args.steps, w.N,
+                                                {"mode_gemm": 2 * n, "plane_gemm": 4 * n,
+                                                 "time_solve": 4 * w.p + 1})
+                        r["kernels"] = kern
+                        r["roofline"] = roofline_of(kern)
+                        floor, bound = apply_floor_ms(w.N, 4 * w.d * n + 4 * w.p + 1, "fp64")
+                        r["apply_roofline"] = {"floor_ms": floor, "bound": bound,
+                                               "frac": floor / r["apply_ms"]}
                 pl.gmres_solve(f, torch.zeros_like(f), restart=30, rtol=1e-8, maxit=300,
                                flexible=True, prec=prec)  # warm (allocations)
                 u = torch.zeros_like(f)
@@ -345,7 +445,7 @@ def main():
         t0 = time.perf_counter()
         a2 = AnnulusSetup(wa)
         host_ms = (time.perf_counter() - t0) * 1e3
-        annulus = annulus_runs(a2, wa, False)
+        annulus = annulus_runs(a2, wa, True)
         annulus["host_setup_ms"] = host_ms
         del a2
         w3 = wl.WORKLOADS["annulus3d_p2_n32"]
@@ -400,6 +500,7 @@ def main():
                                "65^3 x 66 = 18,125,250 unknowns, one FP64 A-hat^-1 apply per step",
                    "N": w.N, "d": w.d, "p": w.p, "n_el": w.n_el, "parallelism": "single GPU"},
         "roofline": roofline,
+        "apply_roofline": apply_roofline,
         "apply_fp64_tflops": apply_tflops,
         "kernels_fp64_apply": kernels,
         "mixed_apply": mixed,
@@ -413,6 +514,7 @@ def main():
                                                   if k != "s_per_apply"},
         "cpu_baseline_1thread": None if cpu1 is None else {k: v for k, v in cpu1.items()
                                                            if k != "s_per_apply"},
+        "cpu_baseline_other_workloads": cpu_more,
     }
     print(json.dumps(line), flush=True)
 
