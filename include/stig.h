@@ -284,6 +284,22 @@ stig_status stig_kron_csr_fill(stig_plan *plan, const int64_t *rowptr, int32_t *
 stig_status stig_apply_Pinv(stig_plan *plan, const double *r, double *s,
                             int nrhs, int transpose, stig_prec prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same apply as
+ * stig_apply_Pinv, same arguments, results and kernels, but its intermediate
+ * tensors live in a static device array of the library (128 MiB, one per GPU,
+ * held until the process ends) instead of the plan's workspace; it calls no
+ * allocation routine and needs no stig_set_workspace.  The plan's device must be
+ * current.  Sizes whose intermediates exceed 128 MiB (stig_workspace_bytes with
+ * restart = 0 gives an upper bound) are refused with STIG_EINVAL, nothing
+ * launched: e.g. FP64 fits up to about 8 million unknowns per call.  Every call
+ * on one GPU, from any plan, shares that array: calls that overlap on one GPU
+ * (other streams or host threads) race; calls ordered on one stream do not.
+ * Nothing in the array needs to start at zero (every intermediate is written
+ * before it is read). */
+stig_status stig_apply_Pinv_noalloc(stig_plan *plan, const double *r, double *s, int nrhs,
+                                    int transpose, stig_prec prec);
+
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1), FP64, eq. syst_mat:
  * A = gamma W_t (x) M_s + nu M_t (x) K_s, computed matrix-free by banded mode
  * products (Section 4.5), with the sparse spatial factors of

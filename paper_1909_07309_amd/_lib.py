@@ -42,6 +42,7 @@ SIGNATURES = {
     "stig_set_A_csr": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64]),
     "stig_set_spatial_factors": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "stig_apply_Pinv": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int]),
+    "stig_apply_Pinv_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int]),
     "stig_matvec_A": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int]),
     "stig_apply_mass": (C.c_int, [_vp, _vp, _vp, C.c_int]),
     "stig_lift_adjoint": (C.c_int, [_vp, _dp, _dp, _vp, _vp, C.c_int]),

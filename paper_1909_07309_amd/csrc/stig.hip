@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <chrono>
 #include <cmath>
@@ -114,6 +115,7 @@ struct stig_plan {
   int nt = 0, ps = 0, pt = 0;
   int64_t Ns = 0, N = 0;
   hipStream_t stream = nullptr;
+  int device = 0;     // the plan's device (current at stig_plan_create)
   int num_cu = 256;  // compute units of the plan's device
   bool ready = false;
   double gamma = 1.0, nu = 1.0;
@@ -1246,6 +1248,8 @@ WsLayout ws_layout(const stig_plan *p, int nrhs, stig_prec prec, int what, int n
 }
 
 // Lay the views of one call over the caller's workspace.
+void lay_views(stig_plan *p, const WsLayout &L, char *b, int what, int nb);
+
 stig_status bind_workspace(stig_plan *p, int nrhs, stig_prec prec, int what, int nb = 0,
                            int m = 0) {
   const WsLayout L = ws_layout(p, nrhs, prec, what, nb, m);
@@ -1255,7 +1259,12 @@ stig_status bind_workspace(stig_plan *p, int nrhs, stig_prec prec, int what, int
   if (L.total > p->ws_bytes)
     return fail(STIG_EINVAL, "workspace of " + std::to_string(p->ws_bytes) + " bytes, " +
                                  std::to_string(L.total) + " needed (stig_workspace_bytes)");
-  char *b = p->ws;
+  lay_views(p, L, p->ws, what, nb);
+  return STIG_OK;
+}
+
+// The views of layout L over the memory at b.
+void lay_views(stig_plan *p, const WsLayout &L, char *b, int what, int nb) {
   p->s0.set(b, 0, L.s0);
   p->s1.set(b, L.s0, L.s1);
   p->tscr.set(b, L.s0 + L.s1, L.tscr);
@@ -1284,6 +1293,32 @@ stig_status bind_workspace(stig_plan *p, int nrhs, stig_prec prec, int what, int
   p->w.set(nb ? b : nullptr, o, L.vec);
   o += L.vec;
   p->tmp.set(nb ? b : nullptr, o, L.vec);
+}
+
+// ------------------------------------------- allocation-free apply (static scratch)
+
+// Device scratch of the allocation-free apply, one copy per GPU, held until the
+// process ends.  Host code must not pass `scratch` itself to a kernel (that is a
+// host-side stand-in): it uses the device address from hipGetSymbolAddress,
+// looked up once per device.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+// Device address of this device's scratch array (looked up on first use).
+stig_status static_scratch(int dev, char **out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(STIG_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(STIG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<char *>(g_scratch_ptr[dev]);
   return STIG_OK;
 }
 
@@ -1868,9 +1903,11 @@ stig_status stig_plan_create(stig_plan **out, int d, const int *n_s, int n_t, in
   p->N = p->Ns * n_t;
   p->stream = (hipStream_t)stream;
   int dev = 0, cu = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
-    p->num_cu = cu;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    p->device = dev;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      p->num_cu = cu;
+  }
   (void)hipGetLastError();
   *out = p;
   return STIG_OK;
@@ -2302,6 +2339,28 @@ stig_status stig_apply_Pinv(stig_plan *p, const double *r, double *s, int nrhs, 
   if (prec != STIG_FP64 && prec != STIG_FP32 && prec != STIG_BF16)
     return fail(STIG_EINVAL, "unknown precision");
   STIG_TRY(bind_workspace(p, nrhs, prec, WS_APPLY));
+  return apply_dispatch(p, r, s, nrhs, transpose ? 1 : 0, prec);
+}
+
+stig_status stig_apply_Pinv_noalloc(stig_plan *p, const double *r, double *s, int nrhs,
+                                    int transpose, stig_prec prec) {
+  STIG_TRY(check_plan(p, true));
+  if (!r || !s || nrhs < 1) return fail(STIG_EINVAL, "bad apply arguments");
+  if (r == s) return fail(STIG_EINVAL, "r and s must not overlap");
+  if (prec != STIG_FP64 && prec != STIG_FP32 && prec != STIG_BF16)
+    return fail(STIG_EINVAL, "unknown precision");
+  const WsLayout L = ws_layout(p, nrhs, prec, WS_APPLY, 0, 0);
+  if (L.total > STATIC_SCRATCH_BYTES)
+    return fail(STIG_EINVAL, "the allocation-free apply needs " + std::to_string(L.total) +
+                                 " bytes of scratch; its static scratch holds " +
+                                 std::to_string(STATIC_SCRATCH_BYTES) +
+                                 " (use stig_apply_Pinv with a workspace)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(STIG_EINVAL, "the plan's device is not the current device");
+  char *base = nullptr;
+  STIG_TRY(static_scratch(dev, &base));
+  lay_views(p, L, base, WS_APPLY, 0);
   return apply_dispatch(p, r, s, nrhs, transpose ? 1 : 0, prec);
 }
 
