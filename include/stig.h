@@ -121,19 +121,25 @@ stig_status stig_set_workspace(stig_plan *plan, void *ws, size_t bytes);
  *   STIG_OPT_PLANE_FUSION: 1 (default) = the mode-1 and mode-2 products of
  *     steps 2 and 4 (Section 2.3, Algorithm 1) in one fused pass per plane when
  *     n_s[0] == n_s[1] <= 80 and no diagonal scaling is set; 0 = one pass per mode.
- *   STIG_OPT_TIME_KERNEL: how the shifted time systems of step 3 are eliminated
- *     for the register-resident shapes (n_t, p_t) = (66, 3), (50, 3), (9, 2):
- *     0 (default) = right-looking with window-state checkpoints, the forward
- *     substitution redone segment by segment in the backward sweep (nothing
- *     stored); 3 = the same with the forward-substituted values stored and read
- *     back; 1 = left-looking, U-row checkpoints; 2 = the generic kernel with
- *     scratch memory (the one every other shape uses); 4 = the paper's own
- *     form (Section 4.2.2, eq. time_eig_2, eq. block_LU): the time pencil
- *     transformed by the real block form of its arrowhead factorization (dense
- *     products along t on MFMA) and the arrowhead middle factor solved by block
- *     LU, for n_t = 34 and 66 only: STIG_EINVAL for other n_t (or when the
- *     set-up time pencil has no arrowhead factorization), and
- *     stig_setup_1d_pencils returns STIG_EBREAKDOWN if it cannot build it.
+ *   STIG_OPT_TIME_KERNEL: how step 3 treats the shifted time systems.
+ *     0 (default): for the register-resident shapes (n_t, p_t) = (66, 3),
+ *     (50, 3), (9, 2), banded elimination right-looking with window-state
+ *     checkpoints, the forward substitution redone segment by segment in the
+ *     backward sweep (nothing stored); for n_t = 131 with fewer than 262,144
+ *     systems per call (N_s times the right-hand sides), the arrowhead form of 4
+ *     (its products along t have a compile-time kernel there); otherwise the
+ *     generic banded kernel of 2.
+ *     3 = as 0, with the forward-substituted values stored and read back;
+ *     1 = left-looking, U-row checkpoints (register shapes; generic otherwise);
+ *     2 = the generic banded kernel with scratch memory;
+ *     4 = the paper's own form (Section 4.2.2, eq. time_eig_2, eq. block_LU):
+ *     the time pencil transformed by the real block form of its arrowhead
+ *     factorization (dense products along t on MFMA) and the arrowhead middle
+ *     factor solved by block LU: one fused kernel for n_t = 34 and 66, three
+ *     passes (product, middle factor, product) for any other n_t <= 200.
+ *     STIG_EINVAL for other n_t or when the set-up time pencil has no arrowhead
+ *     factorization; stig_setup_1d_pencils returns STIG_EBREAKDOWN if it cannot
+ *     build it while 4 is selected.
  *   STIG_OPT_PARITY_SPLIT: 1 (default) = where a spatial pencil is
  *     persymmetric (stig_setup_1d_pencils then picks an eigenbasis of even and
  *     odd modes), its mode products run as two half-size products around a

@@ -212,4 +212,82 @@ time_arrow_solve(const Tio *__restrict__ in, Tio *__restrict__ out,
   }
 }
 
+// ---------------------------------------------- any n_t: the middle factor
+// Step 3 in the arrowhead form for any n_t, as three passes: x~ = U^T r along t
+// (a mode product on MFMA), this kernel, then y = U q along t.  Modes are in
+// the natural order of the real block form: the zero mode first when the
+// skew part has odd size (nz = 1), then the 2 x 2 blocks (nz + 2j, nz + 2j + 1),
+// the arrow mode n - 1 last.  For each system k (column c = rhs * ns + k of x,
+// layout [rhs][mode][ns]) the arrowhead middle factor gamma D + nu lam_k I
+// (eq. block_LU) is solved in place: q_B = H^{-1} (x_B - gamma g q_n),
+// q_n = (x_n - gamma h^T H^{-1} x_B) / (gamma sigma + nu lam_k
+//       - gamma^2 h^T H^{-1} g),
+// H = gamma B + nu lam_k I block diagonal with closed-form 2 x 2 inverses.
+// tab: d of the block that starts at mode a (index a; other entries unused),
+// g[n], h[n] (arrow column / row), sigma, i.e. [d | g | h | sigma].
+// L lanes per system: lanes c % 16 + 16 l (l < L) of a wave share column c
+// and take every L-th block; the two sums are reduced across them.  Two passes
+// over the modes (the second re-reads x, from L2), so nothing is held per mode.
+template <typename TC, int L>
+__global__ void __launch_bounds__(256)
+time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *__restrict__ tab,
+                  TC gamma, TC nu, int n, int nz, int64_t ns, int64_t cols) {
+  static_assert(L == 1 || L == 2 || L == 4, "lanes per system");
+  const int lane = threadIdx.x & 63, sub = lane >> 4;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // a wave covers 64 / L columns: 16 per group of 16 lanes, groups l >= L take
+  // the next 16 columns
+  const int grp = sub % L, cset = sub / L;
+  const int64_t c = wave * (64 / L) + cset * 16 + (lane & 15);
+  const bool valid = c < cols;
+  const int64_t cc = valid ? c : 0;
+  const int64_t rhs = cc / ns, k = cc - rhs * ns;
+  TC *xc = x + rhs * ns * n + k;
+  const TC nul = nu * (TC)lam[k];
+  const int nb = (n - 1 - nz) / 2;  // 2 x 2 blocks
+  const TC *dd = tab, *gv = tab + n, *hv = tab + 2 * n;
+  auto lsum = [](TC v) {
+    if (L >= 2) v += __shfl_xor(v, 16, 64);
+    if (L >= 4) v += __shfl_xor(v, 32, 64);
+    return v;
+  };
+  // pass 1: sums h^T H^{-1} g and h^T H^{-1} x
+  TC sp = 0, yp = 0;
+  for (int j = grp; j < nb; j += L) {
+    const int a = nz + 2 * j;
+    const TC x1 = xc[(int64_t)a * ns], x2 = xc[(int64_t)(a + 1) * ns];
+    const TC gd = gamma * dd[a], inv = recip(nul * nul + gd * gd);
+    const TC g1 = gv[a], g2 = gv[a + 1], h1 = hv[a], h2 = hv[a + 1];
+    sp += (h1 * (nul * g1 - gd * g2) + h2 * (gd * g1 + nul * g2)) * inv;
+    yp += (h1 * (nul * x1 - gd * x2) + h2 * (gd * x1 + nul * x2)) * inv;
+  }
+  sp = lsum(sp);
+  yp = lsum(yp);
+  const TC rnul = recip(nul);
+  TC xz = 0;
+  if (nz) {
+    xz = xc[0];
+    sp += hv[0] * gv[0] * rnul;
+    yp += hv[0] * xz * rnul;
+  }
+  const TC xn = xc[(int64_t)(n - 1) * ns];
+  const TC sch = gamma * tab[3 * n] + nul - gamma * gamma * sp;
+  const TC qn = (xn - gamma * yp) * recip(sch);
+  // pass 2: q_B = H^{-1} (x_B - gamma g q_n)
+  for (int j = grp; j < nb; j += L) {
+    const int a = nz + 2 * j;
+    const TC g1 = gv[a], g2 = gv[a + 1];
+    const TC x1 = xc[(int64_t)a * ns] - gamma * g1 * qn, x2 = xc[(int64_t)(a + 1) * ns] - gamma * g2 * qn;
+    const TC gd = gamma * dd[a], inv = recip(nul * nul + gd * gd);
+    if (valid) {
+      xc[(int64_t)a * ns] = (nul * x1 - gd * x2) * inv;
+      xc[(int64_t)(a + 1) * ns] = (gd * x1 + nul * x2) * inv;
+    }
+  }
+  if (valid && grp == 0) {
+    if (nz) xc[0] = (xz - gamma * gv[0] * qn) * rnul;
+    xc[(int64_t)(n - 1) * ns] = qn;
+  }
+}
+
 }  // namespace stig

@@ -135,8 +135,15 @@ struct stig_plan {
   DevBuf tR64[2], tR32[2];  // step records of [W; M] and [W^T; M] (right-looking solve)
   // arrowhead form of the time pencil (n_t = 32 q + 2): U^T and U in mode order
   // per precision [f64, f32, bf16], tables [d | g | h | sigma] plain / transposed
-  bool arrow_ok = false;
+  bool arrow_ok = false;     // the fused kernel's tables (n_t = 32 q + 2, one zero mode)
   DevBuf aTf[3], aTb[3], aTab64[2], aTab32[2];
+  // the same factorization for any n_t (three-pass form): U^T (rows = modes)
+  // and U (rows = t) in natural mode order per precision, the middle-factor
+  // tables [d | g | h | sigma] plain / transposed, the zero-mode count
+  bool arrow_gen = false;
+  int arrow_nz = 0;
+  DevBuf aGf[3], aGb[3], aGtab64[2], aGtab32[2];
+  std::vector<double> hWt, hMt;  // host copies of the time factors (arrowhead setup)
   DevBuf tgW, tgWT, tnM;  // time bands scaled by gamma / nu (matvec)
   DevBuf sK[3], sM[3];    // spatial bands (matvec, mass apply)
   DevBuf sId, sZero;      // one-row identity / zero band (third direction of a 2D stencil)
@@ -305,17 +312,59 @@ template <> std::vector<uint16_t> convert(const std::vector<double> &v) {
   return o;
 }
 
-// Arrowhead form of the time pencil for the fused time kernel (kernels_arrow.h):
-// for n_t = 32 q + 2 with a zero mode, U^T / U in the kernel's mode order and the
-// block-LU tables, for W_t and (transposed systems) W_t^T, whose form is D^T:
-// d -> -d, arrow column and row exchanged.  Other shapes leave arrow_ok false.
-stig_status setup_arrowhead(stig_plan *p, const double *Wt, const double *Mt) {
+// Largest n_t of the three-pass arrowhead form (its mode products stage U in LDS).
+constexpr int ARROW_GEN_MAX_NT = 200;
+
+// Arrowhead form of the time pencil (Section 4.2.2, eq. time_eig_2).  For any
+// n_t <= ARROW_GEN_MAX_NT (when `general`): U^T / U in natural mode order and the
+// middle-factor tables of the three-pass form (arrow_gen).  For n_t = 32 q + 2
+// with a zero mode: the fused kernel's tables (kernels_arrow.h), U^T / U in its
+// mode order (arrow_ok).  Both for W_t and (transposed systems) W_t^T, whose
+// form is D^T: d -> -d, arrow column and row exchanged.  A pencil without the
+// block structure leaves both false.
+stig_status setup_arrowhead(stig_plan *p, bool general) {
   p->arrow_ok = false;
+  p->arrow_gen = false;
   const int n = p->nt;
-  if (n < 34 || (n - 2) % 32 != 0) return STIG_OK;
+  const bool fused_shape = n >= 34 && (n - 2) % 32 == 0;
+  general = general && n <= ARROW_GEN_MAX_NT;
+  if (!fused_shape && !general) return STIG_OK;
+  if ((int)p->hWt.size() != n * n || (int)p->hMt.size() != n * n) return STIG_OK;
+  const double *Wt = p->hWt.data(), *Mt = p->hMt.data();
   std::vector<double> U((size_t)n * n), D((size_t)n * n);
   int nz = 0;
-  if (!time_arrowhead(n, Wt, Mt, 1e-10, U.data(), D.data(), &nz) || nz != 1) return STIG_OK;
+  if (!time_arrowhead(n, Wt, Mt, 1e-10, U.data(), D.data(), &nz)) return STIG_OK;
+  if (general) {
+    // natural order: zero mode (nz = 1), blocks (nz + 2j, nz + 2j + 1), arrow n - 1
+    std::vector<double> gf((size_t)n * n);
+    for (int r = 0; r < n; ++r)
+      for (int t = 0; t < n; ++t) gf[(size_t)r * n + t] = U[(size_t)t * n + r];
+    STIG_TRY(upload(p->aGf[0], gf, p->stream));
+    STIG_TRY(upload(p->aGb[0], U, p->stream));
+    STIG_TRY(upload(p->aGf[1], convert<float>(gf), p->stream));
+    STIG_TRY(upload(p->aGb[1], convert<float>(U), p->stream));
+    STIG_TRY(upload(p->aGf[2], convert<uint16_t>(gf), p->stream));
+    STIG_TRY(upload(p->aGb[2], convert<uint16_t>(U), p->stream));
+    for (int tr = 0; tr < 2; ++tr) {
+      std::vector<double> tab((size_t)3 * n + 1, 0.0);
+      for (int a = nz; a + 1 < n - 1; a += 2) {
+        const double d = D[(size_t)a * n + a + 1];
+        tab[a] = tr ? -d : d;
+      }
+      for (int r = 0; r < n - 1; ++r) {
+        const double gcol = D[(size_t)r * n + (n - 1)], hrow = D[(size_t)(n - 1) * n + r];
+        tab[n + r] = tr ? hrow : gcol;
+        tab[2 * n + r] = tr ? gcol : hrow;
+      }
+      tab[3 * n] = D[(size_t)(n - 1) * n + (n - 1)];
+      STIG_TRY(upload(p->aGtab64[tr], tab, p->stream));
+      STIG_TRY(upload(p->aGtab32[tr], convert<float>(tab), p->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->arrow_nz = nz;
+    p->arrow_gen = true;
+  }
+  if (!fused_shape || nz != 1) return STIG_OK;
   const int NM = n - 2;  // modes in 2 x 2 blocks
   // mode order: block j -> rows 32 (j/16) + j%16 and that + 16; zero mode NM;
   // last mode NM + 1.  perm[r] = natural index (zero mode 0, block j: 1 + 2j, 2 + 2j).
@@ -377,31 +426,45 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   typedef typename Mfma<TC>::elem E;
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
   // streaming kernel: compile-time sizes of the workloads' spatial directions
-  // (65, 49: cube; 32: extruded annulus; 130: annulus; scaled: 32, 130), runtime
-  // n up to GEMM2_MAX_N otherwise
+  // (65, 49: cube; 32: extruded annulus; 130: annulus; scaled: 32, 130) and of
+  // the annulus time axis (131, arrowhead form), runtime n up to GEMM2_MAX_N
+  // otherwise
   const bool sc = in_scale || out_scale;
   const int nc = sc ? ((n == 32 || n == 130) ? n : 0)
-                    : ((n == 65 || n == 49 || n == 32 || n == 130) ? n : 0);
+                    : ((n == 65 || n == 49 || n == 32 || n == 130 || n == 131) ? n : 0);
   if (nc != 0 || n <= GEMM2_MAX_N) {
     // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N;
     // n = 130 splits its 8 full row tiles over 4 blocks in FP64 (rows: 32 + 2
     // fringe) and over 2 in FP32 / BF16 (64 + 2), the faster split for each
     constexpr int RS130 = sizeof(E) == 8 ? 4 : 2;
     const int nm = nc ? nc : GEMM2_MAX_N;
-    const int rs = nc == 130 ? RS130 : 1;
+    const int rs = (nc == 130 || nc == 131) ? RS130 : 1;
     const int rows = rs == 1 ? round_up(nm, 16) : 16 * (nm / 16 / rs) + nm % 16;
     size_t lds = (size_t)rows * lds_ld<TC>(nm) * sizeof(E);
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
-    unsigned grid = (unsigned)std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID) * rs;
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
     static size_t configured[10] = {};  // per kernel of this type triple
+    static int per_cu[10] = {};         // resident blocks per CU at that LDS size
+    static size_t per_cu_lds[10] = {};
     auto go = [&](auto kern, int slot) -> stig_status {
       if (lds > 65536 && lds > configured[slot]) {
         HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds));
         configured[slot] = lds;
       }
+      if (per_cu_lds[slot] != lds) {
+        int nb = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, GEMM2_THREADS, lds));
+        per_cu[slot] = std::max(nb, 1);
+        per_cu_lds[slot] = lds;
+      }
+      // persistent: no more block groups than are resident at once, so the
+      // strips beyond one round are prefetched by running waves instead of
+      // starting new blocks (which would fill Op into LDS again)
+      const int64_t resident = std::max<int64_t>(1, (int64_t)per_cu[slot] * p->num_cu / rs);
+      const unsigned grid =
+          (unsigned)std::min<int64_t>(std::min<int64_t>((nstrips + 3) / 4, GEMM2_GRID), resident) * rs;
       hipLaunchKernelGGL(kern, dim3(grid), dim3(GEMM2_THREADS), lds, p->stream, in, out, op, n,
                          inner, total_cols, in_scale, out_scale, p->N);
       HIP_TRY(hipGetLastError());
@@ -416,6 +479,7 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     if (nc == 49) return go(mode_gemm_small<Tin, Tout, TC, 49, false>, 1);
     if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, false>, 2);
     if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false, RS130>, 3);
+    if (nc == 131) return go(mode_gemm_small<Tin, Tout, TC, 131, false, RS130>, 8);
     return go(mode_gemm_small<Tin, Tout, TC, 0, false>, 4);
   }
   const int jt = (n + 15) / 16;
@@ -734,12 +798,65 @@ stig_status launch_time_arrow(stig_plan *p, const Tio *in, Tio *out, int nrhs, i
   return fail(STIG_EINVAL, "no arrowhead kernel for this n_t");
 }
 
+template <typename Tio, typename TC>
+stig_status launch_time_banded(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                               TimeView tv);
+
+// Step 3 in the three-pass arrowhead form (any n_t): x~ = U^T r along t into
+// the time scratch (compute type TC), the middle factor in place, s = U q.
+// GM: MFMA type of the two products (that of the apply's mode products).
+template <typename Tio, typename TC, typename GM>
+stig_status launch_time_arrow_gen(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                                  TimeView tv) {
+  typedef typename Mfma<GM>::elem E;
+  const int pi = PrecIdx<GM>::v;
+  const int64_t cols = tv.ns * nrhs;
+  STIG_TRY(p->tscr.ensure((size_t)cols * p->nt * sizeof(TC)));
+  TC *mid = p->tscr.as<TC>();
+  STIG_TRY((launch_mode_gemm<Tio, TC, GM>(p, in, mid, p->aGf[pi].as<E>(), p->nt, tv.ns, cols,
+                                          nullptr, nullptr)));
+  const TC *tab = std::is_same<TC, double>::value
+                      ? (const TC *)p->aGtab64[transpose ? 1 : 0].p
+                      : (const TC *)p->aGtab32[transpose ? 1 : 0].p;
+  {
+    ProfScope ps(p, STIG_K_TIME_SOLVE, (double)cols * p->nt * 3 * sizeof(TC));
+    constexpr int L = 4;
+    const int64_t waves = (cols + 64 / L - 1) / (64 / L);
+    if (waves * 64 > ((int64_t)1 << 20) * 256) return fail(STIG_EINVAL, "too many time systems");
+    hipLaunchKernelGGL((time_arrow_middle<TC, L>), dim3(grid_for(waves * 64, 256)), dim3(256), 0,
+                       p->stream, mid, tv.lam, tab, (TC)p->gamma, (TC)p->nu, p->nt, p->arrow_nz,
+                       tv.ns, cols);
+    HIP_TRY(hipGetLastError());
+  }
+  return launch_mode_gemm<TC, Tio, GM>(p, mid, out, p->aGb[pi].as<E>(), p->nt, tv.ns, cols,
+                                       nullptr, nullptr);
+}
+
 // (n_t, p_t) shapes with register-resident time kernels
 bool time_reg_shape(const stig_plan *p) {
   return (p->nt == 66 && p->pt == 3) || (p->nt == 50 && p->pt == 3) || (p->nt == 9 && p->pt == 2);
 }
 bool time_arrow_shape(const stig_plan *p) {
   return p->time_kernel == 4 && p->arrow_ok && (p->nt == 66 || p->nt == 34);
+}
+// Fewer shifted systems than this (N_s times the right-hand sides of a call)
+// leave the banded elimination, one lane per system, short of waves (below one
+// wavefront per SIMD at four waves each), and a long time axis makes each lane's
+// chain long: the default (time kernel 0) then takes the arrowhead three-pass
+// form, whose mode products parallelise over the time axis too, where its
+// products have a compile-time streaming kernel (n_t = 131; measured faster
+// there: 0.20 vs 0.25 ms per FP64 apply on the 128-element annulus, slower at
+// n_t = 33 with 32,768 systems, 0.115 vs 0.080 ms).
+constexpr int64_t ARROW_AUTO_SYSTEMS = 262144;
+bool arrow_auto_nt(int nt) { return nt == 131; }
+
+// the three-pass arrowhead form: chosen (time kernel 4, other n_t than the
+// fused kernel's) or taken by the default
+bool time_arrow_gen(const stig_plan *p, int64_t systems) {
+  if (!p->arrow_gen || time_arrow_shape(p)) return false;
+  if (p->time_kernel == 4) return true;
+  return p->time_kernel == 0 && !time_reg_shape(p) && arrow_auto_nt(p->nt) &&
+         systems < ARROW_AUTO_SYSTEMS;
 }
 
 // Compute-type entries of scratch the time solve of `ns` systems per time row
@@ -751,6 +868,7 @@ bool time_arrow_shape(const stig_plan *p) {
 int64_t time_scratch_elems(const stig_plan *p, int64_t ns, int nrhs, bool tc_f64, bool io_is_tc) {
   const int64_t sys = ns * p->nt * nrhs;
   if (time_arrow_shape(p)) return 0;
+  if (time_arrow_gen(p, ns * nrhs)) return sys;  // x~ / q between the two products
   if (time_reg_shape(p)) {
     if (p->time_kernel == 1) return (tc_f64 && !io_is_tc) ? sys : 0;
     if (p->time_kernel == 0) return (p->time_recompute || io_is_tc) ? 0 : sys;
@@ -761,11 +879,21 @@ int64_t time_scratch_elems(const stig_plan *p, int64_t ns, int nrhs, bool tc_f64
 template <typename Tio, typename TC>
 stig_status launch_time(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
                         TimeView tv) {
-  // register-resident kernels for the workload shapes (n_t, p_t); generic otherwise
-  if (p->time_kernel == 4) {
-    if (!time_arrow_shape(p)) return fail(STIG_ESTATE, "no arrowhead factorization of the time pencil");
-    return launch_time_arrow<Tio, typename TimeArrowType<Tio, TC>::type>(p, in, out, nrhs, transpose, tv);
-  }
+  if (time_arrow_shape(p))
+    return launch_time_arrow<Tio, typename TimeArrowType<Tio, TC>::type>(p, in, out, nrhs,
+                                                                         transpose, tv);
+  if (time_arrow_gen(p, tv.ns * nrhs))
+    return launch_time_arrow_gen<Tio, TC, typename TimeArrowType<Tio, TC>::type>(p, in, out, nrhs,
+                                                                                transpose, tv);
+  if (p->time_kernel == 4) return fail(STIG_ESTATE, "no arrowhead factorization of the time pencil");
+  return launch_time_banded<Tio, TC>(p, in, out, nrhs, transpose, tv);
+}
+
+// The banded eliminations: register-resident kernels for the workload shapes
+// (n_t, p_t) under time kernels 0 and 1, the generic kernel otherwise.
+template <typename Tio, typename TC>
+stig_status launch_time_banded(stig_plan *p, const Tio *in, Tio *out, int nrhs, int transpose,
+                               TimeView tv) {
   if (p->time_kernel == 1) {
     if (p->nt == 66 && p->pt == 3) return launch_time_reg<Tio, TC, 66, 3, 11>(p, in, out, nrhs, transpose, tv);
     if (p->nt == 50 && p->pt == 3) return launch_time_reg<Tio, TC, 50, 3, 10>(p, in, out, nrhs, transpose, tv);
@@ -1928,10 +2056,14 @@ stig_status stig_set_option(stig_plan *plan, int option, int value) {
       return STIG_OK;
     case STIG_OPT_TIME_KERNEL:
       if (value < 0 || value > 4) return fail(STIG_EINVAL, "time kernel takes 0 .. 4");
-      if (value == 4 && plan->nt != 34 && plan->nt != 66)
-        return fail(STIG_EINVAL, "the arrowhead time kernel needs n_t = 34 or 66");
-      if (value == 4 && plan->ready && !plan->arrow_ok)
-        return fail(STIG_EINVAL, "the time pencil has no arrowhead factorization");
+      if (value == 4 && plan->nt > ARROW_GEN_MAX_NT && (plan->nt - 2) % 32 != 0)
+        return fail(STIG_EINVAL, "the arrowhead time kernel needs n_t <= 200 or n_t = 32 q + 2");
+      if (value == 4 && plan->ready && !plan->arrow_ok && !plan->arrow_gen) {
+        // factor the set-up time pencil now (host work and uploads)
+        STIG_TRY(setup_arrowhead(plan, true));
+        if (!plan->arrow_ok && !plan->arrow_gen)
+          return fail(STIG_EINVAL, "the time pencil has no arrowhead factorization");
+      }
       plan->time_kernel = value == 3 ? 0 : value;
       plan->time_recompute = value != 3;
       return STIG_OK;
@@ -2076,8 +2208,12 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     STIG_TRY(upload(p->tR64[tr], rec, s));
     STIG_TRY(upload(p->tR32[tr], convert<float>(rec), s));
   }
-  STIG_TRY(setup_arrowhead(p, Wt, Mt));
-  if (p->time_kernel == 4 && !p->arrow_ok)
+  p->hWt.assign(Wt, Wt + (size_t)nt * nt);
+  p->hMt.assign(Mt, Mt + (size_t)nt * nt);
+  // the general arrowhead form where it can run: chosen, or a default for shapes
+  // without a register-resident banded kernel
+  STIG_TRY(setup_arrowhead(p, p->time_kernel == 4 || arrow_auto_nt(nt)));
+  if (p->time_kernel == 4 && !p->arrow_ok && !p->arrow_gen)
     return fail(STIG_EBREAKDOWN, "arrowhead factorization of the time pencil not reached "
                                  "(time kernel 4 selected)");
   std::vector<double> gw(wb), gwt(wtb), nm(mb);
@@ -2099,13 +2235,16 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
     DevBuf zin, zout, zscr;
     STIG_TRY(zin.ensure(p->N * sizeof(double)));
     STIG_TRY(zout.ensure(p->N * sizeof(double)));
-    const size_t scr = time_scratch_elems(p, p->Ns, 1, true, true) * sizeof(double);
+    // the banded elimination checks its pivots (whatever form the apply uses)
+    const bool reg = time_reg_shape(p) && (p->time_kernel == 0 || p->time_kernel == 1);
+    const size_t scr = reg ? 0 : (size_t)(p->pt + 1) * p->N * sizeof(double);
     if (scr) STIG_TRY(zscr.ensure(scr));
     const Span keep = p->tscr;
     p->tscr.p = zscr.p;
     p->tscr.bytes = scr;
     HIP_TRY(hipMemsetAsync(zin.p, 0, p->N * sizeof(double), s));
-    const stig_status st = launch_time<double, double>(p, zin.as<double>(), zout.as<double>(), 1, 0);
+    const stig_status st = launch_time_banded<double, double>(
+        p, zin.as<double>(), zout.as<double>(), 1, 0, TimeView{p->Ns, p->lam.as<double>()});
     p->tscr = keep;
     STIG_TRY(st);
     HIP_TRY(hipStreamSynchronize(s));
@@ -2566,7 +2705,9 @@ size_t stig_plan_device_bytes(const stig_plan *p) {
   size_t t = 0;
   const DevBuf *bs[] = {&p->lam, &p->lamp[0], &p->lamp[1], &p->lamp[2], &p->aTf[0], &p->aTf[1],
                         &p->aTf[2], &p->aTb[0], &p->aTb[1], &p->aTb[2], &p->aTab64[0],
-                        &p->aTab64[1], &p->aTab32[0], &p->aTab32[1], &p->tW64, &p->tWT64, &p->tM64,
+                        &p->aTab64[1], &p->aTab32[0], &p->aTab32[1], &p->aGf[0], &p->aGf[1],
+                        &p->aGf[2], &p->aGb[0], &p->aGb[1], &p->aGb[2], &p->aGtab64[0],
+                        &p->aGtab64[1], &p->aGtab32[0], &p->aGtab32[1], &p->tW64, &p->tWT64, &p->tM64,
                         &p->tW32, &p->tWT32, &p->tM32, &p->tR64[0], &p->tR64[1], &p->tR32[0],
                         &p->tR32[1], &p->tgW, &p->tgWT, &p->tnM, &p->dmh, &p->sId, &p->sZero,
                         &p->partial, &p->small, &p->flag};

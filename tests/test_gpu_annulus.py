@@ -31,10 +31,24 @@ def test_annulus_csr_matvec_and_preconditioner_match_oracle():
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
     P = o.preconditioner()
     ref_s = P.apply(x)
+    ref_t = P.apply(x, transpose=True)
     s = plan.apply_Pinv(_dev(x)).cpu().numpy()
     assert np.abs(s - ref_s).max() <= 1e-12 * np.abs(ref_s).max()
     s32 = plan.apply_Pinv(_dev(x), prec="fp32").cpu().numpy()
     assert np.abs(s32 - ref_s).max() <= 1e-4 * np.abs(ref_s).max()
+    # both forms of step 3 (the default picks the arrowhead form at n_t = 131:
+    # MFMA products along t around the block-LU middle factor; the generic
+    # banded elimination on request)
+    for tk in ("arrowhead", "generic"):
+        plan.set_option("time_kernel", tk)
+        for tr, ref in ((False, ref_s), (True, ref_t)):
+            sa = plan.apply_Pinv(_dev(x), transpose=tr).cpu().numpy()
+            ea = np.abs(sa - ref).max() / np.abs(ref).max()
+            sa32 = plan.apply_Pinv(_dev(x), transpose=tr, prec="fp32").cpu().numpy()
+            ea32 = np.abs(sa32 - ref).max() / np.abs(ref).max()
+            print(f"annulus {tk} apply (transpose={tr}): FP64 {ea:.2e}, FP32 {ea32:.2e}")
+            assert ea <= 1e-12 and ea32 <= 1e-4
+    plan.set_option("time_kernel", "right_looking")
     # diag(A-hat^G) = diag(A): D^{1/2} A-tilde D^{1/2} reproduces the diagonal exactly
     assert np.allclose(o.D().ravel() * o.diag_Atilde().ravel(), o.diag_A().ravel(), rtol=1e-13)
 

@@ -172,9 +172,13 @@ def test_argument_validation_without_gpu():
     assert lib.stig_set_workspace(h, None, 0) == 0
     lib.stig_plan_destroy(h)
     assert lib.stig_status_string(-4) == b"breakdown (non-positive pivot)"
-    # the arrowhead time kernel exists for n_t = 34 and 66 only (n_t = 131: refused)
+    # the arrowhead time kernel: any n_t up to 200 (three-pass form) or n_t = 32 q + 2
+    # (fused kernel); n_t = 300 is refused
     n2 = (C.c_int * 2)(130, 130)
     assert lib.stig_plan_create(C.byref(h), 2, n2, 131, 4, 4, None) == 0
+    assert lib.stig_set_option(h, 1, 4) == 0
+    lib.stig_plan_destroy(h)
+    assert lib.stig_plan_create(C.byref(h), 2, n2, 300, 4, 4, None) == 0
     assert lib.stig_set_option(h, 1, 4) == -1
     assert b"n_t" in lib.stig_last_error()
     assert lib.stig_set_option(h, 1, 2) == 0
