@@ -214,17 +214,18 @@ time_arrow_solve(const Tio *__restrict__ in, Tio *__restrict__ out,
 
 // ---------------------------------------------- any n_t: the middle factor
 // Step 3 in the arrowhead form for any n_t, as three passes: x~ = U^T r along t
-// (a mode product on MFMA), this kernel, then y = U q along t.  Modes are in
-// the natural order of the real block form: the zero mode first when the
-// skew part has odd size (nz = 1), then the 2 x 2 blocks (nz + 2j, nz + 2j + 1),
-// the arrow mode n - 1 last.  For each system k (column c = rhs * ns + k of x,
+// (a mode product on MFMA), this kernel, then y = U q along t.  (Fusing this
+// step into the second product's operand load was measured slower in every
+// precision: it leaves one wave per SIMD.)  Mode order: the 2 x 2 blocks
+// (2j, 2j + 1) first, then the zero mode (position n - 2) when the skew part
+// has odd size (nz = 1), the arrow mode n - 1 last.  For each system k (column c = rhs * ns + k of x,
 // layout [rhs][mode][ns]) the arrowhead middle factor gamma D + nu lam_k I
 // (eq. block_LU) is solved in place: q_B = H^{-1} (x_B - gamma g q_n),
 // q_n = (x_n - gamma h^T H^{-1} x_B) / (gamma sigma + nu lam_k
 //       - gamma^2 h^T H^{-1} g),
 // H = gamma B + nu lam_k I block diagonal with closed-form 2 x 2 inverses.
-// tab: d of the block that starts at mode a (index a; other entries unused),
-// g[n], h[n] (arrow column / row), sigma, i.e. [d | g | h | sigma].
+// tab: d of each mode's block (at both positions of the block), g[n], h[n]
+// (arrow column / row), sigma, i.e. [d | g | h | sigma].
 // L lanes per system: lanes c % 16 + 16 l (l < L) of a wave share column c
 // and take every L-th block; the two sums are reduced across them.  Two passes
 // over the modes (the second re-reads x, from L2), so nothing is held per mode.
@@ -256,7 +257,7 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   TC sp = 0, yp = 0;
 #pragma unroll 4
   for (int j = grp; j < nb; j += L) {
-    const int a = nz + 2 * j;
+    const int a = 2 * j;
     const TC x1 = xc[(int64_t)a * ns], x2 = xc[(int64_t)(a + 1) * ns];
     const TC gd = gamma * dd[a], inv = recip(nul * nul + gd * gd);
     const TC g1 = gv[a], g2 = gv[a + 1], h1 = hv[a], h2 = hv[a + 1];
@@ -268,9 +269,9 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   const TC rnul = recip(nul);
   TC xz = 0;
   if (nz) {
-    xz = xc[0];
-    sp += hv[0] * gv[0] * rnul;
-    yp += hv[0] * xz * rnul;
+    xz = xc[(int64_t)(n - 2) * ns];
+    sp += hv[n - 2] * gv[n - 2] * rnul;
+    yp += hv[n - 2] * xz * rnul;
   }
   const TC xn = xc[(int64_t)(n - 1) * ns];
   const TC sch = gamma * tab[3 * n] + nul - gamma * gamma * sp;
@@ -278,7 +279,7 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   // pass 2: q_B = H^{-1} (x_B - gamma g q_n)
 #pragma unroll 4
   for (int j = grp; j < nb; j += L) {
-    const int a = nz + 2 * j;
+    const int a = 2 * j;
     const TC g1 = gv[a], g2 = gv[a + 1];
     const TC x1 = xc[(int64_t)a * ns] - gamma * g1 * qn, x2 = xc[(int64_t)(a + 1) * ns] - gamma * g2 * qn;
     const TC gd = gamma * dd[a], inv = recip(nul * nul + gd * gd);
@@ -288,7 +289,7 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
     }
   }
   if (valid && grp == 0) {
-    if (nz) xc[0] = (xz - gamma * gv[0] * qn) * rnul;
+    if (nz) xc[(int64_t)(n - 2) * ns] = (xz - gamma * gv[n - 2] * qn) * rnul;
     xc[(int64_t)(n - 1) * ns] = qn;
   }
 }

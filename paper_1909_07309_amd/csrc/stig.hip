@@ -335,26 +335,37 @@ stig_status setup_arrowhead(stig_plan *p, bool general) {
   int nz = 0;
   if (!time_arrowhead(n, Wt, Mt, 1e-10, U.data(), D.data(), &nz)) return STIG_OK;
   if (general) {
-    // natural order: zero mode (nz = 1), blocks (nz + 2j, nz + 2j + 1), arrow n - 1
-    std::vector<double> gf((size_t)n * n);
+    // mode order of the three-pass form: blocks (2j, 2j + 1) first (natural
+    // modes nz + 2j, nz + 2j + 1), the zero mode at n - 2 (natural 0) when
+    // nz = 1, the arrow mode n - 1 last; perm[position] = natural mode
+    std::vector<int> perm(n);
+    for (int q = 0; q < n - 1 - nz; ++q) perm[q] = nz + q;
+    if (nz) perm[n - 2] = 0;
+    perm[n - 1] = n - 1;
+    std::vector<double> gf((size_t)n * n), gb((size_t)n * n);
     for (int r = 0; r < n; ++r)
-      for (int t = 0; t < n; ++t) gf[(size_t)r * n + t] = U[(size_t)t * n + r];
+      for (int t = 0; t < n; ++t) {
+        gf[(size_t)r * n + t] = U[(size_t)t * n + perm[r]];
+        gb[(size_t)t * n + r] = U[(size_t)t * n + perm[r]];
+      }
     STIG_TRY(upload(p->aGf[0], gf, p->stream));
-    STIG_TRY(upload(p->aGb[0], U, p->stream));
+    STIG_TRY(upload(p->aGb[0], gb, p->stream));
     STIG_TRY(upload(p->aGf[1], convert<float>(gf), p->stream));
-    STIG_TRY(upload(p->aGb[1], convert<float>(U), p->stream));
+    STIG_TRY(upload(p->aGb[1], convert<float>(gb), p->stream));
     STIG_TRY(upload(p->aGf[2], convert<uint16_t>(gf), p->stream));
-    STIG_TRY(upload(p->aGb[2], convert<uint16_t>(U), p->stream));
+    STIG_TRY(upload(p->aGb[2], convert<uint16_t>(gb), p->stream));
     for (int tr = 0; tr < 2; ++tr) {
       std::vector<double> tab((size_t)3 * n + 1, 0.0);
-      for (int a = nz; a + 1 < n - 1; a += 2) {
+      for (int q = 0; q + 1 < n - 1 - nz; q += 2) {
+        const int a = perm[q];
         const double d = D[(size_t)a * n + a + 1];
-        tab[a] = tr ? -d : d;
+        tab[q] = tab[q + 1] = tr ? -d : d;
       }
-      for (int r = 0; r < n - 1; ++r) {
+      for (int q = 0; q < n - 1; ++q) {
+        const int r = perm[q];
         const double gcol = D[(size_t)r * n + (n - 1)], hrow = D[(size_t)(n - 1) * n + r];
-        tab[n + r] = tr ? hrow : gcol;
-        tab[2 * n + r] = tr ? gcol : hrow;
+        tab[n + q] = tr ? hrow : gcol;
+        tab[2 * n + q] = tr ? gcol : hrow;
       }
       tab[3 * n] = D[(size_t)(n - 1) * n + (n - 1)];
       STIG_TRY(upload(p->aGtab64[tr], tab, p->stream));
@@ -444,9 +455,9 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
-    static size_t configured[10] = {};  // per kernel of this type triple
-    static int per_cu[10] = {};         // resident blocks per CU at that LDS size
-    static size_t per_cu_lds[10] = {};
+    static size_t configured[9] = {};  // per kernel of this type triple
+    static int per_cu[9] = {};         // resident blocks per CU at that LDS size
+    static size_t per_cu_lds[9] = {};
     auto go = [&](auto kern, int slot) -> stig_status {
       if (lds > 65536 && lds > configured[slot]) {
         HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
