@@ -289,17 +289,18 @@ constexpr int GEMM2_THREADS = 256;
 // NC = n as a compile-time constant (0: n taken from the argument).  With NC
 // fixed, the MFMA chain has no runtime guards, so the accumulators stay in
 // place instead of being copied at every branch.
-// SC: in_scale / out_scale (optional, length nscale, index taken modulo
-// nscale) are per-entry factors multiplied in on load / on store; a column's
+// SC: 1 = in_scale, 2 = out_scale (length nscale, index taken modulo nscale):
+// per-entry factors multiplied in on load (1) or on store (2); a column's
 // entries lie in one period of nscale, so the modulo is taken once per column.
-// The scaled form loads each strip just before multiplying it (no prefetch of
-// the next strip: the factors take those registers).  SC false: both null.
+// The scaled forms load each strip just before multiplying it (no prefetch
+// of the next strip: the factors take those registers).  Separate
+// instantiations keep each one's registers to its own path.  SC 0: both null.
 // RS > 1: the full 16-row tiles are split into RS parts, one per block of a
 // group of RS consecutive blocks (numbered so that a group shares an XCD), and
 // each block holds only its part of Op (plus the fringe rows, computed by the
 // last part) in LDS: smaller blocks, more of them per CU, shorter MFMA chains.
 // The grid is then a multiple of RS.
-template <typename Tin, typename Tout, typename TC, int NC, bool SC, int RS = 1>
+template <typename Tin, typename Tout, typename TC, int NC, int SC, int RS = 1>
 __global__ void __launch_bounds__(GEMM2_THREADS)
 mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
                 const typename Mfma<TC>::elem *__restrict__ Op, int n_arg, int64_t inner,
@@ -377,7 +378,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     const bool cvalid = strip < nstrips && c < total_cols;
     int64_t base, step;
     locate(cvalid ? c : 0, base, step);
-    if (!SC || !in_scale) {
+    if (SC != 1) {
 #pragma unroll
       for (int s = 0; s < KSMAX; ++s)
 #pragma unroll
@@ -428,7 +429,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     const bool cvalid = c < total_cols;
     int64_t base, step;
     locate(cvalid ? c : 0, base, step);
-    const int64_t sb = SC && out_scale ? base % nscale : 0;
+    const int64_t sb = SC == 2 ? base % nscale : 0;
     typename MF::acc acc[QMAX];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
@@ -478,7 +479,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     for (int t = 0; t < QMAX; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) yv[t][v] = (double)acc[t][v];
-    if (SC && out_scale) {
+    if (SC == 2) {
       // all output factors of the lane in flight at once
       double sc[QMAX][4], sf[NFR > 0 ? NFR : 1];
 #pragma unroll
@@ -514,7 +515,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     }
   };
   int64_t strip = sblk * (GEMM2_THREADS / 64) + wave;
-  if (SC) {
+  if (SC != 0) {
     for (; strip < nstrips; strip += wstride) {
       E bv[KSMAX][MF::KPL];
       load_b(strip, bv);

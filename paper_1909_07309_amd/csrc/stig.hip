@@ -443,7 +443,9 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   const bool sc = in_scale || out_scale;
   const int nc = sc ? ((n == 32 || n == 130) ? n : 0)
                     : ((n == 65 || n == 49 || n == 32 || n == 130 || n == 131) ? n : 0);
-  if (nc != 0 || n <= GEMM2_MAX_N) {
+  // the streaming kernel scales either its input or its output; both at once
+  // take the tiled kernel
+  if ((nc != 0 || n <= GEMM2_MAX_N) && !(in_scale && out_scale)) {
     // LDS as sized inside mode_gemm_small: the compile-time n, else GEMM2_MAX_N;
     // n = 130 splits its 8 full row tiles over 4 blocks in FP64 (rows: 32 + 2
     // fringe) and over 2 in FP32 / BF16 (64 + 2), the faster split for each
@@ -455,9 +457,9 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
-    static size_t configured[9] = {};  // per kernel of this type triple
-    static int per_cu[9] = {};         // resident blocks per CU at that LDS size
-    static size_t per_cu_lds[9] = {};
+    static size_t configured[12] = {};  // per kernel of this type triple
+    static int per_cu[12] = {};         // resident blocks per CU at that LDS size
+    static size_t per_cu_lds[12] = {};
     auto go = [&](auto kern, int slot) -> stig_status {
       if (lds > 65536 && lds > configured[slot]) {
         HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -481,17 +483,22 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
       HIP_TRY(hipGetLastError());
       return STIG_OK;
     };
-    if (sc) {
-      if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, true>, 5);
-      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, true, RS130>, 6);
-      return go(mode_gemm_small<Tin, Tout, TC, 0, true>, 7);
+    if (in_scale) {
+      if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, 1>, 5);
+      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, 1, RS130>, 6);
+      return go(mode_gemm_small<Tin, Tout, TC, 0, 1>, 7);
     }
-    if (nc == 65) return go(mode_gemm_small<Tin, Tout, TC, 65, false>, 0);
-    if (nc == 49) return go(mode_gemm_small<Tin, Tout, TC, 49, false>, 1);
-    if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, false>, 2);
-    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, false, RS130>, 3);
-    if (nc == 131) return go(mode_gemm_small<Tin, Tout, TC, 131, false, RS130>, 8);
-    return go(mode_gemm_small<Tin, Tout, TC, 0, false>, 4);
+    if (out_scale) {
+      if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, 2>, 9);
+      if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, 2, RS130>, 10);
+      return go(mode_gemm_small<Tin, Tout, TC, 0, 2>, 11);
+    }
+    if (nc == 65) return go(mode_gemm_small<Tin, Tout, TC, 65, 0>, 0);
+    if (nc == 49) return go(mode_gemm_small<Tin, Tout, TC, 49, 0>, 1);
+    if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, 0>, 2);
+    if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, 0, RS130>, 3);
+    if (nc == 131) return go(mode_gemm_small<Tin, Tout, TC, 131, 0, RS130>, 8);
+    return go(mode_gemm_small<Tin, Tout, TC, 0, 0>, 4);
   }
   const int jt = (n + 15) / 16;
   const int ld = lds_ld<TC>(n);
