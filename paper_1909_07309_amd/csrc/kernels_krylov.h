@@ -15,9 +15,9 @@ constexpr int KRY_MAXV = 33;     // basis vectors per call (restart <= 32) + w.w
 
 // Streaming loops take KRY_UNROLL elements per thread per trip (grid-stride
 // apart), so each thread has that many independent loads of every vector in
-// flight.  Kernels are instantiated for basis sizes up to NV (4, 8, 16, 32) so
-// that register arrays stay as small as the call needs; large bases have
-// enough loads in flight with one element per trip.
+// flight.  Kernels are instantiated for basis sizes up to NV (4, 8, 12, 16, 24,
+// 32) so that register arrays and redundant loads stay as small as the call
+// needs; large bases have enough loads in flight with one element per trip.
 constexpr int KRY_UNROLL = 4;
 template <int NV>
 constexpr int kry_unroll() {
@@ -72,16 +72,17 @@ krylov_dots(const double *__restrict__ V, int64_t ldv, int nv, const double *__r
       const int64_t e = e0 + u * stride;
       we[u] = e < N ? w[e] : 0.0;
     }
+    // branch-free: every slot loads (slots past nv re-read V_0, a cache hit,
+    // and are never stored), so all loads of a trip are in flight together
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-      if (i < nv) {
-        const double *vi = V + i * ldv;
+    for (int i = 0; i < NV; ++i) {
+      const double *vi = V + (i < nv ? i : 0) * ldv;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t e = e0 + u * stride;
-          acc[i] += (e < N ? vi[e] : 0.0) * we[u];
-        }
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + u * stride;
+        acc[i] += (e < N ? vi[e] : 0.0) * we[u];
       }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[NV] += we[u] * we[u];
   }
@@ -116,19 +117,19 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
     }
     // the basis entries stay in registers for the dot products below (for large
     // bases a second read would miss the caches)
+    // (branch-free as in krylov_dots: slots past nv have coefficient 0)
     double vv[NV][U];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-      if (i < nv) {
-        const double *vi = V + i * ldv;
-        const double c = cs[i];
+    for (int i = 0; i < NV; ++i) {
+      const double *vi = V + (i < nv ? i : 0) * ldv;
+      const double c = cs[i];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t e = e0 + u * stride;
-          vv[i][u] = e < N ? vi[e] : 0.0;
-          we[u] += c * vv[i][u];
-        }
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + u * stride;
+        vv[i][u] = e < N ? vi[e] : 0.0;
+        we[u] += c * vv[i][u];
       }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + u * stride;
@@ -137,10 +138,8 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
     if (with_dots) {
 #pragma unroll
       for (int i = 0; i < NV; ++i)
-        if (i < nv) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) acc[i] += vv[i][u] * we[u];
-        }
+        for (int u = 0; u < U; ++u) acc[i] += vv[i][u] * we[u];
 #pragma unroll
       for (int u = 0; u < U; ++u) acc[NV] += we[u] * we[u];
     }

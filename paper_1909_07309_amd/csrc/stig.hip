@@ -1503,7 +1503,9 @@ struct Krylov {
     ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 1) * p->N * 8);
     if (nv <= 4) launch_dots<4>(V, nv, w, with_norm);
     else if (nv <= 8) launch_dots<8>(V, nv, w, with_norm);
+    else if (nv <= 12) launch_dots<12>(V, nv, w, with_norm);
     else if (nv <= 16) launch_dots<16>(V, nv, w, with_norm);
+    else if (nv <= 24) launch_dots<24>(V, nv, w, with_norm);
     else launch_dots<32>(V, nv, w, with_norm);
     HIP_TRY(hipGetLastError());
     return reduce(out_slot);
@@ -1519,7 +1521,9 @@ struct Krylov {
     ProfScope ps(p, STIG_K_KRYLOV, (double)(nv + 2) * p->N * 8);
     if (nv <= 4) launch_update<4>(V, nv, coef, sign, w, dst, scale, with_dots);
     else if (nv <= 8) launch_update<8>(V, nv, coef, sign, w, dst, scale, with_dots);
+    else if (nv <= 12) launch_update<12>(V, nv, coef, sign, w, dst, scale, with_dots);
     else if (nv <= 16) launch_update<16>(V, nv, coef, sign, w, dst, scale, with_dots);
+    else if (nv <= 24) launch_update<24>(V, nv, coef, sign, w, dst, scale, with_dots);
     else launch_update<32>(V, nv, coef, sign, w, dst, scale, with_dots);
     HIP_TRY(hipGetLastError());
     return with_dots ? reduce(out_slot) : STIG_OK;
