@@ -98,8 +98,8 @@ stig_status stig_set_stream(stig_plan *plan, void *stream);
  * (its first restart cycle runs up to min(nrhs, 64) right-hand sides in
  * lockstep; with a smaller workspace it runs fewer at a time).  Layout, per
  * right-hand side, of the largest parts: the Krylov bases V (restart + 1
- * vectors), Z = A-hat^{-1} V and A Z (restart vectors each) and two more
- * vectors, all FP64 of N entries (Section 4.5: restarted GMRES); the two
+ * vectors), Z = A-hat^{-1} V and A Z (restart vectors each) and one more
+ * vector, all FP64 of N entries (Section 4.5: restarted GMRES); the two
  * intermediate tensors of the apply in the storage type of prec (Algorithm 1,
  * steps 2-4).  flexible does not change the size (GMRES and FGMRES keep the
  * same vectors).  The result depends on the plan's setup and options (diagonal
@@ -353,7 +353,9 @@ stig_status stig_lift_adjoint(stig_plan *plan, const double *a_col,
  * and form the update as u += Z y, which for a fixed preconditioner equals
  * P^{-1} (V y) and saves one apply per cycle.  A zero initial guess skips the
  * first product (r_0 = f).  Arnoldi with classical Gram-Schmidt and one
- * re-orthogonalisation, all in FP64 on the device; Givens rotations on the host.
+ * re-orthogonalisation delayed to the next step (one reduction and two passes
+ * over the basis per step), all in FP64 on the device; the small least-squares
+ * problem by Givens rotations on the host.
  * A cycle ends when the GMRES estimate reaches rtol, on a happy breakdown, when
  * maxit is spent, or after `restart` iterations.  In the first three cases the
  * residual r = f - A u is computed afresh (one FP64 product of A); if it is still

@@ -148,6 +148,108 @@ krylov_update(const double *__restrict__ V, int64_t ldv, int nv, const double *_
   block_reduce_store<NV>(acc, nv, 1, red, partial);
 }
 
+// ---- delayed re-orthogonalisation (classical Gram-Schmidt, second pass
+// lagged by one Arnoldi step): two passes over the basis per step.
+// Slots of the one-pass products: Q^T u at [0, KRY_MAXV), Q^T w at
+// [KRY_MAXV, 2 KRY_MAXV), then u.u, u.w, w.w.
+constexpr int KRY_D2 = 2 * KRY_MAXV + 3;
+
+// partial[slot * gridDim.x + block]: this block's shares of Q_i . u, Q_i . w
+// (i < nq, Q_i = Q + i * ldv), u . u, u . w and w . w, from one read of each
+// (NV = 0: no basis, the first step of a cycle).
+template <int NV>
+__global__ void __launch_bounds__(KRY_BLOCK)
+krylov_dots2(const double *__restrict__ Q, int64_t ldv, int nq, const double *__restrict__ u,
+             const double *__restrict__ w, int64_t N, double *__restrict__ partial) {
+  constexpr int A = 2 * NV + 3;
+  __shared__ double red[(KRY_BLOCK / 64) * A];
+  double acc[A];
+#pragma unroll
+  for (int i = 0; i < A; ++i) acc[i] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+    const double ue = u[e], we = w[e];
+    // branch-free: slots past nq re-read Q_0 (a cache hit) and are never stored
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double q = Q[(int64_t)(i < nq ? i : 0) * ldv + e];
+      acc[i] += q * ue;
+      acc[NV + i] += q * we;
+    }
+    acc[2 * NV] += ue * ue;
+    acc[2 * NV + 1] += ue * we;
+    acc[2 * NV + 2] += we * we;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < A; ++i) {
+    const bool active = i >= 2 * NV || (i < NV ? i : i - NV) < nq;
+    if (active) {
+      double v = acc[i];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) red[wave * A + i] = v;
+    }
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < A && (i >= 2 * NV || (i < NV ? i : i - NV) < nq)) {
+    double v = 0.0;
+    for (int wv = 0; wv < KRY_BLOCK / 64; ++wv) v += red[wv * A + i];
+    const int slot = i < NV ? i : (i < 2 * NV ? KRY_MAXV + (i - NV) : 2 * KRY_MAXV + (i - 2 * NV));
+    partial[(int64_t)slot * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// The second pass of a step, from one read of Q, u and w:
+//   v = (u - sum_i s_i Q_i) * rv                       (written over u)
+//   x = (w - a u - sum_i (t_i - a s_i) Q_i) * rx       (into x)
+// with s, t in device memory (the reduced one-pass products; s may be a later
+// re-orthogonalisation's); with_norm: shares of x . x in slot KRY_MAXV-1.
+// write_v = 0 leaves u untouched; x = nullptr computes the norm only.
+template <int NV>
+__global__ void __launch_bounds__(KRY_BLOCK)
+krylov_update2(const double *__restrict__ Q, int64_t ldv, int nq, const double *__restrict__ s,
+               const double *__restrict__ t, double *u, const double *__restrict__ w,
+               double *__restrict__ x, double a, double rv, double rx, int64_t N, int write_v,
+               int with_norm, double *__restrict__ partial) {
+  __shared__ double red[KRY_BLOCK / 64];
+  __shared__ double cs[NV > 0 ? NV : 1], ct[NV > 0 ? NV : 1];
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    cs[i] = i < nq ? s[i] : 0.0;
+    ct[i] = i < nq ? t[i] - a * s[i] : 0.0;
+  }
+  __syncthreads();
+  double nx = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+    const double ue = u[e], we = w[e];
+    double pv = 0.0, px = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double q = Q[(int64_t)(i < nq ? i : 0) * ldv + e];
+      pv += cs[i] * q;
+      px += ct[i] * q;
+    }
+    const double xv = (we - a * ue - px) * rx;
+    if (x) x[e] = xv;
+    if (write_v) u[e] = (ue - pv) * rv;
+    nx += xv * xv;
+  }
+  if (!with_norm) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) nx += __shfl_xor(nx, off, 64);
+  if (lane == 0) red[wave] = nx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int wv = 0; wv < KRY_BLOCK / 64; ++wv) v += red[wv];
+    partial[(int64_t)(KRY_MAXV - 1) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // r = f - Ax and this block's share of r . r in slot KRY_MAXV-1 of partial.
 __global__ void __launch_bounds__(KRY_BLOCK)
 residual_norm(const double *__restrict__ f, const double *__restrict__ Ax, double *__restrict__ r,

@@ -176,7 +176,7 @@ struct stig_plan {
   // Krylov bases.  The views are laid out by bind_workspace at each call.
   char *ws = nullptr;
   size_t ws_bytes = 0;
-  Span s0, s1, tscr, m0, m1, m2, m3, lift0, lift1, liftw, V, Z, AZ, w, tmp;
+  Span s0, s1, tscr, m0, m1, m2, m3, lift0, lift1, liftw, V, Z, AZ, tmp;
   // pinned host staging of the small Krylov transfers (setup): 4 coefficient
   // slots of KRY_MAXV doubles per right-hand side, then the breakdown flag
   double *pin = nullptr;
@@ -1363,7 +1363,7 @@ struct WsLayout {
   size_t m = 0;                           // one matvec / mass intermediate
   size_t lm = 0, lw = 0;                  // lifting: one spatial intermediate, weights
   size_t op = 0;                          // operator part
-  size_t v = 0, z = 0, vec = 0;           // Krylov: V, Z and AZ, one vector block (w, tmp)
+  size_t v = 0, z = 0, vec = 0;           // Krylov: V, Z and AZ, one vector block (tmp)
   size_t total = 0;
 };
 
@@ -1389,7 +1389,7 @@ WsLayout ws_layout(const stig_plan *p, int nrhs, stig_prec prec, int what, int n
     L.v = ws_round((size_t)(m + 1) * nb * p->N * sizeof(double));
     L.z = ws_round((size_t)m * nb * p->N * sizeof(double));
   }
-  L.total = L.op + L.v + 2 * L.z + 2 * L.vec;
+  L.total = L.op + L.v + 2 * L.z + L.vec;
   return L;
 }
 
@@ -1436,8 +1436,6 @@ void lay_views(stig_plan *p, const WsLayout &L, char *b, int what, int nb) {
   o += L.z;
   p->AZ.set(nb ? b : nullptr, o, L.z);
   o += L.z;
-  p->w.set(nb ? b : nullptr, o, L.vec);
-  o += L.vec;
   p->tmp.set(nb ? b : nullptr, o, L.vec);
 }
 
@@ -1527,6 +1525,54 @@ struct Krylov {
     else launch_update<32>(V, nv, coef, sign, w, dst, scale, with_dots);
     HIP_TRY(hipGetLastError());
     return with_dots ? reduce(out_slot) : STIG_OK;
+  }
+  // one pass of delayed re-orthogonalisation: Q^T u, Q^T w (nq basis vectors
+  // Q_i = Q + i ldv), u.u, u.w, w.w into slot regions 0, 1 and the first
+  // three entries of 2 (no synchronisation)
+  template <int NV>
+  void launch_dots2(const double *Q, int nq, const double *u, const double *w) {
+    hipLaunchKernelGGL(krylov_dots2<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, Q, ldv(),
+                       nq, u, w, p->N, partial());
+  }
+  stig_status dots2(const double *Q, int nq, const double *u, const double *w) {
+    if (nq > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
+    ProfScope ps(p, STIG_K_KRYLOV, (double)(nq + 2) * p->N * 8);
+    if (nq == 0) launch_dots2<0>(Q, nq, u, w);
+    else if (nq <= 4) launch_dots2<4>(Q, nq, u, w);
+    else if (nq <= 8) launch_dots2<8>(Q, nq, u, w);
+    else if (nq <= 12) launch_dots2<12>(Q, nq, u, w);
+    else if (nq <= 16) launch_dots2<16>(Q, nq, u, w);
+    else if (nq <= 24) launch_dots2<24>(Q, nq, u, w);
+    else launch_dots2<32>(Q, nq, u, w);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(reduce_partials, dim3(KRY_D2), dim3(KRY_BLOCK), 0, p->stream, partial(),
+                       KRY_GRID, slot(0));
+    HIP_TRY(hipGetLastError());
+    return STIG_OK;
+  }
+  // the second pass: v = (u - Q s) rv over u (write_v), x = (w - a u - Q (t - a s)) rx;
+  // with_norm: x.x into slot region 3, entry KRY_MAXV-1 (no synchronisation)
+  template <int NV>
+  void launch_update2(const double *Q, int nq, const double *sv, const double *tv, double *u,
+                      const double *w, double *x, double a, double rv, double rx, int write_v,
+                      int with_norm) {
+    hipLaunchKernelGGL(krylov_update2<NV>, dim3(KRY_GRID), dim3(KRY_BLOCK), 0, p->stream, Q, ldv(),
+                       nq, sv, tv, u, w, x, a, rv, rx, p->N, write_v, with_norm, partial());
+  }
+  stig_status update2(const double *Q, int nq, const double *sv, const double *tv, double *u,
+                      const double *w, double *x, double a, double rv, double rx, int write_v,
+                      int with_norm) {
+    if (nq > KRY_MAXV - 1) return fail(STIG_EINVAL, "too many basis vectors");
+    ProfScope ps(p, STIG_K_KRYLOV, (double)(nq + 3 + write_v) * p->N * 8);
+    if (nq == 0) launch_update2<0>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    else if (nq <= 4) launch_update2<4>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    else if (nq <= 8) launch_update2<8>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    else if (nq <= 12) launch_update2<12>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    else if (nq <= 16) launch_update2<16>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    else if (nq <= 24) launch_update2<24>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    else launch_update2<32>(Q, nq, sv, tv, u, w, x, a, rv, rx, write_v, with_norm);
+    HIP_TRY(hipGetLastError());
+    return with_norm ? reduce(3) : STIG_OK;
   }
   // host value of slot `k`'s entry i (synchronises)
   stig_status fetch(int k, int i, double *out) {
@@ -1658,10 +1704,107 @@ stig_status check_flag(stig_plan *p) {
   return STIG_OK;
 }
 
+// Host side of one right-hand side's Arnoldi process with delayed
+// re-orthogonalisation.  The Hessenberg matrix is kept un-rotated: column j is
+// provisional after step j (its subdiagonal entry is the norm of the once-
+// orthogonalised w_j) and final after step j + 1, which re-orthogonalises the
+// next basis vector and corrects the column; the least-squares problem is
+// re-solved by Givens rotations from scratch at every step (k <= 32).
+struct ArnoldiHost {
+  int m = 0;
+  double beta = 0.0;
+  std::vector<double> H;  // (m + 1) x m, row-major
+  double &h(int i, int j) { return H[(size_t)i * m + j]; }
+  void reset(int m_, double beta_) {
+    m = m_;
+    beta = beta_;
+    H.assign((size_t)(m + 1) * m, 0.0);
+  }
+  // min || beta e_0 - H_k y || over the first k columns: the residual norm, and
+  // y (host, k entries) when asked
+  double solve(int k, double *y) const {
+    std::vector<double> R((size_t)(k + 1) * k), g(k + 1, 0.0);
+    for (int i = 0; i <= k; ++i)
+      for (int c = 0; c < k; ++c) R[(size_t)i * k + c] = H[(size_t)i * m + c];
+    g[0] = beta;
+    for (int c = 0; c < k; ++c) {
+      const double a = R[(size_t)c * k + c], b = R[(size_t)(c + 1) * k + c];
+      const double rr = std::hypot(a, b);
+      const double cs = rr == 0.0 ? 1.0 : a / rr, sn = rr == 0.0 ? 0.0 : b / rr;
+      for (int q = c; q < k; ++q) {
+        const double x = R[(size_t)c * k + q], z = R[(size_t)(c + 1) * k + q];
+        R[(size_t)c * k + q] = cs * x + sn * z;
+        R[(size_t)(c + 1) * k + q] = -sn * x + cs * z;
+      }
+      const double g0 = g[c];
+      g[c] = cs * g0;
+      g[c + 1] = -sn * g0;
+    }
+    if (y)
+      for (int q = k - 1; q >= 0; --q) {
+        double acc = g[q];
+        for (int c = q + 1; c < k; ++c) acc -= R[(size_t)q * k + c] * y[c];
+        y[q] = acc / R[(size_t)q * k + q];
+      }
+    return std::fabs(g[k]);
+  }
+};
+
+// One Arnoldi step's host arithmetic after the one-pass products of
+// krylov_dots2: hs = [Q^T u (KRY_MAXV) | Q^T w (KRY_MAXV) | u.u, u.w, w.w].
+// Re-orthogonalising u_j = w'_{j-1} / nrm_prev against Q = [v_0 .. v_{j-1}]
+// (u_j = Q s + rho v_j) finalises column j - 1; w_j = A z_j is then split as
+// Q t + v_j h_jj + w'_j, the provisional column j.  s2 (optional) is the
+// product of an explicit re-orthogonalisation pass of u_j (then u.u is that
+// pass's norm and s the first pass's).
+// ||w'||^2 = w.w - ||t||^2 - h_jj^2 carries an absolute rounding error of a few
+// eps w.w: below this fraction of w.w the norm is taken from w' itself (one more
+// round trip); above it its relative error is below 1e-7, and the next step's
+// re-orthogonalisation absorbs any error of the scaling.
+constexpr double KRY_CANCEL = 1e-8;
+
+struct StepHost {
+  double rho = 1.0, hjj = 0.0, nrm2 = 0.0, ww = 0.0;
+};
+bool arnoldi_step(ArnoldiHost &ah, int j, const double *hs, const double *s2, double uu2,
+                  double nrm_prev, StepHost &out) {
+  const double *sv = hs, *tv = hs + KRY_MAXV;
+  const double uu = s2 ? uu2 : hs[2 * KRY_MAXV], uw = hs[2 * KRY_MAXV + 1];
+  const double ww = hs[2 * KRY_MAXV + 2];
+  double ss = 0.0, stt = 0.0, tt = 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double st = s2 ? sv[i] + s2[i] : sv[i];  // total component of u_j along v_i
+    const double sr = s2 ? s2[i] : sv[i];           // what remains to remove from u in memory
+    ss += sr * sr;
+    stt += st * tv[i];
+    tt += tv[i] * tv[i];
+  }
+  double rho = 1.0;
+  if (j > 0) {
+    const double rho2 = uu - ss;
+    rho = rho2 > 0.0 ? std::sqrt(rho2) : 0.0;
+    for (int i = 0; i < j; ++i) ah.h(i, j - 1) += nrm_prev * (s2 ? sv[i] + s2[i] : sv[i]);
+    ah.h(j, j - 1) = nrm_prev * rho;
+  }
+  out.rho = rho;
+  out.ww = ww;
+  if (rho == 0.0) return false;  // u_j in span(Q): the Krylov space is invariant
+  for (int i = 0; i < j; ++i) ah.h(i, j) = tv[i];
+  out.hjj = (uw - stt) / rho;
+  ah.h(j, j) = out.hjj;
+  out.nrm2 = ww - tt - out.hjj * out.hjj;
+  return true;
+}
+
 // One right-hand side: restarted (F)GMRES with right preconditioning.  Both
 // variants keep the preconditioned basis Z (m vectors): for a fixed linear
 // preconditioner u += Z y equals u += P^{-1} (V y), and it saves one
-// preconditioner apply per cycle; flexible GMRES needs Z anyway.
+// preconditioner apply per cycle; flexible GMRES needs Z anyway.  The Arnoldi
+// process is classical Gram-Schmidt with delayed re-orthogonalisation (the
+// second pass of step j is done at step j + 1, together with the first pass of
+// w_{j+1}): one reduction and two passes over the basis per step.  z_j is
+// P^{-1} u_j of the once-orthogonalised u_j; A z_j = w_j is expressed in the
+// final basis, so A Z = V H holds with the corrected columns.
 stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rtol, int maxit,
                       int flexible, int transpose, stig_prec prec, stig_info *info) {
   (void)flexible;
@@ -1670,11 +1813,10 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   STIG_TRY(p->V.ensure((size_t)(m + 1) * N * sizeof(double)));
   STIG_TRY(p->Z.ensure((size_t)m * N * sizeof(double)));
   STIG_TRY(p->AZ.ensure((size_t)m * N * sizeof(double)));
-  STIG_TRY(p->w.ensure(N * sizeof(double)));
   STIG_TRY(p->tmp.ensure(N * sizeof(double)));
   double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *AZ = p->AZ.as<double>(),
-         *w = p->w.as<double>(), *tmp = p->tmp.as<double>();
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+         *tmp = p->tmp.as<double>();
+  std::vector<double> y(m);
   double *hs = p->pin;
 
   double fnorm, unorm;
@@ -1703,88 +1845,90 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
   info->relres_true = beta / fnorm;
   info->relres_est = info->relres_true;
   int cycle = 0;
+  ArnoldiHost ah;
+  // pinned layout: [one-pass products (KRY_D2) | explicit pass region (KRY_MAXV)]
+  auto fetch_products = [&]() -> stig_status {
+    HIP_TRY(hipMemcpyAsync(hs, K.slot(0), KRY_D2 * sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipMemcpyAsync(pinned_flag(p), p->flag.p, sizeof(int), hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return flag_result(p, *pinned_flag(p));
+  };
+  double *hx = hs + 3 * KRY_MAXV;  // region 3 copy
   while (beta / fnorm > rtol && info->iters < maxit) {
     if (cycle++ > 0) info->restarts++;
-    STIG_TRY(K.axpby(r, nullptr, V, 1.0 / beta, 0.0));  // v_0 = r / beta
+    STIG_TRY(K.axpby(r, nullptr, V, 1.0 / beta, 0.0));  // u_0 = v_0 = r / beta
     r = V;
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    ah.reset(m, beta);
     int k = 0;
-    bool stop = false;  // estimate at rtol, breakdown or iteration budget spent
+    bool stop = false;       // estimate at rtol, breakdown or iteration budget spent
+    double nrm_prev = 1.0;   // u_j = w'_{j-1} / nrm_prev
     for (int j = 0; j < m; ++j) {
-      double *vj = V + (int64_t)j * N;
+      double *uj = V + (int64_t)j * N;
       double *zj = Z + (int64_t)j * N, *azj = AZ + (int64_t)j * N;
-      STIG_TRY(apply_dispatch(p, vj, zj, 1, transpose, prec));
-      STIG_TRY(run_matvec(p, zj, azj, 1, transpose));  // A z_j, kept for the cycle's residual
-      // classical Gram-Schmidt with one re-orthogonalisation.  The second
-      // correction w -= V h2 is deferred: with V orthonormal,
-      // ||w - V h2||^2 = ||w||^2 - ||h2||^2, and the corrected vector is only
-      // needed as the next basis vector, so the correction is fused with the
-      // scaling into v_{j+1} (and skipped when the cycle ends here).
-      STIG_TRY(K.dots(V, j + 1, azj, 0, 0));  // h1 = V^T A z_j
-      STIG_TRY(K.update(V, j + 1, K.slot(0), -1.0, azj, 1, 1, w));  // w = A z_j - V h1; h2 = V^T w; ||w||^2
-      // the two coefficient slots and the breakdown flag in one round trip
-      HIP_TRY(hipMemcpyAsync(hs, K.slot(0), 2 * KRY_MAXV * sizeof(double),
-                             hipMemcpyDeviceToHost, p->stream));
-      HIP_TRY(hipMemcpyAsync(pinned_flag(p), p->flag.p, sizeof(int), hipMemcpyDeviceToHost,
-                             p->stream));
-      HIP_TRY(hipStreamSynchronize(p->stream));
-      STIG_TRY(flag_result(p, *pinned_flag(p)));
+      STIG_TRY(apply_dispatch(p, uj, zj, 1, transpose, prec));
+      STIG_TRY(run_matvec(p, zj, azj, 1, transpose));  // w_j = A z_j, kept for the cycle's residual
+      STIG_TRY(K.dots2(V, j, uj, azj));
+      STIG_TRY(fetch_products());
       info->iters++;
-      const double wsq = hs[KRY_MAXV + KRY_MAXV - 1];
-      double h2sq = 0.0;
-      for (int i = 0; i <= j; ++i) h2sq += hs[KRY_MAXV + i] * hs[KRY_MAXV + i];
-      bool corrected = false;  // w already holds w - V h2
-      double hnext;
-      if (wsq - h2sq >= 0.25 * wsq) {
-        hnext = std::sqrt(wsq - h2sq);
+      // u_j far from orthogonal to Q (s.s > 3/4 u.u): one explicit pass
+      // u_j -= Q s with Q^T u_j and u_j . u_j (region 3) before v_j is formed
+      const double *s_dev = K.slot(0);
+      const double *s2 = nullptr;
+      double uu2 = 0.0;
+      if (j > 0) {
+        double ss = 0.0;
+        for (int i = 0; i < j; ++i) ss += hs[i] * hs[i];
+        if (!(hs[2 * KRY_MAXV] - ss > 0.25 * hs[2 * KRY_MAXV])) {
+          STIG_TRY(K.update(V, j, K.slot(0), -1.0, uj, 1, 3));
+          HIP_TRY(hipMemcpyAsync(hx, K.slot(3), KRY_MAXV * sizeof(double), hipMemcpyDeviceToHost,
+                                 p->stream));
+          HIP_TRY(hipStreamSynchronize(p->stream));
+          s2 = hx;
+          uu2 = hx[KRY_MAXV - 1];
+          s_dev = K.slot(3);
+        }
+      }
+      StepHost st;
+      const bool alive = arnoldi_step(ah, j, hs, s2, uu2, nrm_prev, st);
+      if (!alive) {  // u_j lies in the span of the basis: the solution is in it
+        k = j;
+        stop = true;
+        break;
+      }
+      if (!std::isfinite(st.hjj) || !std::isfinite(st.nrm2))
+        return fail(STIG_ENONFINITE, "non-finite value in the Arnoldi process");
+      const double a = st.hjj / st.rho;
+      double *unext = V + (int64_t)(j + 1) * N;
+      if (!(st.nrm2 > KRY_CANCEL * st.ww)) {
+        // w_j nearly in the span (the norm by Pythagoras would be lost to
+        // rounding): the norm of w'_j from w'_j itself (one more round trip;
+        // the vector is written below only if the cycle goes on)
+        STIG_TRY(K.update2(V, j, s_dev, K.slot(1), uj, azj, nullptr, a, 1.0 / st.rho, 1.0, 0, 1));
+        double xx;
+        STIG_TRY(K.fetch(3, KRY_MAXV - 1, &xx));
+        ah.h(j + 1, j) = std::sqrt(xx);
       } else {
-        // strong cancellation: apply the correction and take the norm explicitly
-        STIG_TRY(K.update(V, j + 1, K.slot(1), -1.0, w, 1, 2));  // w -= V h2; ||w||^2
-        STIG_TRY(K.fetch(2, KRY_MAXV - 1, &hnext));
-        hnext = std::sqrt(hnext);
-        corrected = true;
+        ah.h(j + 1, j) = std::sqrt(st.nrm2);
       }
+      nrm_prev = ah.h(j + 1, j);
+      k = j + 1;
       double colnorm = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        double h = hs[i] + hs[KRY_MAXV + i];
-        H[(size_t)i * m + j] = h;
-        colnorm += h * h;
-      }
-      H[(size_t)(j + 1) * m + j] = hnext;
+      for (int i = 0; i <= j; ++i) colnorm += ah.h(i, j) * ah.h(i, j);
+      const double hnext = ah.h(j + 1, j);
       if (!std::isfinite(hnext) || !std::isfinite(colnorm))
         return fail(STIG_ENONFINITE, "non-finite value in the Arnoldi process");
-      // apply previous rotations, then a new one that zeroes H[j+1][j]
-      for (int i = 0; i < j; ++i) {
-        double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-      }
-      double a = H[(size_t)j * m + j], b = hnext;
-      double rr = std::hypot(a, b);
-      cs[j] = rr == 0.0 ? 1.0 : a / rr;
-      sn[j] = rr == 0.0 ? 0.0 : b / rr;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
-      info->relres_est = std::fabs(g[j + 1]) / fnorm;
-      bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
+      info->relres_est = ah.solve(k, nullptr) / fnorm;
+      const bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
       stop = info->relres_est <= rtol || breakdown || info->iters >= maxit;
-      if (stop) break;
-      if (j + 1 < m) {
-        double *vn = V + (int64_t)(j + 1) * N;
-        if (corrected) STIG_TRY(K.axpby(w, nullptr, vn, 1.0 / hnext, 0.0));
-        else STIG_TRY(K.update(V, j + 1, K.slot(1), -1.0, w, 0, 0, vn, 1.0 / hnext));
-      }
+      if (stop || j + 1 == m) break;
+      // the step's second pass: v_j over u_j, u_{j+1} = w'_j / nrm
+      STIG_TRY(K.update2(V, j, s_dev, K.slot(1), uj, azj, unext, a, 1.0 / st.rho,
+                         1.0 / nrm_prev, j > 0, 0));
     }
-    // y = R^{-1} g
-    for (int i = k - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
-      y[i] = s / H[(size_t)i * m + i];
-    }
+    if (k == 0) break;  // nothing to add (cannot happen with beta > 0)
+    ah.solve(k, y.data());
     // y and y / beta to the device (the pinned area is not written again
     // before the next synchronisation)
     for (int i = 0; i < k; ++i) {
@@ -1821,12 +1965,14 @@ stig_status gmres_one(stig_plan *p, const double *f, double *u, int m, double rt
 
 // First restart cycle of (F)GMRES for nb right-hand sides in lockstep: step j
 // applies the preconditioner and A to the j-th basis vectors of all of them in
-// one batched call (basis vectors stored [j][rhs][N]), runs each one's Gram-
-// Schmidt kernels, and synchronises once for all.  A right-hand side whose
-// estimate reaches rtol (or that breaks down) freezes; its later basis slots
-// are zeroed so the batched calls stay finite.  At the end every solution is
-// updated and its true residual computed; done[r] tells which reached rtol.
-// The iteration is the same as gmres_one's first cycle for each right-hand side.
+// one batched call (basis vectors stored [j][rhs][N]), runs each one's
+// Gram-Schmidt passes (delayed re-orthogonalisation, as gmres_one), and
+// synchronises once for all.  A right-hand side whose estimate reaches rtol
+// (or that breaks down) freezes; its later basis slots are zeroed so the
+// batched calls stay finite.  At the end every solution is updated and its
+// fresh residual computed (one batched product); done[r] tells which reached
+// rtol.  The iteration is the same as gmres_one's first cycle for each
+// right-hand side.
 stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m, double rtol,
                         int maxit, int transpose, stig_prec prec, stig_info *infos, bool *done) {
   const int64_t N = p->N, ld = (int64_t)nb * N;
@@ -1834,13 +1980,12 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   STIG_TRY(p->V.ensure((size_t)(m + 1) * ld * sizeof(double)));
   STIG_TRY(p->Z.ensure((size_t)m * ld * sizeof(double)));
   STIG_TRY(p->AZ.ensure((size_t)m * ld * sizeof(double)));
-  STIG_TRY(p->w.ensure((size_t)ld * sizeof(double)));
   STIG_TRY(p->tmp.ensure((size_t)ld * sizeof(double)));
   if (nb > KRY_MAXB || p->small.bytes < (size_t)nb * S4 * sizeof(double) ||
       p->pin_n < (size_t)nb * S4 + 1)
     return fail(STIG_EINVAL, "too many right-hand sides in one lockstep cycle");
   double *V = p->V.as<double>(), *Z = p->Z.as<double>(), *AZ = p->AZ.as<double>(),
-         *w = p->w.as<double>(), *tmp = p->tmp.as<double>(), *hs = p->pin;
+         *tmp = p->tmp.as<double>(), *hs = p->pin;
   std::vector<Krylov> K;
   for (int r = 0; r < nb; ++r) K.push_back(Krylov{p, ld, (int64_t)r * S4});
   auto fetch_all = [&](bool with_flag) -> stig_status {
@@ -1855,7 +2000,7 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   // ||f||, ||u|| of every right-hand side in one round trip
   for (int r = 0; r < nb; ++r) STIG_TRY(K[r].norms_async(f + r * N, u + r * N));
   STIG_TRY(fetch_all(false));
-  std::vector<double> fnorm(nb), unorm(nb), beta(nb, 0.0);
+  std::vector<double> fnorm(nb), unorm(nb), beta(nb, 0.0), nrm_prev(nb, 1.0);
   for (int r = 0; r < nb; ++r) {
     fnorm[r] = std::sqrt(hs[r * S4 + 3 * KRY_MAXV]);
     unorm[r] = std::sqrt(hs[r * S4 + 3 * KRY_MAXV + KRY_MAXV - 1]);
@@ -1864,7 +2009,7 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   }
   std::vector<char> active(nb, 0);
   std::vector<int> kk(nb, 0);
-  std::vector<std::vector<double>> H(nb), cs(nb), sn(nb), g(nb);
+  std::vector<ArnoldiHost> ah(nb);
   for (int r = 0; r < nb; ++r) {
     infos[r] = stig_info{0, 0, 0.0, 0.0, 0.0};
     done[r] = false;
@@ -1891,11 +2036,7 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
     }
     infos[r].relres_true = infos[r].relres_est = beta[r] / fnorm[r];
     active[r] = 1;
-    H[r].assign((size_t)(m + 1) * m, 0.0);
-    cs[r].assign(m, 0.0);
-    sn[r].assign(m, 0.0);
-    g[r].assign(m + 1, 0.0);
-    g[r][0] = beta[r];
+    ah[r].reset(m, beta[r]);
   }
   auto any_active = [&]() {
     for (int r = 0; r < nb; ++r)
@@ -1905,62 +2046,66 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
   for (int j = 0; j < m && any_active(); ++j) {
     STIG_TRY(apply_dispatch(p, V + j * ld, Z + j * ld, nb, transpose, prec));
     STIG_TRY(run_matvec(p, Z + j * ld, AZ + j * ld, nb, transpose));
-    for (int r = 0; r < nb; ++r) {
-      if (!active[r]) continue;
-      double *az = AZ + j * ld + r * N;
-      STIG_TRY(K[r].dots(V + r * N, j + 1, az, 0, 0));
-      STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(0), -1.0, az, 1, 1, w + r * N));
-    }
+    for (int r = 0; r < nb; ++r)
+      if (active[r]) STIG_TRY(K[r].dots2(V + r * N, j, V + j * ld + r * N, AZ + j * ld + r * N));
     STIG_TRY(fetch_all(true));
     for (int r = 0; r < nb; ++r) {
       if (!active[r]) continue;
       const double *h = hs + r * S4;
-      std::vector<double> &Hr = H[r];
+      double *uj = V + j * ld + r * N, *azj = AZ + j * ld + r * N;
+      double *unext = V + (j + 1) * ld + r * N;
       infos[r].iters++;
-      const double wsq = h[KRY_MAXV + KRY_MAXV - 1];
-      double h2sq = 0.0;
-      for (int i = 0; i <= j; ++i) h2sq += h[KRY_MAXV + i] * h[KRY_MAXV + i];
-      bool corrected = false;
-      double hnext;
-      if (wsq - h2sq >= 0.25 * wsq) {
-        hnext = std::sqrt(wsq - h2sq);
+      const double *s_dev = K[r].slot(0);
+      const double *s2 = nullptr;
+      double uu2 = 0.0;
+      std::vector<double> s2h;
+      if (j > 0) {
+        double ss = 0.0;
+        for (int i = 0; i < j; ++i) ss += h[i] * h[i];
+        if (!(h[2 * KRY_MAXV] - ss > 0.25 * h[2 * KRY_MAXV])) {
+          STIG_TRY(K[r].update(V + r * N, j, K[r].slot(0), -1.0, uj, 1, 3));
+          s2h.resize(KRY_MAXV);
+          HIP_TRY(hipMemcpyAsync(s2h.data(), K[r].slot(3), KRY_MAXV * sizeof(double),
+                                 hipMemcpyDeviceToHost, p->stream));
+          HIP_TRY(hipStreamSynchronize(p->stream));
+          s2 = s2h.data();
+          uu2 = s2h[KRY_MAXV - 1];
+          s_dev = K[r].slot(3);
+        }
+      }
+      StepHost st;
+      if (!arnoldi_step(ah[r], j, h, s2, uu2, nrm_prev[r], st)) {
+        kk[r] = j;
+        active[r] = 0;
+        continue;
+      }
+      if (!std::isfinite(st.hjj) || !std::isfinite(st.nrm2))
+        return fail(STIG_ENONFINITE, "non-finite value in the Arnoldi process");
+      const double a = st.hjj / st.rho;
+      if (!(st.nrm2 > KRY_CANCEL * st.ww)) {
+        STIG_TRY(K[r].update2(V + r * N, j, s_dev, K[r].slot(1), uj, azj, nullptr, a,
+                              1.0 / st.rho, 1.0, 0, 1));
+        double xx;
+        STIG_TRY(K[r].fetch(3, KRY_MAXV - 1, &xx));
+        ah[r].h(j + 1, j) = std::sqrt(xx);
       } else {
-        STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(1), -1.0, w + r * N, 1, 2));
-        STIG_TRY(K[r].fetch(2, KRY_MAXV - 1, &hnext));
-        hnext = std::sqrt(hnext);
-        corrected = true;
+        ah[r].h(j + 1, j) = std::sqrt(st.nrm2);
       }
+      nrm_prev[r] = ah[r].h(j + 1, j);
+      kk[r] = j + 1;
       double colnorm = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        const double hv = h[i] + h[KRY_MAXV + i];
-        Hr[(size_t)i * m + j] = hv;
-        colnorm += hv * hv;
-      }
+      for (int i = 0; i <= j; ++i) colnorm += ah[r].h(i, j) * ah[r].h(i, j);
+      const double hnext = ah[r].h(j + 1, j);
       if (!std::isfinite(hnext) || !std::isfinite(colnorm))
         return fail(STIG_ENONFINITE, "non-finite value in the Arnoldi process");
-      for (int i = 0; i < j; ++i) {
-        const double a = Hr[(size_t)i * m + j], b = Hr[(size_t)(i + 1) * m + j];
-        Hr[(size_t)i * m + j] = cs[r][i] * a + sn[r][i] * b;
-        Hr[(size_t)(i + 1) * m + j] = -sn[r][i] * a + cs[r][i] * b;
-      }
-      const double a = Hr[(size_t)j * m + j], b = hnext;
-      const double rr = std::hypot(a, b);
-      cs[r][j] = rr == 0.0 ? 1.0 : a / rr;
-      sn[r][j] = rr == 0.0 ? 0.0 : b / rr;
-      Hr[(size_t)j * m + j] = rr;
-      g[r][j + 1] = -sn[r][j] * g[r][j];
-      g[r][j] = cs[r][j] * g[r][j];
-      kk[r] = j + 1;
-      infos[r].relres_est = std::fabs(g[r][j + 1]) / fnorm[r];
+      infos[r].relres_est = ah[r].solve(kk[r], nullptr) / fnorm[r];
       const bool breakdown = hnext <= 1e-14 * std::sqrt(colnorm + hnext * hnext);
       if (infos[r].relres_est <= rtol || breakdown || infos[r].iters >= maxit || j + 1 == m) {
         active[r] = 0;
         continue;
       }
-      double *vn = V + (j + 1) * ld + r * N;
-      if (corrected) STIG_TRY(K[r].axpby(w + r * N, nullptr, vn, 1.0 / hnext, 0.0));
-      else STIG_TRY(K[r].update(V + r * N, j + 1, K[r].slot(1), -1.0, w + r * N, 0, 0, vn,
-                                1.0 / hnext));
+      STIG_TRY(K[r].update2(V + r * N, j, s_dev, K[r].slot(1), uj, azj, unext, a, 1.0 / st.rho,
+                            1.0 / nrm_prev[r], j > 0, 0));
     }
     // frozen right-hand sides: zero basis vector for the next batched step
     if (j + 1 < m)
@@ -1968,30 +2113,18 @@ stig_status gmres_batch(stig_plan *p, const double *f, double *u, int nb, int m,
         if (!active[r])
           HIP_TRY(hipMemsetAsync(V + (j + 1) * ld + r * N, 0, N * sizeof(double), p->stream));
   }
-  // solutions and their true residuals (one batched product, one round trip)
+  // solutions, then their fresh residuals (one batched product, one round trip)
   for (int r = 0; r < nb; ++r) {
     if (kk[r] == 0) continue;
     std::vector<double> y(kk[r]);
-    for (int i = kk[r] - 1; i >= 0; --i) {
-      double sacc = g[r][i];
-      for (int c = i + 1; c < kk[r]; ++c) sacc -= H[r][(size_t)i * m + c] * y[c];
-      y[i] = sacc / H[r][(size_t)i * m + i];
-    }
-    // y and y / beta (staging not written again before the next round trip)
-    double *stage = hs + r * S4 + 2 * KRY_MAXV;
-    for (int i = 0; i < kk[r]; ++i) {
-      stage[i] = y[i];
-      stage[KRY_MAXV + i] = y[i] / beta[r];
-    }
+    ah[r].solve(kk[r], y.data());
+    double *stage = hs + r * S4 + 2 * KRY_MAXV;  // not written again before the next round trip
+    for (int i = 0; i < kk[r]; ++i) stage[i] = y[i];
     HIP_TRY(hipMemcpyAsync(K[r].slot(3), stage, kk[r] * sizeof(double), hipMemcpyHostToDevice,
                            p->stream));
-    HIP_TRY(hipMemcpyAsync(K[r].slot(2), stage + KRY_MAXV, kk[r] * sizeof(double),
-                           hipMemcpyHostToDevice, p->stream));
     if (unorm[r] == 0.0) STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, nullptr, 0, 0, u + r * N));
     else STIG_TRY(K[r].update(Z + r * N, kk[r], K[r].slot(3), 1.0, u + r * N, 0, 0));
   }
-  // fresh residuals r = f - A u of the whole batch: one batched product, then
-  // per right-hand side the difference and its norm (over v_0), one round trip
   STIG_TRY(run_matvec(p, u, tmp, nb, transpose));
   for (int r = 0; r < nb; ++r)
     if (kk[r] > 0) STIG_TRY(K[r].residual_async(f + r * N, tmp + r * N, V + r * N));
@@ -2247,7 +2380,7 @@ stig_status stig_setup_1d_pencils(stig_plan *p, const double *const *K1d, const 
   STIG_TRY(upload(p->tnM, nm, s));
   STIG_TRY(p->flag.ensure(sizeof(int)));
   HIP_TRY(hipMemsetAsync(p->flag.p, 0, sizeof(int), s));
-  STIG_TRY(p->partial.ensure((size_t)KRY_MAXV * KRY_GRID * sizeof(double)));
+  STIG_TRY(p->partial.ensure((size_t)KRY_D2 * KRY_GRID * sizeof(double)));
   STIG_TRY(p->small.ensure((size_t)KRY_MAXB * 4 * KRY_MAXV * sizeof(double)));
   STIG_TRY(ensure_pinned(p, (size_t)KRY_MAXB * 4 * KRY_MAXV + 1));
   HIP_TRY(hipStreamSynchronize(s));

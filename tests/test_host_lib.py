@@ -192,8 +192,8 @@ def _round256(b):
 def test_workspace_bytes_cover_each_calls_tensors():
     """stig_workspace_bytes on the 64-element cube (65^3 x 66 unknowns): the FP64 apply keeps
     two intermediates with x/y planes padded to 128 bytes (65^2 = 4225 -> 4240 entries), the
-    FP32 / BF16 ones to 4256 / 4288; GMRES(m) adds V (m+1 vectors), Z and A Z (m each) and two
-    more vectors of N doubles per right-hand side.  Sizes computed here from the tensor shapes."""
+    FP32 / BF16 ones to 4256 / 4288; GMRES(m) adds V (m+1 vectors), Z and A Z (m each) and one
+    more vector of N doubles per right-hand side.  Sizes computed here from the tensor shapes."""
     L = _lib()
     lib = L.lib()
     h = C.c_void_p()
@@ -208,7 +208,7 @@ def test_workspace_bytes_cover_each_calls_tensors():
             op = max(apply_b, 2 * vec)  # matvec (fused stencil: a, b) and mass (two buffers)
             assert ws(0, prec, 1) == op, prec
             for m in (1, 30):
-                gm = _round256((m + 1) * N * 8) + 2 * _round256(m * N * 8) + 2 * vec
+                gm = _round256((m + 1) * N * 8) + 2 * _round256(m * N * 8) + vec
                 assert ws(m, prec, 1) == op + gm
         # batches: every part scales with the right-hand sides
         assert ws(0, 0, 3) == max(2 * _round256(3 * 65 * 4240 * 66 * 8), 2 * _round256(3 * N * 8))
