@@ -226,20 +226,20 @@ time_arrow_solve(const Tio *__restrict__ in, Tio *__restrict__ out,
 // H = gamma B + nu lam_k I block diagonal with closed-form 2 x 2 inverses.
 // tab: d of each mode's block (at both positions of the block), g[n], h[n]
 // (arrow column / row), sigma, i.e. [d | g | h | sigma].
-// L lanes per system: lanes c % 16 + 16 l (l < L) of a wave share column c
-// and take every L-th block; the two sums are reduced across them.  Two passes
-// over the modes (the second re-reads x, from L2), so nothing is held per mode.
+// L lanes per system: a wave covers CW = 64 / L consecutive columns, lane
+// c + CW l (l < L) takes column c and every L-th block, and the two sums are
+// reduced across the L lanes of a column.  Two passes over the modes (the
+// second re-reads x, from L2), so nothing is held per mode.
 template <typename TC, int L>
 __global__ void __launch_bounds__(256)
 time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *__restrict__ tab,
                   TC gamma, TC nu, int n, int nz, int64_t ns, int64_t cols) {
-  static_assert(L == 1 || L == 2 || L == 4, "lanes per system");
-  const int lane = threadIdx.x & 63, sub = lane >> 4;
+  static_assert(L == 1 || L == 2 || L == 4 || L == 8 || L == 16, "lanes per system");
+  constexpr int CW = 64 / L;
+  const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  // a wave covers 64 / L columns: 16 per group of 16 lanes, groups l >= L take
-  // the next 16 columns
-  const int grp = sub % L, cset = sub / L;
-  const int64_t c = wave * (64 / L) + cset * 16 + (lane & 15);
+  const int grp = lane / CW;
+  const int64_t c = wave * CW + (lane % CW);
   const bool valid = c < cols;
   const int64_t cc = valid ? c : 0;
   const int64_t rhs = cc / ns, k = cc - rhs * ns;
@@ -248,8 +248,8 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   const int nb = (n - 1 - nz) / 2;  // 2 x 2 blocks
   const TC *dd = tab, *gv = tab + n, *hv = tab + 2 * n;
   auto lsum = [](TC v) {
-    if (L >= 2) v += __shfl_xor(v, 16, 64);
-    if (L >= 4) v += __shfl_xor(v, 32, 64);
+#pragma unroll
+    for (int off = CW; off < 64; off *= 2) v += __shfl_xor(v, off, 64);
     return v;
   };
   // pass 1: sums h^T H^{-1} g and h^T H^{-1} x (unrolled: the loads of several

@@ -281,7 +281,8 @@ __global__ void mode_gemm(const Tin *__restrict__ in, Tout *__restrict__ out,
 //    multiplies it by the n/16 full 16-row tiles of Op (A operand from LDS),
 //  * and computes the n % 16 fringe rows on the vector ALU from the same B
 //    registers, reduced across the four k-slices with cross-lane shuffles.
-// Latency is hidden by occupancy (many independent waves per SIMD).
+// Latency is hidden by occupancy (many independent waves per SIMD) and by the
+// next strip's loads, issued under the current strip's products.
 // Dynamic LDS: 16 * ceil(n/16) * ld elements.
 constexpr int GEMM2_MAX_N = 79;
 constexpr int GEMM2_THREADS = 256;
@@ -292,16 +293,15 @@ constexpr int GEMM2_THREADS = 256;
 // SC: 1 = in_scale, 2 = out_scale (length nscale, index taken modulo nscale):
 // per-entry factors multiplied in on load (1) or on store (2); a column's
 // entries lie in one period of nscale, so the modulo is taken once per column.
-// The scaled forms load each strip just before multiplying it (no prefetch
-// of the next strip: the factors take those registers).  Separate
-// instantiations keep each one's registers to its own path.  SC 0: both null.
+// Separate instantiations keep each one's registers to its own path.  SC 0:
+// both null.
 // RS > 1: the full 16-row tiles are split into RS parts, one per block of a
 // group of RS consecutive blocks (numbered so that a group shares an XCD), and
 // each block holds only its part of Op (plus the fringe rows, computed by the
 // last part) in LDS: smaller blocks, more of them per CU, shorter MFMA chains.
 // The grid is then a multiple of RS.
 template <typename Tin, typename Tout, typename TC, int NC, int SC, int RS = 1>
-__global__ void __launch_bounds__(GEMM2_THREADS)
+__global__ void __launch_bounds__(GEMM2_THREADS, 2)
 mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
                 const typename Mfma<TC>::elem *__restrict__ Op, int n_arg, int64_t inner,
                 int64_t total_cols, const double *__restrict__ in_scale,
@@ -333,9 +333,86 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   const int ld = lds_ld<TC>(NMAX);
   E *opl = reinterpret_cast<E *>(smem);  // [NROWS][ld]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // FU loads in flight per thread: when a block multiplies only a few strips,
-  // this copy would otherwise be a chain of dependent L2 round trips
-  constexpr int FILL = NROWS * KPADM, FU = 8;
+  const int64_t nstrips = (total_cols + 15) >> 4;
+  const int64_t slab = (int64_t)n * inner;
+  const uint32_t uinner = (uint32_t)inner;
+  const int col = lane & 15, kg = lane >> 4;
+  const int64_t wstride = nsblk * (GEMM2_THREADS / 64);
+  // column c -> (base address, stride along the contracted axis)
+  auto locate = [&](int64_t c, int64_t &base, int64_t &step) {
+    if (inner == 1) {
+      base = c * n;
+      step = 1;
+    } else {
+      uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
+      base = (int64_t)o * slab + i;
+      step = inner;
+    }
+  };
+  struct Col {
+    int64_t base, step, sb;  // first entry, stride along k, offset in the factors
+    bool valid;
+  };
+  auto column = [&](int64_t strip) {
+    const int64_t c = strip * 16 + col;
+    Col r;
+    r.valid = strip < nstrips && c < total_cols;
+    locate(r.valid ? c : 0, r.base, r.step);
+    r.sb = SC != 0 ? r.base % nscale : 0;
+    return r;
+  };
+  // The B operand of one strip stays in registers as raw input values (and, SC
+  // 1, input factors), one slot per k step.  ROLL: slot s takes the next
+  // strip's k step s as soon as the MFMAs of step s have read it, so the next
+  // strip's loads run under this strip's products with one set of registers (a
+  // second full set, double buffering, halves the waves per SIMD at n = 130,
+  // 131).  The runtime-n form (fringe rows accumulated after the products)
+  // loads each strip after the previous one's stores and converts it to
+  // operands at once, and so do the BF16 forms with a wider input type (their
+  // raw values take 2-4 times the operand registers) and the scaled forms whose
+  // input is wider than the accumulator or whose operands are BF16 (rolled,
+  // they spill).
+  constexpr bool ROLL =
+      NC != 0 && (SC == 0 ? (MF::KPL == 1 || sizeof(Tin) == sizeof(E))
+                          : (MF::KPL == 1 && sizeof(Tin) <= sizeof(typename MF::acc_elem)));
+  constexpr bool SCI = SC == 1;
+  Tin raw[KSMAX][MF::KPL];
+  double rsc[SCI ? KSMAX : 1][MF::KPL];
+  E bv[ROLL ? 1 : KSMAX][MF::KPL];  // !ROLL: the strip's operands
+  auto prepare = [&]() {
+    if constexpr (!ROLL) {
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s)
+#pragma unroll
+        for (int u = 0; u < MF::KPL; ++u) {
+          const int k = s * MF::KSTEP + kg * MF::KPL + u;
+          double x = Conv<Tin>::to_f64(raw[s][u]);
+          if constexpr (SCI) x *= rsc[s][u];
+          bv[s][u] = k < n ? MF::from_f64(x) : MF::zero();
+        }
+    }
+  };
+  auto issue = [&](const Col &L, int s) {
+#pragma unroll
+    for (int u = 0; u < MF::KPL; ++u) {
+      const int k = s * MF::KSTEP + kg * MF::KPL + u;
+      const int64_t off = k < n ? (int64_t)k * L.step : 0;  // padding: a valid address
+      raw[s][u] = in[L.base + off];
+      if constexpr (SCI) rsc[s][u] = in_scale[L.sb + off];
+    }
+  };
+  int64_t strip = sblk * (GEMM2_THREADS / 64) + wave;
+  Col cur = column(strip);
+  // ROLL, unscaled: the first strip's loads go out before the operator copy,
+  // so the two overlap (the scaled forms have no registers to spare there)
+  if constexpr (ROLL && SC == 0) {
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) issue(cur, s);
+  }
+  // operator copy: all of a thread's loads in flight at once (one round trip
+  // for the block's share at n = 130, 131 in FP64)
+  constexpr int FILL = NROWS * KPADM;
+  constexpr int FU0 = (FILL + GEMM2_THREADS - 1) / GEMM2_THREADS, FU = FU0 < 24 ? FU0 : 24;
   for (int e0 = tid; e0 < FILL; e0 += GEMM2_THREADS * FU) {
     E v[FU];
 #pragma unroll
@@ -355,185 +432,158 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     }
   }
   __syncthreads();
+  if constexpr (ROLL && SC != 0) {
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) issue(cur, s);
+  }
 
-  const int64_t nstrips = (total_cols + 15) >> 4;
-  const int64_t slab = (int64_t)n * inner;
-  const uint32_t uinner = (uint32_t)inner;
-  const int col = lane & 15, kg = lane >> 4;
-  const int64_t wstride = nsblk * (GEMM2_THREADS / 64);
-  // column c -> (base address, stride along the contracted axis)
-  auto locate = [&](int64_t c, int64_t &base, int64_t &step) {
-    if (inner == 1) {
-      base = c * n;
-      step = 1;
-    } else {
-      uint32_t o = (uint32_t)c / uinner, i = (uint32_t)c - o * uinner;
-      base = (int64_t)o * slab + i;
-      step = inner;
+  constexpr int NFR = NMAX - 16 * QALL;  // fringe rows (vector ALU, last part)
+  auto operand = [&](int s, E (&be)[MF::KPL]) {
+#pragma unroll
+    for (int u = 0; u < MF::KPL; ++u) {
+      if constexpr (ROLL) {
+        const int k = s * MF::KSTEP + kg * MF::KPL + u;
+        double x = Conv<Tin>::to_f64(raw[s][u]);
+        if constexpr (SCI) x *= rsc[s][u];
+        be[u] = k < n ? MF::from_f64(x) : MF::zero();
+      } else {
+        be[u] = bv[s][u];
+      }
     }
   };
-  // B operand of one strip for all k steps (branch-free loads)
-  auto load_b = [&](int64_t strip, E (&bv)[KSMAX][MF::KPL]) {
-    const int64_t c = strip * 16 + col;
-    const bool cvalid = strip < nstrips && c < total_cols;
-    int64_t base, step;
-    locate(cvalid ? c : 0, base, step);
-    if (SC != 1) {
+  // One strip: full row tiles on MFMA (the Op fragments of k step s+1 are read
+  // from LDS while the MFMAs of step s run), the fringe rows on the vector ALU
+  // from the same operand values (every part computes them, the last stores
+  // them: no branches in the loop), then the stores.
+  auto process = [&](const Col &c, const Col &nx) {
+    // output factors (SC 2): all of the lane's in flight at once; ROLL: before
+    // the next strip's loads, so that the stores wait only for them
+    double osc[SC == 2 ? QMAX : 1][4], osf[NFR > 0 ? NFR : 1];
+    auto load_out_factors = [&]() {
+      if constexpr (SC == 2) {
 #pragma unroll
-      for (int s = 0; s < KSMAX; ++s)
+        for (int t = 0; t < QMAX; ++t)
 #pragma unroll
-        for (int u = 0; u < MF::KPL; ++u) {
-          int k = s * MF::KSTEP + kg * MF::KPL + u;
-          bool ok = cvalid && k < n;
-          int64_t a = ok ? base + (int64_t)k * step : 0;
-          double x = Conv<Tin>::to_f64(in[a]);
-          bv[s][u] = ok ? MF::from_f64(x) : MF::zero();
+          for (int v = 0; v < 4; ++v) {
+            const int j = row0 + 16 * t + MF::out_row(kg, v);
+            osc[t][v] = out_scale[c.sb + (j < n ? (int64_t)j * c.step : 0)];
+          }
+#pragma unroll
+        for (int q = 0; q < NFR; ++q) {
+          const int j = 16 * QALL + q;
+          osf[q] = out_scale[c.sb + (j < n ? (int64_t)j * c.step : 0)];
         }
-      return;
-    }
-    // scaled: every load of the strip (values, then factors) is issued before
-    // the first product, so the two sets of loads overlap
-    const int64_t sb = base % nscale;
-    Tin xr[KSMAX][MF::KPL];
-    double sc[KSMAX][MF::KPL];
-#pragma unroll
-    for (int s = 0; s < KSMAX; ++s)
-#pragma unroll
-      for (int u = 0; u < MF::KPL; ++u) {
-        int k = s * MF::KSTEP + kg * MF::KPL + u;
-        bool ok = cvalid && k < n;
-        xr[s][u] = in[ok ? base + (int64_t)k * step : 0];
       }
-#pragma unroll
-    for (int s = 0; s < KSMAX; ++s)
-#pragma unroll
-      for (int u = 0; u < MF::KPL; ++u) {
-        int k = s * MF::KSTEP + kg * MF::KPL + u;
-        bool ok = cvalid && k < n;
-        sc[s][u] = in_scale[ok ? sb + (int64_t)k * step : 0];
-      }
-#pragma unroll
-    for (int s = 0; s < KSMAX; ++s)
-#pragma unroll
-      for (int u = 0; u < MF::KPL; ++u) {
-        int k = s * MF::KSTEP + kg * MF::KPL + u;
-        bool ok = cvalid && k < n;
-        bv[s][u] = ok ? MF::from_f64(Conv<Tin>::to_f64(xr[s][u]) * sc[s][u]) : MF::zero();
-      }
-  };
-  // Process one strip whose B operand is already in registers: full row tiles
-  // on MFMA (the Op fragments of k step s+1 are read from LDS while the MFMAs of
-  // step s run), then the fringe rows on the vector ALU, then the stores.
-  auto process = [&](int64_t strip, const E (&bv)[KSMAX][MF::KPL]) {
-    const int64_t c = strip * 16 + col;
-    const bool cvalid = c < total_cols;
-    int64_t base, step;
-    locate(cvalid ? c : 0, base, step);
-    const int64_t sb = SC == 2 ? base % nscale : 0;
+    };
+    if constexpr (ROLL) load_out_factors();
     typename MF::acc acc[QMAX];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
       for (int v = 0; v < 4; ++v) acc[t][v] = 0;
     const E *abase = opl + (size_t)col * ld + kg * MF::KPL;
+    const E *fbase = opl + (size_t)16 * QMAX * ld + kg * MF::KPL;  // fringe rows
     typename MF::frag acur[QMAX], anext[QMAX];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t) anext[t] = MF::load(abase + (size_t)16 * t * ld);
+    double fr[NFR > 0 ? NFR : 1] = {};
 #pragma unroll
     for (int s = 0; s < KSMAX; ++s) {
 #pragma unroll
       for (int t = 0; t < QMAX; ++t) acur[t] = anext[t];
+      // this step's fringe-row values, then the next step's A fragments:
+      // issued ahead of this step's MFMAs (the fence keeps them there), so
+      // both reads have those MFMAs to arrive
+      E fo[ROLL && NFR > 0 ? NFR : 1][MF::KPL];
+      if constexpr (ROLL) {
+#pragma unroll
+        for (int q = 0; q < NFR; ++q)
+#pragma unroll
+          for (int u = 0; u < MF::KPL; ++u) fo[q][u] = fbase[(size_t)q * ld + s * MF::KSTEP + u];
+      }
       if (s + 1 < KSMAX) {
 #pragma unroll
         for (int t = 0; t < QMAX; ++t)
           anext[t] = MF::load(abase + (size_t)16 * t * ld + (s + 1) * MF::KSTEP);
       }
-      typename MF::frag b = MF::make(bv[s]);
+      __builtin_amdgcn_sched_barrier(0);
+      E be[MF::KPL];
+      operand(s, be);
+      typename MF::frag b = MF::make(be);
 #pragma unroll
       for (int t = 0; t < QMAX; ++t) acc[t] = MF::mma(acur[t], b, acc[t]);
+      if constexpr (ROLL) {
+        __builtin_amdgcn_sched_barrier(0);  // fringe products after the MFMAs
+#pragma unroll
+        for (int q = 0; q < NFR; ++q)
+#pragma unroll
+          for (int u = 0; u < MF::KPL; ++u) fr[q] += MF::to_f64(fo[q][u]) * MF::to_f64(be[u]);
+        issue(nx, s);  // past the last strip: column 0 again, never used
+      }
       // one k step of lookahead only: without this fence the scheduler hoists
       // every LDS read of the loop and the register count quadruples
       __builtin_amdgcn_sched_barrier(0);
     }
-    // fringe rows on the vector ALU from the B registers (before the stores,
-    // so that the B registers are free while output factors are loaded); the
-    // last part only
-    constexpr int NFR = NMAX - 16 * QALL;
-    double fr[NFR > 0 ? NFR : 1] = {};
+    if constexpr (!ROLL) {
+#pragma unroll
+      for (int q = 0; q < NFR; ++q) {
+        if (!lastp) break;
+        double sum = 0.0;
+#pragma unroll
+        for (int s = 0; s < KSMAX; ++s) {
+          E be[MF::KPL];
+          operand(s, be);
+#pragma unroll
+          for (int u = 0; u < MF::KPL; ++u)
+            sum += MF::to_f64(fbase[(size_t)q * ld + s * MF::KSTEP + u]) * MF::to_f64(be[u]);
+        }
+        fr[q] = sum;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NFR; ++q) {
-      if (!lastp) break;
-      const E *orow = opl + (size_t)(16 * QMAX + q) * ld + kg * MF::KPL;
-      double sum = 0.0;
-#pragma unroll
-      for (int s = 0; s < KSMAX; ++s)
-#pragma unroll
-        for (int u = 0; u < MF::KPL; ++u)
-          sum += MF::to_f64(orow[s * MF::KSTEP + u]) * MF::to_f64(bv[s][u]);
-      sum += __shfl_xor(sum, 16, 64);
-      sum += __shfl_xor(sum, 32, 64);
-      fr[q] = sum;
+      fr[q] += __shfl_xor(fr[q], 16, 64);
+      fr[q] += __shfl_xor(fr[q], 32, 64);
     }
-    if (!cvalid) return;
+    if (!c.valid) return;
     double yv[QMAX][4];
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) yv[t][v] = (double)acc[t][v];
-    if (SC == 2) {
-      // all output factors of the lane in flight at once
-      double sc[QMAX][4], sf[NFR > 0 ? NFR : 1];
+    if constexpr (SC == 2) {
+      if constexpr (!ROLL) load_out_factors();
 #pragma unroll
       for (int t = 0; t < QMAX; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int j = row0 + 16 * t + MF::out_row(kg, v);
-          sc[t][v] = out_scale[j < n ? sb + (int64_t)j * step : sb];
-        }
+        for (int v = 0; v < 4; ++v) yv[t][v] *= osc[t][v];
 #pragma unroll
-      for (int q = 0; q < NFR; ++q) {
-        int j = 16 * QALL + q;
-        sf[q] = out_scale[j < n ? sb + (int64_t)j * step : sb];
-      }
-#pragma unroll
-      for (int t = 0; t < QMAX; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) yv[t][v] *= sc[t][v];
-#pragma unroll
-      for (int q = 0; q < NFR; ++q) fr[q] *= sf[q];
+      for (int q = 0; q < NFR; ++q) fr[q] *= osf[q];
     }
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int j = row0 + 16 * t + MF::out_row(kg, v);
-        if (j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(yv[t][v]);
+        if (j < n) out[c.base + (int64_t)j * c.step] = Conv<Tout>::from_f64(yv[t][v]);
       }
 #pragma unroll
     for (int q = 0; q < NFR; ++q) {
       int j = 16 * QALL + q;
-      if (lastp && kg == 0 && j < n) out[base + (int64_t)j * step] = Conv<Tout>::from_f64(fr[q]);
+      if (lastp && kg == 0 && j < n) out[c.base + (int64_t)j * c.step] = Conv<Tout>::from_f64(fr[q]);
     }
   };
-  int64_t strip = sblk * (GEMM2_THREADS / 64) + wave;
-  if (SC != 0) {
-    for (; strip < nstrips; strip += wstride) {
-      E bv[KSMAX][MF::KPL];
-      load_b(strip, bv);
-      process(strip, bv);
-    }
-    return;
-  }
-  // one strip in flight per wave while the current one is multiplied
-  E bnext[KSMAX][MF::KPL];
-  load_b(strip, bnext);
   for (; strip < nstrips; strip += wstride) {
-    E bv[KSMAX][MF::KPL];
+    if constexpr (ROLL) {
+      const Col nx = column(strip + wstride);
+      process(cur, nx);
+      cur = nx;
+    } else {
+      cur = column(strip);
 #pragma unroll
-    for (int s = 0; s < KSMAX; ++s)
-#pragma unroll
-      for (int u = 0; u < MF::KPL; ++u) bv[s][u] = bnext[s][u];
-    load_b(strip + wstride, bnext);
-    process(strip, bv);
+      for (int s = 0; s < KSMAX; ++s) issue(cur, s);
+      prepare();
+      process(cur, cur);
+    }
   }
 }
 

@@ -838,7 +838,9 @@ stig_status launch_time_arrow_gen(stig_plan *p, const Tio *in, Tio *out, int nrh
                       : (const TC *)p->aGtab32[transpose ? 1 : 0].p;
   {
     ProfScope ps(p, STIG_K_TIME_SOLVE, (double)cols * p->nt * 3 * sizeof(TC));
-    constexpr int L = 4;
+    // lanes per system, measured at 16,900 systems of 131 modes: FP64 17 us
+    // with 8 (21.6 with 4, 19.1 with 16), FP32 12.3 us with 4 (13.2 with 8)
+    constexpr int L = sizeof(TC) == 8 ? 8 : 4;
     const int64_t waves = (cols + 64 / L - 1) / (64 / L);
     if (waves * 64 > ((int64_t)1 << 20) * 256) return fail(STIG_EINVAL, "too many time systems");
     hipLaunchKernelGGL((time_arrow_middle<TC, L>), dim3(grid_for(waves * 64, 256)), dim3(256), 0,
@@ -1024,11 +1026,35 @@ stig_status run_apply(stig_plan *p, const double *r, double *s, int nrhs, int tr
     if (use_sym(l))
       return fwd ? launch_sym<Ti, To, TC, true>(p, tin, tout, l, inner, cols)
                  : launch_sym<Ti, To, TC, false>(p, tin, tout, l, inner, cols);
-    const bool first = fwd && l == 0, last = !fwd && l == 0;
+    const bool first = fwd && l == p->d - 1, last = !fwd && l == p->d - 1;
     return launch_mode_gemm<Ti, To, TC>(p, tin, tout, fwd ? OpSet<TC>::UT(p, l) : OpSet<TC>::U(p, l),
                                         p->n[l], inner, cols, first ? scale : nullptr,
                                         last ? scale : nullptr);
   };
+  if (scale) {
+    // D^{-1/2} on both sides: the products run from the slowest spatial axis
+    // to the fastest and back, so the two scaled ones (first and last) stride
+    // over whole rows (coalesced loads of values and factors) instead of
+    // running along the contiguous axis.  The mode products commute.
+    int64_t in_l[3] = {1, 1, 1};
+    for (int l = 1; l < p->d; ++l) in_l[l] = in_l[l - 1] * p->n[l - 1];
+    for (int l = p->d - 1; l >= 0; --l) {
+      if (l == p->d - 1) STIG_TRY(mode(r, buf[cur], l, true, in_l[l]));
+      else STIG_TRY(mode((const S *)buf[cur ^ 1], buf[cur], l, true, in_l[l]));
+      cur ^= 1;
+    }
+    STIG_TRY((launch_time<S, typename TimeCompute<TC>::type>(p, buf[cur ^ 1], buf[cur], nrhs,
+                                                              transpose, tv)));
+    cur ^= 1;
+    for (int l = 0; l < p->d; ++l) {
+      if (l == p->d - 1) STIG_TRY(mode((const S *)buf[cur ^ 1], s, l, false, in_l[l]));
+      else {
+        STIG_TRY(mode((const S *)buf[cur ^ 1], buf[cur], l, false, in_l[l]));
+        cur ^= 1;
+      }
+    }
+    return STIG_OK;
+  }
   // step 2: forward spatial transform, X x_l U_l^T for l = 1..d
   const bool fuse_sym = fuse && use_sym(0) && use_sym(1);
   int64_t inner = 1;
