@@ -192,6 +192,193 @@ __device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi
   }
 }
 
+// One 16-column strip j of a quadrant: Out[.][16j + c'] = (OpY In OpX^T)
+// for c' < 16, with In (16Q+RY) x (16Q+RX), OpX (16Q+RX)^2 and OpY (16Q+RY)^2
+// in LDS (leading dimensions ldi, ldo, ldo).  The strips of a quadrant are
+// independent: product 2 of strip j only needs strip j of Z = In OpX^T.
+// RY / RX: the quadrant's y / x size is 16Q + 1 (contraction index 16Q on
+// the vector ALU, as rank-one starts).  The fringe row 16Q of the output
+// (RY) is computed by every strip for its own columns; OWN: this strip also
+// computes the fringe column 16Q (of Z and of the output) and, with RY, the
+// corner.  store(row, col, value) receives every output entry of the strip,
+// after before_store() (called once, when the strip no longer reads `in`).
+template <typename TC, int Q, int RY, int RX, bool OWN, typename StoreF, typename SyncF>
+__device__ inline void quad_strip(const typename Mfma<TC>::elem *in, int ldi,
+                                  const typename Mfma<TC>::elem *opx,
+                                  const typename Mfma<TC>::elem *opy, int ldo, int c, int g, int j,
+                                  StoreF store, SyncF before_store) {
+  typedef Mfma<TC> MF;
+  typedef PlaneVal<TC> PV;
+  typedef typename PV::vt VT;
+  static_assert(!OWN || RX, "the fringe column exists only with RX");
+  constexpr int KSTEP = MF::KSTEP, KPL = MF::KPL, KS = 16 * Q / KSTEP, SPT = 16 / KSTEP;
+  auto xor_sum = [](VT x) {
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+  };
+  const typename MF::elem *oxrow = opx + 16 * Q * ldo;  // RX: row 16Q of OpX
+  const typename MF::elem *oxj = opx + (16 * j + c) * ldo;  // OpX row 16j + c
+  VT bxf = 0, oxff = 0;  // RX: OpX[16j + c][16Q], OpX[16Q][16Q]
+  if constexpr (RX != 0) {
+    bxf = PV::of(oxj[16 * Q]);
+    oxff = PV::of(oxrow[16 * Q]);
+  }
+  // ---- product 1: Z[y][16j + c] for y < 16Q
+  typename MF::acc acc1[Q];  // [row tile T]
+  VT zp[Q];                  // OWN: partial sums of Z[16T + c][16Q]
+#pragma unroll
+  for (int T = 0; T < Q; ++T) {
+    zp[T] = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc1[T][v] = 0;
+      if constexpr (RX != 0)  // contraction index 16Q: rank-one start
+        acc1[T][v] = PV::of(in[(16 * T + MF::out_row(g, v)) * ldi + 16 * Q]) * bxf;
+    }
+  }
+  // fragments of k step s (B: OpX row 16j + c, A: input rows 16T + c), read
+  // one step ahead, before the previous step's MFMAs (the fences keep them
+  // there), so the LDS latency runs under those MFMAs
+  typename MF::frag bqn, aqn[Q];
+  auto frags1 = [&](int s) {
+    bqn = MF::load(oxj + s * KSTEP + g * KPL);
+#pragma unroll
+    for (int T = 0; T < Q; ++T) aqn[T] = MF::load(in + (16 * T + c) * ldi + s * KSTEP + g * KPL);
+  };
+  frags1(0);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    typename MF::frag bq = bqn, aq[Q];
+#pragma unroll
+    for (int T = 0; T < Q; ++T) aq[T] = aqn[T];
+    VT of[KPL];
+    if constexpr (OWN) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) of[u] = PV::of(oxrow[s * KSTEP + g * KPL + u]);
+    }
+    if (s + 1 < KS) frags1(s + 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int T = 0; T < Q; ++T) {
+      acc1[T] = MF::mma(aq[T], bq, acc1[T]);
+      if constexpr (OWN) {
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) zp[T] += PV::get(aq[T], u) * of[u];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // fringe of product 1: row 16Q of Z for this strip (zr, RY), column 16Q
+  // (zp, OWN), corner (zcc, OWN and RY)
+  VT zr = 0, zcc = 0;
+  if constexpr (RY != 0) {
+    VT zc2 = 0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) {
+        const VT xv = PV::of(in[16 * Q * ldi + s * KSTEP + g * KPL + u]);
+        zr += xv * PV::of(oxj[s * KSTEP + g * KPL + u]);
+        if constexpr (OWN) zc2 += xv * PV::of(oxrow[s * KSTEP + g * KPL + u]);
+      }
+    zr = xor_sum(zr);
+    if constexpr (RX != 0) {
+      const VT x64 = PV::of(in[16 * Q * ldi + 16 * Q]);
+      zr += x64 * bxf;
+      if constexpr (OWN) zcc = xor_sum(zc2) + x64 * oxff;
+    }
+  }
+  if constexpr (OWN) {
+#pragma unroll
+    for (int T = 0; T < Q; ++T) zp[T] = xor_sum(zp[T]) + PV::of(in[(16 * T + c) * ldi + 16 * Q]) * oxff;
+  }
+  // ---- product 2: Out = OpY Z for the strip
+  VT yc[Q], ycc = 0;  // OWN: output column 16Q (rows 16t + c), corner
+#pragma unroll
+  for (int t = 0; t < Q; ++t) yc[t] = 0;
+  typename MF::acc acc2[Q];  // [row tile t]
+  VT yr = 0;                 // RY: output row 16Q of the strip
+#pragma unroll
+  for (int t = 0; t < Q; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc2[t][v] = 0;
+      if constexpr (RY != 0)
+        acc2[t][v] = PV::of(opy[(16 * t + MF::out_row(g, v)) * ldo + 16 * Q]) * zr;
+    }
+  // A fragments of OpY (and, RY, its row 16Q) one k step ahead, as in product 1
+  typename MF::frag an[Q];
+  VT oyn[KPL];
+  auto frags2 = [&](int s) {
+    const int kc = 16 * (s / SPT) + MF::out_row(g, (s % SPT) * KPL);
+#pragma unroll
+    for (int t = 0; t < Q; ++t) an[t] = MF::load(opy + (16 * t + c) * ldo + kc);
+    if constexpr (RY != 0) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) oyn[u] = PV::of(opy[16 * Q * ldo + kc + u]);
+    }
+  };
+  frags2(0);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int T = s / SPT, v0 = (s % SPT) * KPL;
+    typename MF::frag a[Q];
+    VT oyr[KPL];  // RY: OpY row 16Q at the contraction indices of this step
+#pragma unroll
+    for (int t = 0; t < Q; ++t) a[t] = an[t];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) oyr[u] = RY != 0 ? oyn[u] : VT(0);
+    if (s + 1 < KS) frags2(s + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    VT zc[KPL];
+    if constexpr (OWN) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) zc[u] = __shfl(zp[T], MF::out_row(g, v0 + u), 64);
+#pragma unroll
+      for (int t = 0; t < Q; ++t)
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) yc[t] += PV::get(a[t], u) * zc[u];
+    }
+    typename MF::elem be[KPL];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) be[u] = PV::to_elem(acc1[T][v0 + u]);
+    typename MF::frag b = MF::make(be);
+#pragma unroll
+    for (int t = 0; t < Q; ++t) acc2[t] = MF::mma(a[t], b, acc2[t]);
+    if constexpr (RY != 0) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) yr += oyr[u] * PV::of(be[u]);
+    }
+    if constexpr (RY != 0 && OWN) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) ycc += oyr[u] * zc[u];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  before_store();
+#pragma unroll
+  for (int t = 0; t < Q; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) store(16 * t + MF::out_row(g, v), 16 * j + c, (VT)acc2[t][v]);
+  if constexpr (RY != 0) {
+    const VT r = xor_sum(yr) + PV::of(opy[16 * Q * ldo + 16 * Q]) * zr;
+    if (g == 0) store(16 * Q, 16 * j + c, r);
+  }
+  if constexpr (OWN) {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      VT y = xor_sum(yc[t]);
+      if constexpr (RY != 0) y += PV::of(opy[(16 * t + c) * ldo + 16 * Q]) * zcc;
+      if (g == 0) store(16 * t + c, 16 * Q, y);
+    }
+    if constexpr (RY != 0) {
+      ycc = xor_sum(ycc) + PV::of(opy[16 * Q * ldo + 16 * Q]) * zcc;
+      if (g == 0 && c == 0) store(16 * Q, 16 * Q, ycc);
+    }
+  }
+}
+
 // LDS leading dimensions: quadrant columns start at 0 (even) and PS_COLO (odd,
 // rounded up so that bf16 fragments stay 8-byte aligned).
 template <int M, bool ODD> struct PlaneSymDims {
@@ -224,10 +411,20 @@ template <typename TC, int M, bool ODD, bool FWD> __host__ __device__ constexpr 
 // planes in `in`; !FWD: the reverse.  Plane o starts at in + o*in_stride and
 // out + o*out_stride (strides >= n*n; padding is neither read nor written).  opx*/opy*: half operators of directions
 // x and y (FWD: rows of U^T; !FWD: rows of U), even (NE x NE) and odd (M x M).
-// Block = 4 waves (one quadrant each); persistent over planes, the next
-// plane's loads in flight while the current one is transformed.
+// Block = 4 WQ waves: WQ per quadrant, each transforming Q / WQ of its
+// 16-column strips (Q = M / 16); registers sized for two blocks per CU
+// (2 WQ waves per SIMD); persistent over planes, the next plane's loads in
+// flight while the current one is transformed.  WQ = Q (one strip per wave)
+// in FP32 and BF16; in FP64 one wave per quadrant (a strip per wave needs more
+// than the 128 registers of four waves per SIMD: measured slower, spilling).
+template <typename TC, int M> __host__ __device__ constexpr int plane_sym_wq() {
+  return sizeof(typename Mfma<TC>::elem) == 8 ? 1 : M / 16;
+}
+template <typename TC, int M> __host__ __device__ constexpr int plane_sym_threads() {
+  return 64 * 4 * plane_sym_wq<TC, M>();
+}
 template <typename Tin, typename Tout, typename TC, int M, bool ODD, bool FWD>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__((plane_sym_threads<TC, M>()), (2 * plane_sym_wq<TC, M>()))
 mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
                     const typename Mfma<TC>::elem *__restrict__ opxE,
                     const typename Mfma<TC>::elem *__restrict__ opxO,
@@ -243,7 +440,7 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
   constexpr int NE = D::NE, N = D::N, COLO = D::COLO, Q = M / 16;
   constexpr int KSTEP = MF::KSTEP, KPL = MF::KPL, KS = 16 * Q / KSTEP;
   constexpr int LDP = plane_sym_ldp<TC, M, ODD>(), LDO = plane_sym_ldo<TC, M, ODD>();
-  constexpr int NT = 256;
+  constexpr int NT = plane_sym_threads<TC, M>(), WQ = plane_sym_wq<TC, M>();
   constexpr int NORB = NE * NE;                  // orbits (forward loads)
   constexpr int PER = FWD ? (NORB + NT - 1) / NT : (N * N + NT - 1) / NT;
   constexpr int NLD = FWD ? 4 : 1;               // loads per item
@@ -256,7 +453,8 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
                                              : reinterpret_cast<AE *>(pl);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int qa = w >> 1, qb = w & 1;  // quadrant: y parity, x parity (0 even)
+  const int quad = w / WQ, js = w % WQ;  // quadrant and strip of this wave
+  const int qa = quad >> 1, qb = quad & 1;  // quadrant: y parity, x parity (0 even)
 
   for (int e = tid; e < NE * NE; e += NT) {
     oy[(e / NE) * LDO + e % NE] = opyE[e];
@@ -328,11 +526,31 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
       if (FWD) dst[(r0 + row) * N + c0 + col] = Conv<Tout>::from_f64((double)v);
       else zb[(r0 + row) * LDP + cl0 + col] = (AE)v;
     };
-    switch (w) {  // wave-uniform
-      case 0: quad_transform<TC, Q, ODD ? 1 : 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
-      case 1: quad_transform<TC, Q, ODD ? 1 : 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
-      case 2: quad_transform<TC, Q, 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
-      default: quad_transform<TC, Q, 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+    if constexpr (WQ == 1) {
+      switch (quad) {  // wave-uniform
+        case 0: quad_transform<TC, Q, ODD ? 1 : 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+        case 1: quad_transform<TC, Q, ODD ? 1 : 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+        case 2: quad_transform<TC, Q, 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+        default: quad_transform<TC, Q, 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+      }
+    } else {
+      // the backward results overwrite the plane in LDS when they have its
+      // type: every strip of the quadrant has to be done reading it first
+      auto before_store = [&]() {
+        if constexpr (!FWD)
+          if ((void *)zb == (void *)pl) __syncthreads();
+      };
+      // wave-uniform: the quadrant's fringe sizes, and the fringe column for strip 0
+      constexpr int F = ODD ? 1 : 0;
+      switch (quad * 2 + (js == 0 ? 1 : 0)) {
+        case 1: quad_strip<TC, Q, F, F, ODD>(inq, LDP, opxq, opyq, LDO, c, g, js, store, before_store); break;
+        case 0: quad_strip<TC, Q, F, F, false>(inq, LDP, opxq, opyq, LDO, c, g, js, store, before_store); break;
+        case 2:
+        case 3: quad_strip<TC, Q, F, 0, false>(inq, LDP, opxq, opyq, LDO, c, g, js, store, before_store); break;
+        case 5: quad_strip<TC, Q, 0, F, ODD>(inq, LDP, opxq, opyq, LDO, c, g, js, store, before_store); break;
+        case 4: quad_strip<TC, Q, 0, F, false>(inq, LDP, opxq, opyq, LDO, c, g, js, store, before_store); break;
+        default: quad_strip<TC, Q, 0, 0, false>(inq, LDP, opxq, opyq, LDO, c, g, js, store, before_store); break;
+      }
     }
     __syncthreads();  // every quadrant done
     if (!FWD) {

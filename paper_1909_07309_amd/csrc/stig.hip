@@ -642,7 +642,7 @@ stig_status launch_plane_sym_m(stig_plan *p, const Tin *in, Tout *out, int64_t p
       HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds));
     int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, (plane_sym_threads<TC, M>()), lds));
     per_cu = std::max(nb, 1);
   }
   int64_t grid = std::min<int64_t>(planes, (int64_t)per_cu * p->num_cu);
@@ -650,7 +650,8 @@ stig_status launch_plane_sym_m(stig_plan *p, const Tin *in, Tout *out, int64_t p
   grid = (planes + per - 1) / per;
   const int n = 2 * M + (ODD ? 1 : 0);
   ProfScope ps(p, STIG_K_PLANE_GEMM, (double)planes * n * n * (sizeof(Tin) + sizeof(Tout)));
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, p->stream, in, out, xE, xO, yE, yO,
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((plane_sym_threads<TC, M>())), lds, p->stream, in, out,
+                     xE, xO, yE, yO,
                      planes, in_stride, out_stride);
   HIP_TRY(hipGetLastError());
   return STIG_OK;
