@@ -62,12 +62,21 @@ __device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi
           acc1[j][T][v] = PV::of(in[(16 * T + MF::out_row(g, v)) * ldi + 16 * Q]) * bxf[j];
       }
   }
+  // fringe sums of product 1, accumulated in the same k steps from the same
+  // operand values: row 16Q of Z (zr, RY), column 16Q (zp, RX), corner (zc2)
+  VT zr[Q], zcc = 0, zc2 = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) zr[j] = 0;
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
-    VT of[KPL];
+    VT of[KPL], xv[KPL];
     if constexpr (RX != 0) {
 #pragma unroll
       for (int u = 0; u < KPL; ++u) of[u] = PV::of(oxrow[s * KSTEP + g * KPL + u]);
+    }
+    if constexpr (RY != 0) {
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) xv[u] = PV::of(in[16 * Q * ldi + s * KSTEP + g * KPL + u]);
     }
     typename MF::frag bq[Q];  // B fragments of OpX rows 16j + c
 #pragma unroll
@@ -82,31 +91,24 @@ __device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi
         for (int u = 0; u < KPL; ++u) zp[T] += PV::get(a, u) * of[u];
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // fringe of product 1: row 16Q of Z (zr, RY), column 16Q (zc via zp, RX),
-  // corner (zcc, RX and RY)
-  VT zr[Q], zcc = 0;
-#pragma unroll
-  for (int j = 0; j < Q; ++j) zr[j] = 0;
-  if constexpr (RY != 0) {
-    VT zc2 = 0;
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
+    if constexpr (RY != 0) {
 #pragma unroll
       for (int u = 0; u < KPL; ++u) {
-        const VT xv = PV::of(in[16 * Q * ldi + s * KSTEP + g * KPL + u]);
 #pragma unroll
-        for (int j = 0; j < Q; ++j) zr[j] += xv * PV::of(opx[(16 * j + c) * ldo + s * KSTEP + g * KPL + u]);
-        if constexpr (RX != 0) zc2 += xv * PV::of(oxrow[s * KSTEP + g * KPL + u]);
+        for (int j = 0; j < Q; ++j) zr[j] += xv[u] * PV::get(bq[j], u);
+        if constexpr (RX != 0) zc2 += xv[u] * of[u];
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (RY != 0) {
 #pragma unroll
     for (int j = 0; j < Q; ++j) zr[j] = xor_sum(zr[j]);
     if constexpr (RX != 0) {
       const VT x64 = PV::of(in[16 * Q * ldi + 16 * Q]);
 #pragma unroll
       for (int j = 0; j < Q; ++j) zr[j] += x64 * bxf[j];
-      zcc = xor_sum(zc2) + x64 * oxff;
+      if constexpr (RX != 0) zcc = xor_sum(zc2) + x64 * oxff;
     }
   }
   if constexpr (RX != 0) {
@@ -132,6 +134,15 @@ __device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi
           acc2[j][t][v] = PV::of(opy[(16 * t + MF::out_row(g, v)) * ldo + 16 * Q]) * zr[j];
       }
   }
+  // RX: Z[y][16Q] at the contraction indices of a k step, gathered across
+  // lanes one step ahead (the shuffle's latency runs under a step's MFMAs)
+  VT zcn[KPL];
+  auto zc_of = [&](int s) {
+#pragma unroll
+    for (int u = 0; u < KPL; ++u)
+      zcn[u] = __shfl(zp[s / SPT], MF::out_row(g, (s % SPT) * KPL + u), 64);
+  };
+  if constexpr (RX != 0) zc_of(0);
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     const int T = s / SPT, v0 = (s % SPT) * KPL;
@@ -142,7 +153,8 @@ __device__ inline void quad_transform(const typename Mfma<TC>::elem *in, int ldi
     VT zc[KPL];
     if constexpr (RX != 0) {
 #pragma unroll
-      for (int u = 0; u < KPL; ++u) zc[u] = __shfl(zp[T], MF::out_row(g, v0 + u), 64);
+      for (int u = 0; u < KPL; ++u) zc[u] = zcn[u];
+      if (s + 1 < KS) zc_of(s + 1);
 #pragma unroll
       for (int t = 0; t < Q; ++t)
 #pragma unroll
@@ -527,10 +539,13 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
       else zb[(r0 + row) * LDP + cl0 + col] = (AE)v;
     };
     if constexpr (WQ == 1) {
-      switch (quad) {  // wave-uniform
-        case 0: quad_transform<TC, Q, ODD ? 1 : 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
-        case 1: quad_transform<TC, Q, ODD ? 1 : 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
-        case 2: quad_transform<TC, Q, 0, ODD ? 1 : 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+      // wave-uniform: each wave transforms its own quadrant, which it alone
+      // reads and (backward) overwrites
+      constexpr int F = ODD ? 1 : 0;
+      switch (quad) {
+        case 0: quad_transform<TC, Q, F, F>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+        case 1: quad_transform<TC, Q, F, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
+        case 2: quad_transform<TC, Q, 0, F>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
         default: quad_transform<TC, Q, 0, 0>(inq, LDP, opxq, opyq, LDO, c, g, store); break;
       }
     } else {
@@ -554,19 +569,33 @@ mode_gemm_plane_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
     }
     __syncthreads();  // every quadrant done
     if (!FWD) {
-      // X at the four mirror points of each half coordinate
-      for (int e = tid; e < NORB; e += NT) {
-        const int yh = e / NE, xh = e - yh * NE;
-        const bool xm = ODD && xh == M, ym = ODD && yh == M;
-        const double zee = (double)zb[yh * LDP + xh];
-        const double zeo = xm ? 0.0 : (double)zb[yh * LDP + COLO + xh];
-        const double zoe = ym ? 0.0 : (double)zb[(NE + yh) * LDP + xh];
-        const double zoo = (xm || ym) ? 0.0 : (double)zb[(NE + yh) * LDP + COLO + xh];
-        const int y2 = N - 1 - yh, x2 = N - 1 - xh;
-        dst[yh * N + xh] = Conv<Tout>::from_f64((zee + zoe) + (zeo + zoo));
-        if (!xm) dst[yh * N + x2] = Conv<Tout>::from_f64((zee + zoe) - (zeo + zoo));
-        if (!ym) dst[y2 * N + xh] = Conv<Tout>::from_f64((zee - zoe) + (zeo - zoo));
-        if (!xm && !ym) dst[y2 * N + x2] = Conv<Tout>::from_f64((zee - zoe) - (zeo - zoo));
+      // X at the four mirror points of each half coordinate, two half
+      // coordinates per trip, branch-free: the LDS reads past the middle row /
+      // column stay inside the allocation and are replaced by zeros, and on the
+      // middle row / column the mirror point is the point itself, so its
+      // second store writes the same value again
+      constexpr int PB = (NORB + NT - 1) / NT;
+#pragma unroll 1
+      for (int i0 = 0; i0 < PB; i0 += 2)
+#pragma unroll
+      for (int i = i0; i < i0 + 2; ++i) {
+        const int e = tid + i * NT;
+        if (i < PB && e < NORB) {
+          const int yh = e / NE, xh = e - yh * NE;
+          const bool xm = ODD && xh == M, ym = ODD && yh == M;
+          const double zee = (double)zb[yh * LDP + xh];
+          double zeo = (double)zb[yh * LDP + COLO + xh];
+          double zoe = (double)zb[(NE + yh) * LDP + xh];
+          double zoo = (double)zb[(NE + yh) * LDP + COLO + xh];
+          if (xm) zeo = 0.0;
+          if (ym) zoe = 0.0;
+          if (xm || ym) zoo = 0.0;
+          const int y2 = N - 1 - yh, x2 = N - 1 - xh;
+          dst[yh * N + xh] = Conv<Tout>::from_f64((zee + zoe) + (zeo + zoo));
+          dst[yh * N + x2] = Conv<Tout>::from_f64((zee + zoe) - (zeo + zoo));
+          dst[y2 * N + xh] = Conv<Tout>::from_f64((zee - zoe) + (zeo - zoo));
+          dst[y2 * N + x2] = Conv<Tout>::from_f64((zee - zoe) - (zeo - zoo));
+        }
       }
       if ((void *)zb == (void *)pl) __syncthreads();  // the results alias the plane
     }
