@@ -31,7 +31,8 @@ struct alignas(sizeof(T) * CG) ColPack {
 // the half product, columns = contraction index (FWD: Ue^T, Uo^T; !FWD: Ue, Uo).
 // M is a multiple of 16.  Each wave streams strips of 16 CG columns; the
 // operators sit in LDS; the B operand (the butterflied or split input) is
-// loaded straight into registers in the MFMA layout, one strip ahead.
+// loaded straight into registers in the MFMA layout, the next strip's k steps
+// one by one under the current strip's products.
 // Column groups: lane l % 16 owns the CG adjacent columns 16 CG s + CG (l % 16)
 // .. + CG - 1 of strip s and feeds them to CG separate MFMA tiles that share
 // each A fragment; its loads and stores are CG-element vectors (8 bytes for
@@ -41,8 +42,13 @@ struct alignas(sizeof(T) * CG) ColPack {
 // Dynamic LDS: (NE + M) * lds_ld<TC>(NE) elements.
 constexpr int SYM_THREADS = 256;
 
+// waves per SIMD the registers are sized for: 3 (168 registers), FP32 with
+// column pairs 2
+template <typename TC, int CG> __host__ __device__ constexpr int sym_waves() {
+  return sizeof(typename Mfma<TC>::elem) == 4 && CG > 1 ? 2 : 3;
+}
 template <typename Tin, typename Tout, typename TC, int M, bool ODD, bool FWD, int CG>
-__global__ void __launch_bounds__(SYM_THREADS)
+__global__ void __launch_bounds__(SYM_THREADS, (sym_waves<TC, CG>()))
 mode_gemm_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
               const typename Mfma<TC>::elem *__restrict__ opE,
               const typename Mfma<TC>::elem *__restrict__ opO, int64_t inner,
@@ -59,16 +65,6 @@ mode_gemm_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
   E *le = reinterpret_cast<E *>(smem);  // [NE][ld]
   E *lo = le + NE * ld;                 // [M][ld]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < NE * NE; e += SYM_THREADS) {
-    int j = e / NE, k = e - j * NE;
-    le[j * ld + k] = opE[e];
-  }
-  for (int e = tid; e < M * M; e += SYM_THREADS) {
-    int j = e / M, k = e - j * M;
-    lo[j * ld + k] = opO[e];
-  }
-  __syncthreads();
-
   const int64_t nstrips = (total_cols + 16 * CG - 1) / (16 * CG);
   const int64_t slab = (int64_t)N * inner;
   const uint32_t uinner = (uint32_t)inner;
@@ -96,50 +92,50 @@ mode_gemm_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
     if constexpr (KPL == 1) return MF::to_f64(f);
     else return MF::to_f64((E)(uint16_t)f[u]);
   };
-  struct Frags {
-    typename MF::frag e[CG][KS], o[CG][KS];
-    double m[CG];  // ODD: the middle entry (contraction index M of the even half)
-  };
-  // B operands of one strip (branch-free loads)
-  auto load_b = [&](int64_t strip, Frags &f) {
-    const int64_t c = (strip * 16 + col) * CG;
-    const bool cvalid = strip < nstrips && c < total_cols;
+  // The B operand of a strip stays in registers as the raw entries (both
+  // mirror entries per contraction index), one slot per k step; the butterfly
+  // is formed when the slot is used.  Slot s takes the next strip's k step s
+  // as soon as the MFMAs of step s have read it, so the next strip's loads run
+  // under this strip's products with one set of registers (a second full set,
+  // double buffering, costs a wave per SIMD).
+  PIn ra[KS][KPL], rb[KS][KPL];  // entries k and its mirror (FWD) / partner (!FWD)
+  PIn rm;                         // ODD: the middle entry M
+  struct Col {
     int64_t base, step;
-    locate(cvalid ? c : 0, base, step);
+    bool valid;
+  };
+  auto column = [&](int64_t strip) {
+    const int64_t c = (strip * 16 + col) * CG;
+    Col r;
+    r.valid = strip < nstrips && c < total_cols;
+    locate(r.valid ? c : 0, r.base, r.step);
+    return r;
+  };
+  auto issue = [&](const Col &L, int s) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      E te[CG][KPL], to[CG][KPL];
-#pragma unroll
-      for (int u = 0; u < KPL; ++u) {
-        const int k = s * MF::KSTEP + kg * KPL + u;  // < M
-        const PIn a = vload(cvalid ? base + (int64_t)k * step : 0);
-        const PIn b = vload(cvalid ? base + (int64_t)(FWD ? N - 1 - k : NE + k) * step : 0);
-#pragma unroll
-        for (int g = 0; g < CG; ++g) {
-          const double x = Conv<Tin>::to_f64(a.v[g]), y = Conv<Tin>::to_f64(b.v[g]);
-          te[g][u] = MF::from_f64(FWD ? x + y : x);
-          to[g][u] = MF::from_f64(FWD ? x - y : y);
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < CG; ++g) {
-        f.e[g][s] = MF::make(te[g]);
-        f.o[g][s] = MF::make(to[g]);
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < CG; ++g) f.m[g] = 0.0;
-    if (ODD) {
-      const PIn mm = vload(cvalid ? base + (int64_t)M * step : 0);
-#pragma unroll
-      for (int g = 0; g < CG; ++g) f.m[g] = MF::to_f64(MF::from_f64(Conv<Tin>::to_f64(mm.v[g])));
+    for (int u = 0; u < KPL; ++u) {
+      const int k = s * MF::KSTEP + kg * KPL + u;  // < M
+      ra[s][u] = vload(L.base + (int64_t)k * L.step);
+      rb[s][u] = vload(L.base + (int64_t)(FWD ? N - 1 - k : NE + k) * L.step);
     }
   };
-  auto process = [&](int64_t strip, const Frags &f) {
-    const int64_t c = (strip * 16 + col) * CG;
-    const bool cvalid = c < total_cols;
-    int64_t base, step;
-    locate(cvalid ? c : 0, base, step);
+  // fragments of k step s for column group g: even and odd halves
+  auto frags = [&](int s, int g, typename MF::frag &fe, typename MF::frag &fo) {
+    E te[KPL], to[KPL];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) {
+      const double x = Conv<Tin>::to_f64(ra[s][u].v[g]), y = Conv<Tin>::to_f64(rb[s][u].v[g]);
+      te[u] = MF::from_f64(FWD ? x + y : x);
+      to[u] = MF::from_f64(FWD ? x - y : y);
+    }
+    fe = MF::make(te);
+    fo = MF::make(to);
+  };
+  auto process = [&](const Col &cc, const Col &nx) {
+    double fm[CG];  // ODD: the middle entry, as the operand type rounds it
+#pragma unroll
+    for (int g = 0; g < CG; ++g) fm[g] = ODD ? MF::to_f64(MF::from_f64(Conv<Tin>::to_f64(rm.v[g]))) : 0.0;
+    if (ODD) rm = vload(nx.base + (int64_t)M * nx.step);
     typename MF::acc ae[CG][Q], ao[CG][Q];
 #pragma unroll
     for (int t = 0; t < Q; ++t)
@@ -150,46 +146,67 @@ mode_gemm_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
 #pragma unroll
         for (int g = 0; g < CG; ++g) {
           ao[g][t][v] = 0;
-          ae[g][t][v] = ODD ? (typename MF::acc_elem)(cm * f.m[g]) : (typename MF::acc_elem)0;
+          ae[g][t][v] = ODD ? (typename MF::acc_elem)(cm * fm[g]) : (typename MF::acc_elem)0;
         }
       }
     const E *abe = le + col * ld + kg * KPL, *abo = lo + col * ld + kg * KPL;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-#pragma unroll
-      for (int t = 0; t < Q; ++t) {
-        const typename MF::frag fe = MF::load(abe + 16 * t * ld + s * MF::KSTEP);
-        const typename MF::frag fo = MF::load(abo + 16 * t * ld + s * MF::KSTEP);
-#pragma unroll
-        for (int g = 0; g < CG; ++g) {
-          ae[g][t] = MF::mma(fe, f.e[g][s], ae[g][t]);
-          ao[g][t] = MF::mma(fo, f.o[g][s], ao[g][t]);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    // ODD: row M of the even half on the vector ALU
+    // ODD: row M of the even half on the vector ALU, accumulated in the same
+    // k steps from the same operand values
     double fr[CG];
 #pragma unroll
     for (int g = 0; g < CG; ++g) fr[g] = 0.0;
-    if (ODD) {
+    // A fragments one k step ahead, read before the previous step's MFMAs
+    typename MF::frag ane[Q], ano[Q];
+    auto afr = [&](int s) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
+      for (int t = 0; t < Q; ++t) {
+        ane[t] = MF::load(abe + 16 * t * ld + s * MF::KSTEP);
+        ano[t] = MF::load(abo + 16 * t * ld + s * MF::KSTEP);
+      }
+    };
+    afr(0);
 #pragma unroll
-        for (int u = 0; u < KPL; ++u) {
-          const double w = MF::to_f64(le[M * ld + s * MF::KSTEP + kg * KPL + u]);
+    for (int s = 0; s < KS; ++s) {
+      typename MF::frag fe[Q], fo[Q];
 #pragma unroll
-          for (int g = 0; g < CG; ++g) fr[g] += w * felem(f.e[g][s], u);
+      for (int t = 0; t < Q; ++t) {
+        fe[t] = ane[t];
+        fo[t] = ano[t];
+      }
+      double w[KPL];
+      if (ODD) {
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) w[u] = MF::to_f64(le[M * ld + s * MF::KSTEP + kg * KPL + u]);
+      }
+      if (s + 1 < KS) afr(s + 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int g = 0; g < CG; ++g) {
+        typename MF::frag be, bo;
+        frags(s, g, be, bo);
+#pragma unroll
+        for (int t = 0; t < Q; ++t) {
+          ae[g][t] = MF::mma(fe[t], be, ae[g][t]);
+          ao[g][t] = MF::mma(fo[t], bo, ao[g][t]);
         }
+        if (ODD) {
+#pragma unroll
+          for (int u = 0; u < KPL; ++u) fr[g] += w[u] * felem(be, u);
+        }
+      }
+      issue(nx, s);  // past the last strip: column 0 again, never used
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ODD) {
       const double wm = MF::to_f64(le[M * ld + M]);
 #pragma unroll
       for (int g = 0; g < CG; ++g) {
         fr[g] += __shfl_xor(fr[g], 16, 64);
         fr[g] += __shfl_xor(fr[g], 32, 64);
-        fr[g] += wm * f.m[g];
+        fr[g] += wm * fm[g];
       }
     }
-    if (cvalid) {
+    if (cc.valid) {
 #pragma unroll
       for (int t = 0; t < Q; ++t)
 #pragma unroll
@@ -202,19 +219,31 @@ mode_gemm_sym(const Tin *__restrict__ in, Tout *__restrict__ out,
             lo_[g] = FWD ? ve : ve + vo;
             hi_[g] = FWD ? vo : ve - vo;
           }
-          vstore(base + (int64_t)j * step, lo_);
-          vstore(base + (int64_t)(FWD ? NE + j : N - 1 - j) * step, hi_);
+          vstore(cc.base + (int64_t)j * cc.step, lo_);
+          vstore(cc.base + (int64_t)(FWD ? NE + j : N - 1 - j) * cc.step, hi_);
         }
-      if (ODD && kg == 0) vstore(base + (int64_t)M * step, fr);
+      if (ODD && kg == 0) vstore(cc.base + (int64_t)M * cc.step, fr);
     }
   };
   int64_t strip = (int64_t)blockIdx.x * (SYM_THREADS / 64) + wave;
-  Frags fnext;
-  load_b(strip, fnext);
+  Col cur = column(strip);
+  // the first strip's loads go out before the operator copy, so the two overlap
+#pragma unroll
+  for (int s = 0; s < KS; ++s) issue(cur, s);
+  if (ODD) rm = vload(cur.base + (int64_t)M * cur.step);
+  for (int e = tid; e < NE * NE; e += SYM_THREADS) {
+    int j = e / NE, k = e - j * NE;
+    le[j * ld + k] = opE[e];
+  }
+  for (int e = tid; e < M * M; e += SYM_THREADS) {
+    int j = e / M, k = e - j * M;
+    lo[j * ld + k] = opO[e];
+  }
+  __syncthreads();
   for (; strip < nstrips; strip += wstride) {
-    Frags f = fnext;
-    load_b(strip + wstride, fnext);
-    process(strip, f);
+    const Col nx = column(strip + wstride);
+    process(cur, nx);
+    cur = nx;
   }
 }
 
