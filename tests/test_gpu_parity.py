@@ -62,11 +62,13 @@ def test_apply_pinv_fp64_matches_oracle(name, n_el, transpose):
         assert res <= 1e-13
 
 
-@pytest.mark.parametrize("n_el", [5, 14, 48, 64])
+@pytest.mark.parametrize("n_el", [5, 14, 48, 63, 64])
 def test_fused_plane_products_match_per_mode_passes(n_el):
     """apply_Pinv with the fused mode-1/mode-2 plane kernel against one pass per
     mode and against the oracle: n_s = 6, 15 (runtime size, zero padded), 49 and
-    65 (compile-time sizes 16q + 1 with vector-ALU fringes), every precision."""
+    65 (compile-time sizes 16q + 1 with vector-ALU fringes), and 64 (the even
+    size of the parity-split plane kernel with one wave per 16-column strip in
+    FP32 and BF16), every precision."""
     w, fac, plan, pr = _setup("cube_p3_n64", n_el)
     nrhs = 2 if n_el < 64 else 1
     r = wl.random_tensor((nrhs,) + w.shape, 11)
@@ -119,9 +121,9 @@ def test_time_kernels_match_oracle(name, n_el, kernel):
         assert e <= 2 * ed + 1e-3, (kernel, transpose, e, ed)
 
 
-@pytest.mark.parametrize("n_el", [31, 32, 64])
+@pytest.mark.parametrize("n_el", [31, 32, 63, 64])
 def test_parity_split_products_match_oracle(n_el):
-    """n_s = 32, 33, 65: half-size products around the butterfly (split basis),
+    """n_s = 32, 33, 64, 65: half-size products around the butterfly (split basis),
     with and without the fused plane pass, against the dense products and the
     oracle, every precision, plain and transposed."""
     w, fac, plan, pr = _setup("cube_p3_n64", n_el)
