@@ -369,12 +369,14 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   // 131).  The runtime-n form (fringe rows accumulated after the products)
   // loads each strip after the previous one's stores and converts it to
   // operands at once, and so do the BF16 forms with a wider input type (their
-  // raw values take 2-4 times the operand registers) and the scaled forms whose
-  // input is wider than the accumulator or whose operands are BF16 (rolled,
-  // they spill).
+  // raw values take 2-4 times the operand registers), the scaled forms whose
+  // input is wider than the accumulator or whose operands are BF16, and the
+  // FP64 input-scaled form (rolled, they spill: 36.0 against 32.0 us for the
+  // FP64 n = 130 product at 16,900 columns of 131).
   constexpr bool ROLL =
       NC != 0 && (SC == 0 ? (MF::KPL == 1 || sizeof(Tin) == sizeof(E))
-                          : (MF::KPL == 1 && sizeof(Tin) <= sizeof(typename MF::acc_elem)));
+                          : (MF::KPL == 1 && sizeof(Tin) <= sizeof(typename MF::acc_elem) &&
+                             !(SC == 1 && sizeof(E) == 8)));
   constexpr bool SCI = SC == 1;
   Tin raw[KSMAX][MF::KPL];
   double rsc[SCI ? KSMAX : 1][MF::KPL];
