@@ -255,7 +255,7 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   // pass 1: sums h^T H^{-1} g and h^T H^{-1} x (unrolled: the loads of several
   // blocks in flight)
   TC sp = 0, yp = 0;
-#pragma unroll 4
+#pragma unroll 8
   for (int j = grp; j < nb; j += L) {
     const int a = 2 * j;
     const TC x1 = xc[(int64_t)a * ns], x2 = xc[(int64_t)(a + 1) * ns];
@@ -277,7 +277,7 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   const TC sch = gamma * tab[3 * n] + nul - gamma * gamma * sp;
   const TC qn = (xn - gamma * yp) * recip(sch);
   // pass 2: q_B = H^{-1} (x_B - gamma g q_n)
-#pragma unroll 4
+#pragma unroll 8
   for (int j = grp; j < nb; j += L) {
     const int a = 2 * j;
     const TC g1 = gv[a], g2 = gv[a + 1];
