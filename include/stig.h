@@ -125,9 +125,9 @@ stig_status stig_set_workspace(stig_plan *plan, void *ws, size_t bytes);
  *     0 (default): for the register-resident shapes (n_t, p_t) = (66, 3),
  *     (50, 3), (9, 2), banded elimination right-looking with window-state
  *     checkpoints, the forward substitution redone segment by segment in the
- *     backward sweep (nothing stored); for n_t = 131 with fewer than 262,144
- *     systems per call (N_s times the right-hand sides), the arrowhead form of 4
- *     (its products along t have a compile-time kernel there); otherwise the
+ *     backward sweep (nothing stored); for n_t = 131 or 33 with fewer than
+ *     262,144 systems per call (N_s times the right-hand sides), the arrowhead
+ *     form of 4 (its products along t have a compile-time kernel there); otherwise the
  *     generic banded kernel of 2.
  *     3 = as 0, with the forward-substituted values stored and read back;
  *     1 = left-looking, U-row checkpoints (register shapes; generic otherwise);

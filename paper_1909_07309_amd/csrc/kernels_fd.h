@@ -1015,7 +1015,9 @@ time_band_solve_rl(const Tio *__restrict__ in, Tio *__restrict__ out, const doub
   __shared__ TC rstash[LROWS > 0 ? LROWS * 256 : 1];
   typedef SegPlan<NT, P, NSEG> SP;
   constexpr int LMAX = SP::maxlen();
-  constexpr int D = NT - P < 8 ? NT - P : 8;  // right-hand-side prefetch distance (rows)
+  // right-hand-side prefetch distance (rows)
+  constexpr int DP = sizeof(TC) == 8 ? 8 : 16;  // measured: FP64 no gain past 8
+  constexpr int D = NT - P < DP ? NT - P : DP;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ns * nrhs) return;
   int64_t rhs = g / ns, k = g - rhs * ns;

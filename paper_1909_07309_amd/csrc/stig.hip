@@ -438,11 +438,11 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
   if (total_cols >= ((int64_t)1 << 31)) return fail(STIG_EINVAL, "tensor too large for one launch");
   // streaming kernel: compile-time sizes of the workloads' spatial directions
   // (65, 49: cube; 32: extruded annulus; 130: annulus; scaled: 32, 130) and of
-  // the annulus time axis (131, arrowhead form), runtime n up to GEMM2_MAX_N
-  // otherwise
+  // the annulus time axes (131 and 33, arrowhead form), runtime n up to
+  // GEMM2_MAX_N otherwise
   const bool sc = in_scale || out_scale;
   const int nc = sc ? ((n == 32 || n == 130) ? n : 0)
-                    : ((n == 65 || n == 49 || n == 32 || n == 130 || n == 131) ? n : 0);
+                    : ((n == 65 || n == 49 || n == 32 || n == 130 || n == 131 || n == 33) ? n : 0);
   // the streaming kernel scales either its input or its output; both at once
   // take the tiled kernel
   if ((nc != 0 || n <= GEMM2_MAX_N) && !(in_scale && out_scale)) {
@@ -457,9 +457,9 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     if (lds > GEMM_LDS_LIMIT) return fail(STIG_EINVAL, "mode size too large for LDS");
     int64_t nstrips = (total_cols + 15) / 16;
     ProfScope ps(p, STIG_K_MODE_GEMM, (double)total_cols * n * (sizeof(Tin) + sizeof(Tout)));
-    static size_t configured[12] = {};  // per kernel of this type triple
-    static int per_cu[12] = {};         // resident blocks per CU at that LDS size
-    static size_t per_cu_lds[12] = {};
+    static size_t configured[13] = {};  // per kernel of this type triple
+    static int per_cu[13] = {};         // resident blocks per CU at that LDS size
+    static size_t per_cu_lds[13] = {};
     auto go = [&](auto kern, int slot) -> stig_status {
       if (lds > 65536 && lds > configured[slot]) {
         HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -498,6 +498,7 @@ stig_status launch_mode_gemm(stig_plan *p, const Tin *in, Tout *out,
     if (nc == 32) return go(mode_gemm_small<Tin, Tout, TC, 32, 0>, 2);
     if (nc == 130) return go(mode_gemm_small<Tin, Tout, TC, 130, 0, RS130>, 3);
     if (nc == 131) return go(mode_gemm_small<Tin, Tout, TC, 131, 0, RS130>, 8);
+    if (nc == 33) return go(mode_gemm_small<Tin, Tout, TC, 33, 0>, 12);
     return go(mode_gemm_small<Tin, Tout, TC, 0, 0>, 4);
   }
   const int jt = (n + 15) / 16;
@@ -865,11 +866,12 @@ bool time_arrow_shape(const stig_plan *p) {
 // wavefront per SIMD at four waves each), and a long time axis makes each lane's
 // chain long: the default (time kernel 0) then takes the arrowhead three-pass
 // form, whose mode products parallelise over the time axis too, where its
-// products have a compile-time streaming kernel (n_t = 131; measured faster
-// there: 0.20 vs 0.25 ms per FP64 apply on the 128-element annulus, slower at
-// n_t = 33 with 32,768 systems, 0.115 vs 0.080 ms).
+// products have a compile-time streaming kernel (n_t = 131, 33; measured
+// faster there: 0.20 vs 0.25 ms per FP64 apply on the 128-element annulus,
+// 0.066 vs 0.073 ms on the extruded one, n_t = 33 with 32,768 systems, which
+// took 0.115 ms while its products ran the runtime-n kernel).
 constexpr int64_t ARROW_AUTO_SYSTEMS = 262144;
-bool arrow_auto_nt(int nt) { return nt == 131; }
+bool arrow_auto_nt(int nt) { return nt == 131 || nt == 33; }
 
 // the three-pass arrowhead form: chosen (time kernel 4, other n_t than the
 // fused kernel's) or taken by the default

@@ -61,16 +61,21 @@ def test_annulus3d_full_size_csr_and_solve():
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
     # the 3D A-hat^G apply at n_s = 32 (compile-time mode products with the
     # diagonal scaling fused into the first and last), element by element
-    # against the oracle, FP64 and FP32, plain and transposed
+    # against the oracle, FP64 and FP32, plain and transposed, with both forms
+    # of step 3 (the default at n_t = 33 is the arrowhead form, whose products
+    # along t have a compile-time kernel; the generic banded elimination)
     P = o.preconditioner()
-    for tr in (False, True):
-        ref_s = P.apply(x, transpose=tr)
-        s64 = plan.apply_Pinv(_dev(x), transpose=tr).cpu().numpy()
-        s32 = plan.apply_Pinv(_dev(x), transpose=tr, prec="fp32").cpu().numpy()
-        e64 = np.abs(s64 - ref_s).max() / np.abs(ref_s).max()
-        e32 = np.abs(s32 - ref_s).max() / np.abs(ref_s).max()
-        print(f"3D annulus apply (transpose={tr}): FP64 {e64:.2e}, FP32 {e32:.2e}")
-        assert e64 <= 1e-12 and e32 <= 1e-4
+    for kernel in ("right_looking", "generic"):
+        plan.set_option("time_kernel", kernel)
+        for tr in (False, True):
+            ref_s = P.apply(x, transpose=tr)
+            s64 = plan.apply_Pinv(_dev(x), transpose=tr).cpu().numpy()
+            s32 = plan.apply_Pinv(_dev(x), transpose=tr, prec="fp32").cpu().numpy()
+            e64 = np.abs(s64 - ref_s).max() / np.abs(ref_s).max()
+            e32 = np.abs(s32 - ref_s).max() / np.abs(ref_s).max()
+            print(f"3D annulus apply ({kernel}, transpose={tr}): FP64 {e64:.2e}, FP32 {e32:.2e}")
+            assert e64 <= 1e-12 and e32 <= 1e-4
+    plan.set_option("time_kernel", "right_looking")
     f = a.source()
     u, info = plan.gmres_solve(f, restart=30, rtol=1e-8, maxit=300, flexible=True, prec="fp32")
     f_ref = o.source()
