@@ -294,4 +294,120 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
   }
 }
 
+// The same solve with each block taking CB = 256 / G consecutive columns and
+// G threads per column (thread tid: column tid % CB, group tid / CB, blocks
+// j = group + G i).  A half-wave (FP64, CB = 32) or a wave (FP32, CB = 64)
+// then reads and writes whole 256-byte runs of a mode row, and a thread keeps
+// its JM >= ceil(nb / G) blocks and their reciprocals in registers between the
+// two passes, so x is read once.  The table goes to LDS first (its loads in
+// flight with those of x; read from global memory inside the loops, each
+// step's table loads took a round trip of their own).  The group sums are
+// reduced through LDS in a fixed order, and the two modes after the blocks come
+// from group 0 through LDS too (no thread reads a row that another writes).
+template <typename TC, int G, int JM>
+__global__ void __launch_bounds__(256)
+time_arrow_middle_reg(TC *__restrict__ x, const double *__restrict__ lam,
+                      const TC *__restrict__ tab, TC gamma, TC nu, int n, int nz, int64_t ns,
+                      int64_t cols) {
+  constexpr int CB = 256 / G;
+  constexpr int NT = 3 * (2 * G * JM + 2) + 1;  // table entries at the largest n
+  static_assert(CB * G == 256 && CB % 32 == 0, "columns per block");
+  __shared__ TC red[2][G][CB];
+  __shared__ TC last[2][CB];
+  __shared__ TC tl[NT];
+  const int tid = threadIdx.x, cl = tid % CB, grp = tid / CB;
+  const int64_t c = (int64_t)blockIdx.x * CB + cl;
+  const bool valid = c < cols;
+  const int64_t cc = valid ? c : 0;
+  const int64_t rhs = cc / ns, k = cc - rhs * ns;
+  TC *xc = x + rhs * ns * n + k;
+  const int nb = (n - 1 - nz) / 2, ntab = 3 * n + 1;
+  TC tv[(NT + 255) / 256];
+#pragma unroll
+  for (int u = 0; u < (NT + 255) / 256; ++u) {
+    const int e = tid + 256 * u;
+    tv[u] = tab[e < ntab ? e : 0];
+  }
+  TC xr[JM][2], ir[JM];
+#pragma unroll
+  for (int i = 0; i < JM; ++i) {
+    const int j = grp + G * i;
+    xr[i][0] = xr[i][1] = ir[i] = 0;
+    if (j < nb) {
+      xr[i][0] = xc[(int64_t)(2 * j) * ns];
+      xr[i][1] = xc[(int64_t)(2 * j + 1) * ns];
+    }
+  }
+  TC xz = 0, xn = 0;
+  if (grp == 0) {
+    if (nz) xz = xc[(int64_t)(n - 2) * ns];
+    xn = xc[(int64_t)(n - 1) * ns];
+  }
+  const TC nul = nu * (TC)lam[k];
+#pragma unroll
+  for (int u = 0; u < (NT + 255) / 256; ++u) {
+    const int e = tid + 256 * u;
+    if (e < ntab) tl[e] = tv[u];
+  }
+  __syncthreads();
+  const TC *dd = tl, *gv = tl + n, *hv = tl + 2 * n;
+  // pass 1: this group's share of h^T H^{-1} g and h^T H^{-1} x
+  TC sp = 0, yp = 0;
+#pragma unroll
+  for (int i = 0; i < JM; ++i) {
+    const int j = grp + G * i;
+    const bool ok = j < nb;
+    const int a = ok ? 2 * j : 0;
+    const TC gd = gamma * dd[a], inv = recip(nul * nul + gd * gd);
+    const TC g1 = gv[a], g2 = gv[a + 1], h1 = hv[a], h2 = hv[a + 1];
+    const TC x1 = xr[i][0], x2 = xr[i][1];
+    const TC s1 = (h1 * (nul * g1 - gd * g2) + h2 * (gd * g1 + nul * g2)) * inv;
+    const TC y1 = (h1 * (nul * x1 - gd * x2) + h2 * (gd * x1 + nul * x2)) * inv;
+    sp += ok ? s1 : (TC)0;
+    yp += ok ? y1 : (TC)0;
+    ir[i] = inv;
+  }
+  red[0][grp][cl] = sp;
+  red[1][grp][cl] = yp;
+  if (grp == 0) {
+    last[0][cl] = xz;
+    last[1][cl] = xn;
+  }
+  __syncthreads();
+  sp = 0;
+  yp = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    sp += red[0][g][cl];
+    yp += red[1][g][cl];
+  }
+  xz = last[0][cl];
+  xn = last[1][cl];
+  const TC rnul = recip(nul);
+  if (nz) {
+    sp += hv[n - 2] * gv[n - 2] * rnul;
+    yp += hv[n - 2] * xz * rnul;
+  }
+  const TC sch = gamma * tl[3 * n] + nul - gamma * gamma * sp;
+  const TC qn = (xn - gamma * yp) * recip(sch);
+  // pass 2: q_B = H^{-1} (x_B - gamma g q_n) from the registers
+  if (!valid) return;
+#pragma unroll
+  for (int i = 0; i < JM; ++i) {
+    const int j = grp + G * i;
+    const bool ok = j < nb;
+    const int a = ok ? 2 * j : 0;
+    const TC gd = gamma * dd[a], inv = ir[i];
+    const TC x1 = xr[i][0] - gamma * gv[a] * qn, x2 = xr[i][1] - gamma * gv[a + 1] * qn;
+    if (ok) {
+      xc[(int64_t)a * ns] = (nul * x1 - gd * x2) * inv;
+      xc[(int64_t)(a + 1) * ns] = (gd * x1 + nul * x2) * inv;
+    }
+  }
+  if (grp == 0) {
+    if (nz) xc[(int64_t)(n - 2) * ns] = (xz - gamma * gv[n - 2] * qn) * rnul;
+    xc[(int64_t)(n - 1) * ns] = qn;
+  }
+}
+
 }  // namespace stig

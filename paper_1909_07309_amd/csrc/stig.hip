@@ -840,14 +840,27 @@ stig_status launch_time_arrow_gen(stig_plan *p, const Tio *in, Tio *out, int nrh
                       : (const TC *)p->aGtab32[transpose ? 1 : 0].p;
   {
     ProfScope ps(p, STIG_K_TIME_SOLVE, (double)cols * p->nt * 3 * sizeof(TC));
-    // lanes per system, measured at 16,900 systems of 131 modes: FP64 17 us
-    // with 8 (21.6 with 4, 19.1 with 16), FP32 12.3 us with 4 (13.2 with 8)
-    constexpr int L = sizeof(TC) == 8 ? 8 : 4;
-    const int64_t waves = (cols + 64 / L - 1) / (64 / L);
-    if (waves * 64 > ((int64_t)1 << 20) * 256) return fail(STIG_EINVAL, "too many time systems");
-    hipLaunchKernelGGL((time_arrow_middle<TC, L>), dim3(grid_for(waves * 64, 256)), dim3(256), 0,
-                       p->stream, mid, tv.lam, tab, (TC)p->gamma, (TC)p->nu, p->nt, p->arrow_nz,
-                       tv.ns, cols);
+    // register form: 8 threads per system in FP64, 4 in FP32, up to 72 / 68
+    // blocks of the middle factor (n_t up to 146 / 138); beyond, the two-pass
+    // form with 8 / 4 lanes per system.  At 16,900 systems of 131 modes: FP64
+    // 12.0 us (two-pass: 17.1), FP32 9.9 us (11.7; 11.8 with 8 threads)
+    constexpr int G = sizeof(TC) == 8 ? 8 : 4, JM = sizeof(TC) == 8 ? 9 : 17;
+    const int nb = (p->nt - 1 - p->arrow_nz) / 2;
+    if (nb <= G * JM) {
+      constexpr int CB = 256 / G;
+      const int64_t blocks = (cols + CB - 1) / CB;
+      if (blocks > ((int64_t)1 << 30)) return fail(STIG_EINVAL, "too many time systems");
+      hipLaunchKernelGGL((time_arrow_middle_reg<TC, G, JM>), dim3((unsigned)blocks), dim3(256), 0,
+                         p->stream, mid, tv.lam, tab, (TC)p->gamma, (TC)p->nu, p->nt,
+                         p->arrow_nz, tv.ns, cols);
+    } else {
+      constexpr int L = G;
+      const int64_t waves = (cols + 64 / L - 1) / (64 / L);
+      if (waves * 64 > ((int64_t)1 << 20) * 256) return fail(STIG_EINVAL, "too many time systems");
+      hipLaunchKernelGGL((time_arrow_middle<TC, L>), dim3(grid_for(waves * 64, 256)), dim3(256), 0,
+                         p->stream, mid, tv.lam, tab, (TC)p->gamma, (TC)p->nu, p->nt,
+                         p->arrow_nz, tv.ns, cols);
+    }
     HIP_TRY(hipGetLastError());
   }
   return launch_mode_gemm<TC, Tio, GM>(p, mid, out, p->aGb[pi].as<E>(), p->nt, tv.ns, cols,

@@ -379,6 +379,37 @@ def test_longest_time_axis():
         assert _relmax(y, ref) <= 1e-13, transpose
 
 
+@pytest.mark.parametrize("nt_el", [135, 144, 148])
+def test_arrowhead_middle_register_and_streaming_forms(nt_el):
+    """The three-pass arrowhead form of step 3 where the middle factor's 2 x 2
+    blocks just fit the register kernel or spill over to the two-pass one:
+    n_t = 137 (68 blocks: the FP32 limit), 146 (72 blocks and the zero mode: the
+    FP64 limit, FP32 streaming), 150 (74: both streaming); d = 1, n_s = 7, two
+    right-hand sides, plain and transposed, against the oracle."""
+    from oracle import bsplines as bs
+    from paper_1909_07309_amd.api import Plan, assemble_1d
+    p, ns_el = 3, 6
+    Kf, Mf = assemble_1d(ns_el, p, "stiffness"), assemble_1d(ns_el, p, "mass")
+    Wf, Mtf = assemble_1d(nt_el, p, "advection"), assemble_1d(nt_el, p, "mass")
+    plan = Plan([ns_el + p - 2], nt_el + p - 1, p, p)
+    plan.setup_1d_pencils([Kf[1:-1, 1:-1].copy()], [Mf[1:-1, 1:-1].copy()],
+                          Wf[1:, 1:].copy(), Mtf[1:, 1:].copy(), 1.0, 1.0)
+    plan.set_option("time_kernel", "arrowhead")
+    Ko, Mo = bs.space_matrices(ns_el, p)
+    Wo, Mto = bs.time_matrices(nt_el, p)
+    P = fd.FDPreconditioner([Ko], [Mo], Wo, Mto)
+    r = wl.random_tensor((2,) + tuple(plan.shape), 23)
+    for transpose in (False, True):
+        ref = np.stack([P.apply(r[b], transpose=transpose) for b in range(2)])
+        s = plan.apply_Pinv(_dev(r), transpose=transpose).cpu().numpy()
+        e64 = _relmax(s, ref)
+        s32 = plan.apply_Pinv(_dev(r), transpose=transpose, prec="fp32").cpu().numpy()
+        e32 = np.linalg.norm(s32 - ref) / np.linalg.norm(ref)
+        print(f"n_t={plan.n_t} transpose={transpose}: fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 <= 1e-11, (transpose, e64)
+        assert e32 <= 1e-5, (transpose, e32)
+
+
 def test_errors_are_reported():
     from paper_1909_07309_amd import StigError
     w, fac, plan, pr = _setup("square_p2_n8", None)
