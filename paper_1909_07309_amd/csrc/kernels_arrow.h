@@ -299,7 +299,8 @@ time_arrow_middle(TC *__restrict__ x, const double *__restrict__ lam, const TC *
 // j = group + G i).  A half-wave (FP64, CB = 32) or a wave (FP32, CB = 64)
 // then reads and writes whole 256-byte runs of a mode row, and a thread keeps
 // its JM >= ceil(nb / G) blocks and their reciprocals in registers between the
-// two passes, so x is read once.  The table goes to LDS first (its loads in
+// two passes, so x is read once (nb >= 1; JM is the smallest of the compiled
+// counts that covers nb, so few iterations run idle).  The table goes to LDS first (its loads in
 // flight with those of x; read from global memory inside the loops, each
 // step's table loads took a round trip of their own).  The group sums are
 // reduced through LDS in a fixed order, and the two modes after the blocks come
@@ -331,12 +332,10 @@ time_arrow_middle_reg(TC *__restrict__ x, const double *__restrict__ lam,
   TC xr[JM][2], ir[JM];
 #pragma unroll
   for (int i = 0; i < JM; ++i) {
-    const int j = grp + G * i;
-    xr[i][0] = xr[i][1] = ir[i] = 0;
-    if (j < nb) {
-      xr[i][0] = xc[(int64_t)(2 * j) * ns];
-      xr[i][1] = xc[(int64_t)(2 * j + 1) * ns];
-    }
+    const int j = grp + G * i, a = j < nb ? 2 * j : 0;  // nb >= 1: rows 0, 1 exist
+    xr[i][0] = xc[(int64_t)a * ns];
+    xr[i][1] = xc[(int64_t)(a + 1) * ns];
+    ir[i] = 0;
   }
   TC xz = 0, xn = 0;
   if (grp == 0) {

@@ -840,16 +840,24 @@ stig_status launch_time_arrow_gen(stig_plan *p, const Tio *in, Tio *out, int nrh
                       : (const TC *)p->aGtab32[transpose ? 1 : 0].p;
   {
     ProfScope ps(p, STIG_K_TIME_SOLVE, (double)cols * p->nt * 3 * sizeof(TC));
-    // register form: 8 threads per system in FP64, 4 in FP32, up to 72 / 68
-    // blocks of the middle factor (n_t up to 146 / 138); beyond, the two-pass
-    // form with 8 / 4 lanes per system.  At 16,900 systems of 131 modes: FP64
-    // 12.0 us (two-pass: 17.1), FP32 9.9 us (11.7; 11.8 with 8 threads)
+    // register form: 8 threads per system in FP64, 4 in FP32, with up to 16 or
+    // up to 72 / 68 blocks of the middle factor (n_t up to 34, up to 146 / 138);
+    // beyond, the two-pass form with 8 / 4 lanes per system.  At 16,900
+    // systems of 131 modes: FP64 12.0 us (two-pass: 17.1), FP32 9.9 us (11.7;
+    // 11.8 with 8 threads); at 32,768 of 33 modes (the short count): 5.6 and
+    // 4.2 us (two-pass: 7.4 and 5.3; the long count there: 8.0 and 5.5)
     constexpr int G = sizeof(TC) == 8 ? 8 : 4, JM = sizeof(TC) == 8 ? 9 : 17;
+    constexpr int JS = 16 / G;
+    constexpr int CB = 256 / G;
     const int nb = (p->nt - 1 - p->arrow_nz) / 2;
-    if (nb <= G * JM) {
-      constexpr int CB = 256 / G;
-      const int64_t blocks = (cols + CB - 1) / CB;
-      if (blocks > ((int64_t)1 << 30)) return fail(STIG_EINVAL, "too many time systems");
+    const int64_t blocks = (cols + CB - 1) / CB;
+    if (nb >= 1 && nb <= G * JM && blocks > ((int64_t)1 << 30))
+      return fail(STIG_EINVAL, "too many time systems");
+    if (nb >= 1 && nb <= G * JS) {
+      hipLaunchKernelGGL((time_arrow_middle_reg<TC, G, JS>), dim3((unsigned)blocks), dim3(256), 0,
+                         p->stream, mid, tv.lam, tab, (TC)p->gamma, (TC)p->nu, p->nt,
+                         p->arrow_nz, tv.ns, cols);
+    } else if (nb >= 1 && nb <= G * JM) {
       hipLaunchKernelGGL((time_arrow_middle_reg<TC, G, JM>), dim3((unsigned)blocks), dim3(256), 0,
                          p->stream, mid, tv.lam, tab, (TC)p->gamma, (TC)p->nu, p->nt,
                          p->arrow_nz, tv.ns, cols);
