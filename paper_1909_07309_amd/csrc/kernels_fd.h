@@ -574,9 +574,91 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       if (lastp && kg == 0 && j < n) out[c.base + (int64_t)j * c.step] = Conv<Tout>::from_f64(fr[q]);
     }
   };
-  for (; strip < nstrips; strip += wstride) {
+  // Tail split (unscaled streaming forms): when the
+  // strips beyond the last full round of waves are no more than the block
+  // groups (at 16,900 columns of 130 / 131, 33 of 1,057 strips with 512 waves
+  // per row part), the waves run only the full rounds, and block group g then
+  // takes tail strip g with its four waves splitting the k steps; the partial
+  // sums meet in LDS (the operator's space, after a barrier) and are added in
+  // wave order.  Otherwise a third round ran a full strip on a few waves.
+  // FP64 operands only: with FP32 operands (shorter MFMA chains) the split
+  // tail measured slower than the partial round.
+  constexpr bool TSPLIT = ROLL && SC == 0 && sizeof(E) == 8;
+  constexpr int NV = QMAX * 4 + (NFR > 0 ? NFR : 0);  // partial sums per lane
+  typedef typename MF::acc_elem AE;
+  const int64_t full = TSPLIT ? nstrips / wstride * wstride : nstrips;
+  const int64_t ntail = nstrips - full;
+  const bool split = TSPLIT && ntail > 0 && ntail <= nsblk &&
+                     (size_t)NROWS * ld * sizeof(E) >= (size_t)4 * NV * 64 * sizeof(AE);
+  const int64_t lim = split ? full : nstrips;
+  auto tail = [&](int64_t tstrip) {
+    const Col tc = column(tstrip);
+    constexpr int KQ = (KSMAX + 3) / 4;  // k steps per wave
+    const int s0 = wave * KQ;
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+      if (s >= s0 && s < s0 + KQ) issue(tc, s);
+    typename MF::acc acc[QMAX];
+#pragma unroll
+    for (int t = 0; t < QMAX; ++t)
+      for (int v = 0; v < 4; ++v) acc[t][v] = 0;
+    double fr[NFR > 0 ? NFR : 1] = {};
+    const E *abase = opl + (size_t)col * ld + kg * MF::KPL;
+    const E *fbase = opl + (size_t)16 * QMAX * ld + kg * MF::KPL;
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      if (s < s0 || s >= s0 + KQ) continue;
+      E be[MF::KPL];
+      operand(s, be);
+      typename MF::frag b = MF::make(be);
+#pragma unroll
+      for (int t = 0; t < QMAX; ++t)
+        acc[t] = MF::mma(MF::load(abase + (size_t)16 * t * ld + s * MF::KSTEP), b, acc[t]);
+#pragma unroll
+      for (int q = 0; q < NFR; ++q)
+#pragma unroll
+        for (int u = 0; u < MF::KPL; ++u)
+          fr[q] += MF::to_f64(fbase[(size_t)q * ld + s * MF::KSTEP + u]) * MF::to_f64(be[u]);
+    }
+#pragma unroll
+    for (int q = 0; q < NFR; ++q) {
+      fr[q] += __shfl_xor(fr[q], 16, 64);
+      fr[q] += __shfl_xor(fr[q], 32, 64);
+    }
+    __syncthreads();  // every wave is done with Op: its space takes the partial sums
+    AE *red = reinterpret_cast<AE *>(smem);  // [wave][NV][64]
+#pragma unroll
+    for (int t = 0; t < QMAX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[((size_t)wave * NV + 4 * t + v) * 64 + lane] = acc[t][v];
+#pragma unroll
+    for (int q = 0; q < NFR; ++q) red[((size_t)wave * NV + 4 * QMAX + q) * 64 + lane] = (AE)fr[q];
+    __syncthreads();
+    if (wave != 0 || !tc.valid) return;
+    auto total = [&](int i) {
+      AE v = red[(size_t)i * 64 + lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) v += red[((size_t)w * NV + i) * 64 + lane];
+      return (double)v;
+    };
+#pragma unroll
+    for (int t = 0; t < QMAX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = row0 + 16 * t + MF::out_row(kg, v);
+        const double y = total(4 * t + v);
+        if (j < n) out[tc.base + (int64_t)j * tc.step] = Conv<Tout>::from_f64(y);
+      }
+#pragma unroll
+    for (int q = 0; q < NFR; ++q) {
+      const int j = 16 * QALL + q;
+      const double y = total(4 * QMAX + q);
+      if (lastp && kg == 0 && j < n) out[tc.base + (int64_t)j * tc.step] = Conv<Tout>::from_f64(y);
+    }
+  };
+  for (; strip < lim; strip += wstride) {
     if constexpr (ROLL) {
-      const Col nx = column(strip + wstride);
+      const Col nx = column(strip + wstride < lim ? strip + wstride : nstrips);
       process(cur, nx);
       cur = nx;
     } else {
@@ -586,6 +668,9 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       prepare();
       process(cur, cur);
     }
+  }
+  if constexpr (TSPLIT) {
+    if (split && sblk < ntail) tail(full + sblk);  // the same for a whole block
   }
 }
 
