@@ -576,8 +576,9 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   };
   // Tail split (unscaled streaming forms): when the
   // strips beyond the last full round of waves are no more than the block
-  // groups (at 16,900 columns of 130 / 131, 33 of 1,057 strips with 512 waves
-  // per row part), the waves run only the full rounds, and block group g then
+  // groups (on the 128-element annulus, 33 of 1,057 strips along t and 41 of
+  // 1,065 along x, with 512 waves per row part), the waves run only the full
+  // rounds, and block group g then
   // takes tail strip g with its four waves splitting the k steps; the partial
   // sums meet in LDS (the operator's space, after a barrier) and are added in
   // wave order.  Otherwise a third round ran a full strip on a few waves.
