@@ -574,7 +574,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       if (lastp && kg == 0 && j < n) out[c.base + (int64_t)j * c.step] = Conv<Tout>::from_f64(fr[q]);
     }
   };
-  // Tail split (unscaled streaming forms): when the
+  // Tail split (streaming forms without input scaling): when the
   // strips beyond the last full round of waves are no more than the block
   // groups (on the 128-element annulus, 33 of 1,057 strips along t and 41 of
   // 1,065 along x, with 512 waves per row part), the waves run only the full
@@ -584,7 +584,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
   // wave order.  Otherwise a third round ran a full strip on a few waves.
   // FP64 operands only: with FP32 operands (shorter MFMA chains) the split
   // tail measured slower than the partial round.
-  constexpr bool TSPLIT = ROLL && SC == 0 && sizeof(E) == 8;
+  constexpr bool TSPLIT = ROLL && SC != 1 && sizeof(E) == 8;
   constexpr int NV = QMAX * 4 + (NFR > 0 ? NFR : 0);  // partial sums per lane
   typedef typename MF::acc_elem AE;
   const int64_t full = TSPLIT ? nstrips / wstride * wstride : nstrips;
@@ -647,13 +647,15 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = row0 + 16 * t + MF::out_row(kg, v);
-        const double y = total(4 * t + v);
+        double y = total(4 * t + v);
+        if constexpr (SC == 2) y *= out_scale[tc.sb + (j < n ? (int64_t)j * tc.step : 0)];
         if (j < n) out[tc.base + (int64_t)j * tc.step] = Conv<Tout>::from_f64(y);
       }
 #pragma unroll
     for (int q = 0; q < NFR; ++q) {
       const int j = 16 * QALL + q;
-      const double y = total(4 * QMAX + q);
+      double y = total(4 * QMAX + q);
+      if constexpr (SC == 2) y *= out_scale[tc.sb + (j < n ? (int64_t)j * tc.step : 0)];
       if (lastp && kg == 0 && j < n) out[tc.base + (int64_t)j * tc.step] = Conv<Tout>::from_f64(y);
     }
   };
