@@ -574,27 +574,27 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       if (lastp && kg == 0 && j < n) out[c.base + (int64_t)j * c.step] = Conv<Tout>::from_f64(fr[q]);
     }
   };
-  // Tail split (streaming forms without input scaling): when the
-  // strips beyond the last full round of waves are no more than the block
-  // groups (on the 128-element annulus, 33 of 1,057 strips along t and 41 of
-  // 1,065 along x, with 512 waves per row part), the waves run only the full
-  // rounds, and block group g then
-  // takes tail strip g with its four waves splitting the k steps; the partial
-  // sums meet in LDS (the operator's space, after a barrier) and are added in
-  // wave order.  Otherwise a third round ran a full strip on a few waves.
-  // FP64 operands only: with FP32 operands (shorter MFMA chains) the split
-  // tail measured slower than the partial round.
+  // Tail split (streaming forms without input scaling): when the strips
+  // beyond the last full round of waves are no more than the block groups (on
+  // the 128-element annulus, 33 of 1,057 strips along t and 41 of 1,065 along
+  // x, with 512 waves per row part), the waves run only the full rounds, and
+  // block group g then takes tail strip g with the NW waves of each block
+  // splitting the k steps; the partial sums meet in LDS (the operator's space,
+  // after a barrier) and are added in wave order.  Otherwise a third round ran
+  // a full strip on a few waves.  FP64 operands only: with FP32 operands
+  // (shorter MFMA chains) the split tail measured slower than that round.
   constexpr bool TSPLIT = ROLL && SC != 1 && sizeof(E) == 8;
+  constexpr int NW = GEMM2_THREADS / 64;                // waves per block
   constexpr int NV = QMAX * 4 + (NFR > 0 ? NFR : 0);  // partial sums per lane
   typedef typename MF::acc_elem AE;
   const int64_t full = TSPLIT ? nstrips / wstride * wstride : nstrips;
   const int64_t ntail = nstrips - full;
   const bool split = TSPLIT && ntail > 0 && ntail <= nsblk &&
-                     (size_t)NROWS * ld * sizeof(E) >= (size_t)4 * NV * 64 * sizeof(AE);
+                     (size_t)NROWS * ld * sizeof(E) >= (size_t)NW * NV * 64 * sizeof(AE);
   const int64_t lim = split ? full : nstrips;
   auto tail = [&](int64_t tstrip) {
     const Col tc = column(tstrip);
-    constexpr int KQ = (KSMAX + 3) / 4;  // k steps per wave
+    constexpr int KQ = (KSMAX + NW - 1) / NW;  // k steps per wave
     const int s0 = wave * KQ;
 #pragma unroll
     for (int s = 0; s < KSMAX; ++s)
@@ -627,7 +627,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
       fr[q] += __shfl_xor(fr[q], 32, 64);
     }
     __syncthreads();  // every wave is done with Op: its space takes the partial sums
-    AE *red = reinterpret_cast<AE *>(smem);  // [wave][NV][64]
+    AE *red = reinterpret_cast<AE *>(smem);  // [NW][NV][64]
 #pragma unroll
     for (int t = 0; t < QMAX; ++t)
 #pragma unroll
@@ -639,7 +639,7 @@ mode_gemm_small(const Tin *__restrict__ in, Tout *__restrict__ out,
     auto total = [&](int i) {
       AE v = red[(size_t)i * 64 + lane];
 #pragma unroll
-      for (int w = 1; w < 4; ++w) v += red[((size_t)w * NV + i) * 64 + lane];
+      for (int w = 1; w < NW; ++w) v += red[((size_t)w * NV + i) * 64 + lane];
       return (double)v;
     };
 #pragma unroll
