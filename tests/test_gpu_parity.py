@@ -410,6 +410,39 @@ def test_arrowhead_middle_register_and_streaming_forms(nt_el):
         assert e32 <= 1e-5, (transpose, e32)
 
 
+@pytest.mark.parametrize("nrhs", [2, 2416])
+def test_split_tail_strips_of_the_streaming_products(nrhs):
+    """n_t = 131 in the arrowhead form (two n = 131 products along t), d = 1,
+    n_s = 7: with 2 right-hand sides the 14 columns are one ragged strip, taken
+    by one block group with its waves splitting the k steps; with 2,416 the
+    16,912 columns are 1,057 strips, and the ones past the last full round of
+    waves go the same way (the FP64 split; FP32 runs them as a partial round).
+    Plain and transposed, against the oracle on the first right-hand sides and
+    on all those from column 16,352 (strip 1,022) on."""
+    from oracle import bsplines as bs
+    from paper_1909_07309_amd.api import Plan, assemble_1d
+    p, ns_el, nt_el = 3, 6, 129
+    Kf, Mf = assemble_1d(ns_el, p, "stiffness"), assemble_1d(ns_el, p, "mass")
+    Wf, Mtf = assemble_1d(nt_el, p, "advection"), assemble_1d(nt_el, p, "mass")
+    plan = Plan([ns_el + p - 2], nt_el + p - 1, p, p)
+    assert plan.n_t == 131
+    plan.setup_1d_pencils([Kf[1:-1, 1:-1].copy()], [Mf[1:-1, 1:-1].copy()],
+                          Wf[1:, 1:].copy(), Mtf[1:, 1:].copy(), 1.0, 1.0)
+    plan.set_option("time_kernel", "arrowhead")
+    Ko, Mo = bs.space_matrices(ns_el, p)
+    Wo, Mto = bs.time_matrices(nt_el, p)
+    P = fd.FDPreconditioner([Ko], [Mo], Wo, Mto)
+    r = wl.random_tensor((nrhs,) + tuple(plan.shape), 29)
+    rd = _dev(r)
+    pick = list(range(min(nrhs, 8))) + list(range(max(8, nrhs - 80), nrhs))
+    for transpose in (False, True):
+        ref = np.stack([P.apply(r[b], transpose=transpose) for b in pick])
+        s = plan.apply_Pinv(rd, transpose=transpose).cpu().numpy()[pick]
+        assert _relmax(s, ref) <= 1e-11, (nrhs, transpose)
+        s32 = plan.apply_Pinv(rd, transpose=transpose, prec="fp32").cpu().numpy()[pick]
+        assert np.linalg.norm(s32 - ref) / np.linalg.norm(ref) <= 1e-5, (nrhs, transpose)
+
+
 def test_errors_are_reported():
     from paper_1909_07309_amd import StigError
     w, fac, plan, pr = _setup("square_p2_n8", None)
